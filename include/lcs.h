@@ -1,0 +1,278 @@
+/*
+ * lcs.h -- C ABI of an MI355X (gfx950) engine for the longest common
+ * subsequence of two strings, following the grid-graph method of
+ * "Parallel Longest Common SubSequence Analysis In Chapel" (arXiv 2309.09072),
+ * itself a variant of Lu and Lin's first parallel algorithm.
+ *
+ * Problem (Section I): two strings over a finite alphabet in; the length of a
+ * longest common subsequence and one such subsequence (a "witness") out.
+ *
+ * Method (Section II): the LCS is the heaviest path from the top-left to the
+ * bottom-right vertex of the grid graph whose diagonal edges (weight 1) sit
+ * where the symbols match (Section II-A, Fig. 1).  For a horizontal strip of
+ * rows, the breakout matrix D(i, j) holds the leftmost bottom-row column that a
+ * path of weight j can reach from top-row column i (Section II-B-1).  Strips of
+ * base_rows rows are built from per-symbol next-match tables (the base case of
+ * Section II-B-3), adjacent strips are merged with the combine equation of
+ * Section II-B-1 up to the whole grid, the length is read off the top matrix,
+ * and the witness comes from the cross vertices found by a recursive midpoint
+ * search (Sections II-C to II-E).
+ *
+ * Conventions shared by every call:
+ *   - a is the ROW string (length m), b the COLUMN string (length n).  Symbols
+ *     are uint8 codes 0..alphabet-1.  Swapping a and b leaves the length
+ *     unchanged but may change the witness.
+ *   - Columns and breakouts are 0-indexed vertex columns 0..n.  "Unreachable"
+ *     (the paper's infinity) is stored as n + 1.
+ *   - The caller owns every device buffer (inputs, outputs, workspace); the
+ *     library never allocates or frees device memory.  Workspaces are plain
+ *     device allocations of the size the planning call reports.
+ *   - Device work is enqueued on the caller's HIP stream (a hipStream_t passed
+ *     as void*, NULL = the null stream) and is asynchronous unless stated.
+ *     Device outputs are valid once that stream has been synchronised.
+ *   - Every call returns an int32 status: LCS_OK or a negative LCS_E_* code.
+ *     No C++ exception or abort crosses this interface.
+ *   - A plan, batch or server handle is not thread-safe; distinct handles are
+ *     independent.
+ */
+#ifndef LCS_H_
+#define LCS_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ status */
+#define LCS_OK 0
+#define LCS_E_INVAL (-1)     /* bad argument: null pointer, size or alphabet out of range */
+#define LCS_E_TOO_BIG (-2)   /* sizes exceed the plan, or an index would not fit in int32 */
+#define LCS_E_WORKSPACE (-3) /* workspace smaller than required */
+#define LCS_E_HIP (-4)       /* a HIP runtime call or kernel launch failed */
+#define LCS_E_SYMBOL (-5)    /* a symbol >= alphabet was found on the device */
+#define LCS_E_CAPACITY (-6)  /* witness output buffer too small */
+#define LCS_E_STATE (-7)     /* call out of order (e.g. length before any build) */
+#define LCS_E_NOMEM (-8)     /* host memory allocation failed */
+#define LCS_E_BUDGET (-9)    /* serving: request does not fit the memory budget */
+#define LCS_E_AGAIN (-10)    /* serving: queue full, try again after polling */
+
+/* Human-readable name of a status code (static storage, never NULL). */
+const char *lcs_status_string(int32_t status);
+
+/* ============================================================ single pair */
+
+typedef struct lcs_plan_s *lcs_plan_t;
+
+typedef struct lcs_plan_desc {
+    int32_t max_m;     /* largest row-string length the plan accepts, >= 0 */
+    int32_t max_n;     /* largest column-string length, >= 0 */
+    int32_t alphabet;  /* number of symbol codes, 1..256 */
+    int32_t base_rows; /* rows per base strip (Section II-B-3 generalised to
+                          base_rows rows): 16, 32 or 64; 0 selects 64 */
+    int32_t tile;      /* vertices per search tile of the combine: power of two
+                          in 4..128; 0 selects the tuned default */
+    uint32_t flags;    /* reserved, must be 0 */
+} lcs_plan_desc;
+
+/*
+ * Plan the breakout-matrix recursion for strings up to max_m x max_n.
+ * On success *out receives a new plan (host memory only) and *workspace_bytes
+ * the exact device workspace size needed by lcs_dist_build for the largest
+ * sizes: every level of the strip recursion (all kept for the trace), a
+ * sentinel row per matrix, the next-match tables and search/trace scratch.
+ * Errors: LCS_E_INVAL (null pointer, negative size, alphabet outside 1..256,
+ * unsupported base_rows or tile), LCS_E_TOO_BIG (a matrix would have 2^31 or
+ * more cells), LCS_E_NOMEM.
+ */
+int32_t lcs_plan(const lcs_plan_desc *desc, lcs_plan_t *out, size_t *workspace_bytes);
+
+/* Workspace size for one pair of exact sizes (m, n) <= the plan's maxima. */
+int32_t lcs_plan_workspace(lcs_plan_t plan, int32_t m, int32_t n, size_t *workspace_bytes);
+
+/* Release a plan (host memory only; the workspace stays the caller's). */
+int32_t lcs_plan_destroy(lcs_plan_t plan);
+
+/*
+ * Build every breakout matrix of the strip recursion for the pair (a, b):
+ * the per-symbol next-match tables (Section II-B-3 base case), the base strips
+ * of base_rows rows, then the combine equation of Section II-B-1 level by
+ * level up to the whole grid, whose argmin search follows the monotone-matrix
+ * property of Section II-B-1 (Alg. 1 and Alg. 2 for every tile-th vertex,
+ * bracketed searches in between), and finally the LCS length.
+ *   a, b       device pointers to m and n symbol codes (may be NULL when the
+ *              length is 0).
+ *   workspace  device pointer, at least lcs_plan_workspace(plan, m, n) bytes,
+ *              256-byte aligned.  It must stay allocated and untouched while
+ *              lcs_length / lcs_trace / lcs_dist_view use this build.
+ * m = 0 or n = 0 is legal: no device work, length 0.
+ * Errors: LCS_E_INVAL, LCS_E_TOO_BIG (m or n above the plan's maxima),
+ * LCS_E_WORKSPACE, LCS_E_HIP.  A symbol >= alphabet is only detected on the
+ * device and reported as LCS_E_SYMBOL by the next lcs_length or lcs_trace.
+ */
+int32_t lcs_dist_build(lcs_plan_t plan, const uint8_t *a, int32_t m, const uint8_t *b, int32_t n,
+                       void *workspace, size_t workspace_bytes, void *stream);
+
+/*
+ * LCS length of the last build: the largest weight j whose breakout from top
+ * vertex 0 of the whole grid is reachable (Sections II-B-1 and II-C).
+ * Copies it to *length_host and SYNCHRONISES the stream.
+ * Errors: LCS_E_STATE (no build), LCS_E_SYMBOL, LCS_E_HIP.
+ */
+int32_t lcs_length(lcs_plan_t plan, int32_t *length_host, void *stream);
+
+/* Same value written to device memory *length_dev, asynchronously (graph-safe). */
+int32_t lcs_length_device(lcs_plan_t plan, int32_t *length_dev, void *stream);
+
+/*
+ * One witness of the last build via the recursive midpoint-vertex search
+ * (Section II-D): at every split of a strip into upper and lower halves the
+ * cross vertex on the boundary row is taken with the smallest upper weight
+ * (the tie rule of Alg. 2), which yields the optimal path entering every row
+ * as far left as possible; inside a base strip the same rule is applied row by
+ * row.  The diagonal (weight 1) edges of that path are the matched pairs
+ * (Section II-E): a_idx[t], b_idx[t] (device int32 arrays) receive them in
+ * increasing order, t = 0..L-1, with a[a_idx[t]] == b[b_idx[t]].
+ * capacity must be >= min(m, n).  *length_host receives L (the stream is
+ * SYNCHRONISED).
+ * Errors: LCS_E_STATE, LCS_E_CAPACITY, LCS_E_INVAL, LCS_E_SYMBOL, LCS_E_HIP.
+ */
+int32_t lcs_trace(lcs_plan_t plan, int32_t *a_idx, int32_t *b_idx, int32_t capacity,
+                  int32_t *length_host, void *stream);
+
+/*
+ * Inspection of the last build (for tests and debugging).
+ * lcs_plan_levels: number of levels (level 0 = base strips, the last level is
+ * the whole grid) and, if strips_per_level is not NULL, the strip count of
+ * each level (the array must hold *levels entries; pass NULL first to size it).
+ * lcs_dist_view: device pointer to the breakout matrix of strip `strip` at
+ * level `level`, row-major with (*rows) = n + 2 rows (vertices 0..n and one
+ * all-unreachable sentinel row) and (*cols) = h + 1 columns (weights 0..h);
+ * *row0 is the first grid row of the strip (rows row0 .. row0 + h - 1 of a).
+ */
+int32_t lcs_plan_levels(lcs_plan_t plan, int32_t *levels, int32_t *strips_per_level);
+int32_t lcs_dist_view(lcs_plan_t plan, int32_t level, int32_t strip, const int32_t **matrix,
+                      int32_t *rows, int32_t *cols, int32_t *row0);
+
+/* ============================================================== batches */
+
+typedef struct lcs_batch_s *lcs_batch_t;
+
+/* One pair of a batch: offsets (in symbols) into the shared symbol buffer. */
+typedef struct lcs_pair_desc {
+    int64_t a_off;
+    int64_t b_off;
+    int32_t m;
+    int32_t n;
+} lcs_pair_desc;
+
+#define LCS_BATCH_PERSISTENT 0u /* one persistent launch drains a device work queue */
+#define LCS_BATCH_PER_PAIR 1u   /* same kernels, launched pair after pair */
+#define LCS_BATCH_GRAPH 2u      /* OR-able: replay the launch as a captured hipGraph */
+
+typedef struct lcs_batch_desc {
+    int32_t max_pairs; /* most pairs per submit */
+    int32_t max_len;   /* largest m and largest n of any pair */
+    int32_t alphabet;  /* 1..256 */
+    int32_t base_rows; /* as in lcs_plan_desc */
+    int32_t tile;      /* as in lcs_plan_desc */
+    int32_t slots;     /* pairs whose matrices may be resident at once (0 = all);
+                          pair p reuses slot p mod slots after pair p - slots
+                          has been traced */
+    uint32_t flags;    /* reserved, must be 0 */
+} lcs_batch_desc;
+
+/*
+ * Plan a batch.  *workspace_bytes receives the device workspace needed by
+ * lcs_batch_submit: `slots` pair-sized regions for the largest allowed pair
+ * plus the task queue and its dependency counters.
+ */
+int32_t lcs_batch_plan(const lcs_batch_desc *desc, lcs_batch_t *out, size_t *workspace_bytes);
+int32_t lcs_batch_destroy(lcs_batch_t batch);
+
+/*
+ * Length and witness of every pair (Sections II-B to II-E, per pair).
+ *   pairs      HOST array of `count` descriptors; m, n in 0..max_len.
+ *   symbols    device buffer holding all strings (symbols_len bytes).
+ *   lengths    device int32[count] <- LCS lengths.
+ *   a_idx/b_idx device int32 arrays <- witnesses; pair p's L pairs start at
+ *              wit_off[p] = sum over q < p of min(m_q, n_q); witness_capacity
+ *              must be >= that sum over all pairs.  May be NULL (lengths only)
+ *              when witness_capacity is 0.
+ *   mode       LCS_BATCH_PERSISTENT or LCS_BATCH_PER_PAIR, optionally OR
+ *              LCS_BATCH_GRAPH.
+ * Asynchronous on `stream`.  Errors: LCS_E_INVAL, LCS_E_TOO_BIG,
+ * LCS_E_WORKSPACE, LCS_E_CAPACITY, LCS_E_NOMEM, LCS_E_HIP.  A bad symbol sets
+ * the length of its pair to LCS_E_SYMBOL.
+ */
+int32_t lcs_batch_submit(lcs_batch_t batch, const lcs_pair_desc *pairs, int32_t count,
+                         const uint8_t *symbols, int64_t symbols_len, int32_t *lengths,
+                         int32_t *a_idx, int32_t *b_idx, int64_t witness_capacity,
+                         void *workspace, size_t workspace_bytes, uint32_t mode, void *stream);
+
+/* ============================================================== serving */
+
+typedef struct lcs_server_s *lcs_server_t;
+
+typedef struct lcs_server_desc {
+    int32_t max_len;      /* largest m and n of a request */
+    int32_t alphabet;     /* largest alphabet of a request, 1..256 */
+    int32_t base_rows;    /* as in lcs_plan_desc */
+    int32_t tile;         /* as in lcs_plan_desc */
+    int32_t slots;        /* requests that may run on the device at once */
+    int32_t max_queue;    /* waiting requests held on the host */
+    uint32_t flags;       /* reserved, must be 0 */
+} lcs_server_desc;
+
+typedef struct lcs_result {
+    int64_t tag;          /* caller's tag from lcs_server_submit */
+    int32_t status;       /* LCS_OK or an error code */
+    int32_t length;       /* LCS length */
+    int64_t wit_off;      /* where the witness was written in the caller's arrays */
+    double t_submit;      /* host clock (s) at submit, admission and completion */
+    double t_admit;
+    double t_done;
+} lcs_result;
+
+/*
+ * Open a continuous-batching server over a caller-owned device arena of
+ * arena_bytes (the memory budget for breakout matrices).  Requests wait on the
+ * host until both a slot and enough arena memory are free; each admitted
+ * request runs on its slot's stream, so requests overlap on the device.
+ * Witnesses go to the caller's device arrays a_idx/b_idx (capacity entries).
+ */
+int32_t lcs_server_open(const lcs_server_desc *desc, void *arena, size_t arena_bytes,
+                        int32_t *a_idx, int32_t *b_idx, int64_t capacity, lcs_server_t *out);
+
+/* Device bytes a request of sizes (m, n) occupies while it runs. */
+int32_t lcs_server_footprint(lcs_server_t server, int32_t m, int32_t n, size_t *bytes);
+
+/*
+ * Queue one request; a and b are HOST strings (copied at submit).  Returns
+ * LCS_E_BUDGET if the request can never fit the arena, LCS_E_AGAIN if the
+ * host queue is full.
+ */
+int32_t lcs_server_submit(lcs_server_t server, int64_t tag, const uint8_t *a, int32_t m,
+                          const uint8_t *b, int32_t n, int32_t alphabet);
+
+/*
+ * Make progress: collect finished requests, then admit waiting ones in
+ * arrival order while a slot and arena memory are free.  Up to max_results
+ * finished requests are written to results; *count receives how many.
+ * Never blocks on the device.
+ */
+int32_t lcs_server_poll(lcs_server_t server, lcs_result *results, int32_t max_results,
+                        int32_t *count);
+
+/* Requests admitted and not yet collected, and requests still waiting. */
+int32_t lcs_server_pending(lcs_server_t server, int32_t *running, int32_t *waiting);
+
+/* Wait for every running request, then release the server (not the arena). */
+int32_t lcs_server_close(lcs_server_t server);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LCS_H_ */

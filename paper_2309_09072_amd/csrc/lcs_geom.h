@@ -1,0 +1,89 @@
+// Geometry of the strip recursion, shared by the host planner and the kernels.
+//
+// The grid of a (m rows) x b (n columns) is cut into base strips of h0 rows
+// (the last one may be shorter).  Level 0 holds the base strips; strip s of
+// level l+1 is the combine of strips 2s and 2s+1 of level l, or -- when level l
+// has an odd number of strips -- its last strip carried up unchanged (the
+// same matrix, no copy).  The top level has one strip: the whole grid.
+//
+// Every strip of h rows owns one breakout matrix D (Section II-B-1) stored
+// row-major as (n + 2) x (h + 1) int32: row i = top vertex i (0..n), column
+// j = path weight, and a last all-unreachable sentinel row n + 1 so that a
+// lookup D(x, .) with x = n + 1 ("unreachable") needs no branch.  Only the last
+// strip of a level can be shorter than the others, so strip q of a level sits
+// at base + q * (n + 2) * (hfull + 1) unless it is the last one.
+#pragma once
+#include <stddef.h>
+#include <stdint.h>
+
+namespace lcs {
+
+// error bits of the workspace header word 0
+constexpr int32_t kErrSymbol = 1;  // a symbol >= alphabet was read
+constexpr int32_t kErrTrace = 2;   // the trace found no split reproducing a breakout
+
+struct LevelGeom {
+    int32_t nstrips;     // strips at this level
+    int32_t hfull;       // rows of every strip except possibly the last
+    int32_t hlast;       // rows of the last strip
+    int32_t npairs;      // combines producing this level (0 at level 0)
+    int32_t last_alias;  // 1: last strip is the lower level's last strip
+    int64_t base;        // byte offset of strip 0 inside the workspace
+    int64_t last_off;    // byte offset of the last strip's matrix
+    int64_t bytes;       // bytes owned by this level (aliased strip excluded)
+};
+
+// Arguments of one combine level, passed by value to the kernels.
+struct CombineArgs {
+    const int32_t *cbase;  // child level: strip 0
+    const int32_t *clast;  // child level: last strip
+    int32_t hc;            // child full strip rows
+    int32_t hclast;        // child last strip rows
+    int32_t nc;            // child strip count
+    int32_t *pbase;        // parent level: strip 0
+    int32_t *plast;        // parent level: last strip
+    int32_t np;            // parent strip count
+    int32_t n;             // columns of the grid
+    int32_t tile;          // vertices per search tile (anchors every `tile` vertices)
+    int32_t nanch;         // anchors per pair = ceil(n / tile) + 1
+    int32_t hs;            // anchor scratch row stride = 2 * hc + 1
+    int32_t *anch;         // anchor argmins [pair][anchor][hs]
+    int32_t jchunk;        // weights per bracket block
+    int32_t nchunks;       // bracket blocks along the weights of the widest pair
+};
+
+struct StripRef {
+    const int32_t *d;
+    int32_t h;
+};
+
+#if defined(__HIPCC__) || defined(__HIP_DEVICE_COMPILE__)
+#define LCS_HD __host__ __device__ __forceinline__
+#else
+#define LCS_HD inline
+#endif
+
+LCS_HD size_t strip_elems(int32_t n, int32_t h) { return (size_t)(n + 2) * (size_t)(h + 1); }
+
+LCS_HD StripRef child_strip(const CombineArgs &c, int32_t q) {
+    StripRef r;
+    if (q < c.nc - 1) {
+        r.d = c.cbase + (size_t)q * strip_elems(c.n, c.hc);
+        r.h = c.hc;
+    } else {
+        r.d = c.clast;
+        r.h = c.hclast;
+    }
+    return r;
+}
+
+LCS_HD int32_t *parent_strip(const CombineArgs &c, int32_t p) {
+    return (p < c.np - 1) ? c.pbase + (size_t)p * strip_elems(c.n, 2 * c.hc) : c.plast;
+}
+
+LCS_HD int32_t anchor_vertex(int32_t a, int32_t tile, int32_t n) {
+    int64_t v = (int64_t)a * tile;
+    return v < n ? (int32_t)v : n;
+}
+
+}  // namespace lcs

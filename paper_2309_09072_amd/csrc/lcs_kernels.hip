@@ -1,0 +1,189 @@
+// Per-level kernels of the single-pair path: every launch covers one step of
+// the strip recursion for all strips of a level.  The work-group bodies are in
+// lcs_device.h and are shared with the persistent batch kernel.
+#include "lcs_device.h"
+#include "lcs_launch.h"
+
+namespace lcs {
+
+__global__ void __launch_bounds__(kBlock) k_clear(int32_t *words, int32_t count) {
+    for (int32_t i = blockIdx.x * kBlock + threadIdx.x; i < count; i += gridDim.x * kBlock) words[i] = 0;
+}
+
+__global__ void __launch_bounds__(kBlock) k_nextmatch(const uint8_t *b, int32_t n, int32_t *nm) {
+    __shared__ int32_t lds[kWaves];
+    const int32_t x = blockIdx.x;
+    nextmatch_block(b, n, x, nm + (size_t)x * (size_t)(n + 2), lds);
+}
+
+template <int H0>
+__global__ void __launch_bounds__(kBlock) k_base(const uint8_t *a, int32_t n, int32_t sigma,
+                                                 const int32_t *nm, int32_t *base0, int32_t *last,
+                                                 int32_t nstrips, int32_t hlast, int32_t *err) {
+    __shared__ int32_t lds[kWaves * kWave * (H0 + 1)];
+    const int32_t s = blockIdx.y;
+    const bool is_last = (s == nstrips - 1);
+    const int32_t h = is_last ? hlast : H0;
+    int32_t *out = is_last ? last : base0 + (size_t)s * strip_elems(n, H0);
+    base_strip_block<H0>(a + (size_t)s * H0, h, n, sigma, nm, out, (int32_t)blockIdx.x * kBlock, err,
+                         lds);
+}
+
+__global__ void __launch_bounds__(kBlock) k_anchor(CombineArgs c) {
+    __shared__ unsigned long long lds[kBlock];
+    const int32_t p = blockIdx.y, a = blockIdx.x;
+    const StripRef U = child_strip(c, 2 * p), L = child_strip(c, 2 * p + 1);
+    int32_t *G = parent_strip(c, p);
+    const int32_t vtx = anchor_vertex(a, c.tile, c.n);
+    int32_t *Krow = c.anch + ((size_t)p * c.nanch + a) * (size_t)c.hs;
+    anchor_block(U.d, U.h, L.d, L.h, G, c.n, vtx, Krow, lds);
+    if (a == c.nanch - 1) {  // sentinel row n + 1
+        const int32_t H = U.h + L.h + 1;
+        int32_t *srow = G + (size_t)(c.n + 1) * H;
+        for (int32_t j = threadIdx.x; j < H; j += kBlock) srow[j] = c.n + 1;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_bracket(CombineArgs c) {
+    __shared__ BracketSmem sm;
+    const int32_t p = blockIdx.y;
+    const int32_t tile = blockIdx.x / c.nchunks, chunk = blockIdx.x - tile * c.nchunks;
+    const StripRef U = child_strip(c, 2 * p), L = child_strip(c, 2 * p + 1);
+    const int32_t H = U.h + L.h + 1;
+    const int32_t nch = imax(1, (H - 1 + c.jchunk - 1) / c.jchunk);
+    if (chunk >= nch) return;
+    const int32_t j0 = chunk * c.jchunk;
+    const int32_t jn = (chunk == nch - 1) ? H - j0 : c.jchunk;
+    const int32_t i0 = tile * c.tile;
+    const int32_t len = imin(c.tile, c.n - i0);
+    int32_t *G = parent_strip(c, p);
+    const int32_t *Ka = c.anch + ((size_t)p * c.nanch + tile) * (size_t)c.hs;
+    const int32_t *Kb = c.anch + ((size_t)p * c.nanch + tile + 1) * (size_t)c.hs;
+    bracket_block(U.d, U.h, L.d, L.h, G, c.n, i0, len, j0, jn, Ka, Kb, sm);
+}
+
+__global__ void __launch_bounds__(kBlock) k_length(const int32_t *top, int32_t m, int32_t n,
+                                                   int32_t *hdr, int4 *root) {
+    __shared__ int32_t lds[1];
+    length_block(top, m, n, hdr, root, lds);
+}
+
+__global__ void __launch_bounds__(kBlock) k_trace_split(CombineArgs c, const int4 *nodes_in,
+                                                        int4 *nodes_out, int32_t *err) {
+    __shared__ int32_t lds[1];
+    const int32_t p = blockIdx.x;
+    const int4 node = nodes_in[p];
+    if (2 * p + 1 >= c.nc) {  // carried-up strip: same node one level down
+        if (threadIdx.x == 0) nodes_out[2 * p] = node;
+        return;
+    }
+    const StripRef U = child_strip(c, 2 * p), L = child_strip(c, 2 * p + 1);
+    trace_split_block(U.d, U.h, L.d, L.h, c.n, node, nodes_out + 2 * p, nodes_out + 2 * p + 1, err,
+                      lds);
+}
+
+template <int H0>
+__global__ void __launch_bounds__(kBlock) k_trace_leaf(const uint8_t *a, int32_t n, int32_t sigma,
+                                                       const int32_t *nm, int32_t nstrips,
+                                                       int32_t hlast, const int4 *nodes,
+                                                       int32_t *a_idx, int32_t *b_idx,
+                                                       int32_t *err) {
+    __shared__ int32_t lds[(H0 + 1) * (H0 + 1)];
+    const int32_t s = blockIdx.x;
+    const int32_t h = (s == nstrips - 1) ? hlast : H0;
+    trace_leaf_block<H0>(a + (size_t)s * H0, h, n, sigma, nm, nodes[s], s * H0, a_idx, b_idx, err,
+                         lds);
+}
+
+__global__ void k_copy_len(const int32_t *hdr, int32_t *dst) {
+    if (threadIdx.x == 0) *dst = hdr[1];
+}
+
+// ------------------------------------------------------------------ launchers
+
+hipError_t launch_clear(int32_t *words, int32_t count, hipStream_t s) {
+    const int32_t blocks = imin(1024, (count + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(k_clear, dim3(imax(blocks, 1)), dim3(kBlock), 0, s, words, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_nextmatch(const uint8_t *b, int32_t n, int32_t sigma, int32_t *nm, hipStream_t s) {
+    hipLaunchKernelGGL(k_nextmatch, dim3(sigma), dim3(kBlock), 0, s, b, n, nm);
+    return hipGetLastError();
+}
+
+hipError_t launch_base(int32_t h0, const uint8_t *a, int32_t n, int32_t sigma, const int32_t *nm,
+                       int32_t *base0, int32_t *last, int32_t nstrips, int32_t hlast, int32_t *err,
+                       hipStream_t s) {
+    const dim3 grid((n + 2 + kBlock - 1) / kBlock, nstrips);
+    switch (h0) {
+        case 16:
+            hipLaunchKernelGGL(k_base<16>, grid, dim3(kBlock), 0, s, a, n, sigma, nm, base0, last,
+                               nstrips, hlast, err);
+            break;
+        case 32:
+            hipLaunchKernelGGL(k_base<32>, grid, dim3(kBlock), 0, s, a, n, sigma, nm, base0, last,
+                               nstrips, hlast, err);
+            break;
+        case 64:
+            hipLaunchKernelGGL(k_base<64>, grid, dim3(kBlock), 0, s, a, n, sigma, nm, base0, last,
+                               nstrips, hlast, err);
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_combine(const CombineArgs &c, int32_t npairs, hipStream_t s) {
+    hipLaunchKernelGGL(k_anchor, dim3(c.nanch, npairs), dim3(kBlock), 0, s, c);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int32_t ntiles = (c.n + c.tile - 1) / c.tile;
+    if (ntiles > 0) {
+        hipLaunchKernelGGL(k_bracket, dim3(ntiles * c.nchunks, npairs), dim3(kBlock), 0, s, c);
+        e = hipGetLastError();
+    }
+    return e;
+}
+
+hipError_t launch_length(const int32_t *top, int32_t m, int32_t n, int32_t *hdr, int4 *root,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(k_length, dim3(1), dim3(kBlock), 0, s, top, m, n, hdr, root);
+    return hipGetLastError();
+}
+
+hipError_t launch_trace_split(const CombineArgs &c, int32_t nparent, const int4 *nodes_in,
+                              int4 *nodes_out, int32_t *err, hipStream_t s) {
+    hipLaunchKernelGGL(k_trace_split, dim3(nparent), dim3(kBlock), 0, s, c, nodes_in, nodes_out, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_trace_leaf(int32_t h0, const uint8_t *a, int32_t n, int32_t sigma,
+                             const int32_t *nm, int32_t nstrips, int32_t hlast, const int4 *nodes,
+                             int32_t *a_idx, int32_t *b_idx, int32_t *err, hipStream_t s) {
+    switch (h0) {
+        case 16:
+            hipLaunchKernelGGL(k_trace_leaf<16>, dim3(nstrips), dim3(kBlock), 0, s, a, n, sigma, nm,
+                               nstrips, hlast, nodes, a_idx, b_idx, err);
+            break;
+        case 32:
+            hipLaunchKernelGGL(k_trace_leaf<32>, dim3(nstrips), dim3(kBlock), 0, s, a, n, sigma, nm,
+                               nstrips, hlast, nodes, a_idx, b_idx, err);
+            break;
+        case 64:
+            hipLaunchKernelGGL(k_trace_leaf<64>, dim3(nstrips), dim3(kBlock), 0, s, a, n, sigma, nm,
+                               nstrips, hlast, nodes, a_idx, b_idx, err);
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_len(const int32_t *hdr, int32_t *dst, hipStream_t s) {
+    hipLaunchKernelGGL(k_copy_len, dim3(1), dim3(64), 0, s, hdr, dst);
+    return hipGetLastError();
+}
+
+}  // namespace lcs

@@ -1,0 +1,25 @@
+// Host-side launchers of the single-pair kernels (defined in lcs_kernels.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lcs_geom.h"
+
+namespace lcs {
+
+hipError_t launch_clear(int32_t *words, int32_t count, hipStream_t s);
+hipError_t launch_nextmatch(const uint8_t *b, int32_t n, int32_t sigma, int32_t *nm, hipStream_t s);
+hipError_t launch_base(int32_t h0, const uint8_t *a, int32_t n, int32_t sigma, const int32_t *nm,
+                       int32_t *base0, int32_t *last, int32_t nstrips, int32_t hlast, int32_t *err,
+                       hipStream_t s);
+hipError_t launch_combine(const CombineArgs &c, int32_t npairs, hipStream_t s);
+hipError_t launch_length(const int32_t *top, int32_t m, int32_t n, int32_t *hdr, int4 *root,
+                         hipStream_t s);
+hipError_t launch_trace_split(const CombineArgs &c, int32_t nparent, const int4 *nodes_in,
+                              int4 *nodes_out, int32_t *err, hipStream_t s);
+hipError_t launch_trace_leaf(int32_t h0, const uint8_t *a, int32_t n, int32_t sigma,
+                             const int32_t *nm, int32_t nstrips, int32_t hlast, const int4 *nodes,
+                             int32_t *a_idx, int32_t *b_idx, int32_t *err, hipStream_t s);
+hipError_t launch_copy_len(const int32_t *hdr, int32_t *dst, hipStream_t s);
+
+}  // namespace lcs

@@ -1,0 +1,256 @@
+"""Thin ctypes binding of ``liblcs.so`` (the C ABI declared in include/lcs.h).
+
+Argument marshalling only: torch tensors on the ROCm device are passed as raw
+device pointers, streams as ``hipStream_t`` handles.  Every step of the method
+runs in the library's HIP kernels; there is no CPU fallback, and loading fails
+loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "liblcs.so")
+
+LCS_OK = 0
+STATUS = {
+    0: "LCS_OK", -1: "LCS_E_INVAL", -2: "LCS_E_TOO_BIG", -3: "LCS_E_WORKSPACE", -4: "LCS_E_HIP",
+    -5: "LCS_E_SYMBOL", -6: "LCS_E_CAPACITY", -7: "LCS_E_STATE", -8: "LCS_E_NOMEM",
+    -9: "LCS_E_BUDGET", -10: "LCS_E_AGAIN",
+}
+BATCH_PERSISTENT, BATCH_PER_PAIR, BATCH_GRAPH = 0, 1, 2
+
+
+class LcsError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__("%s: %s" % (where, _lib_status(status)))
+
+
+class PlanDesc(ctypes.Structure):
+    _fields_ = [("max_m", ctypes.c_int32), ("max_n", ctypes.c_int32), ("alphabet", ctypes.c_int32),
+                ("base_rows", ctypes.c_int32), ("tile", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class PairDesc(ctypes.Structure):
+    _fields_ = [("a_off", ctypes.c_int64), ("b_off", ctypes.c_int64), ("m", ctypes.c_int32),
+                ("n", ctypes.c_int32)]
+
+
+class BatchDesc(ctypes.Structure):
+    _fields_ = [("max_pairs", ctypes.c_int32), ("max_len", ctypes.c_int32),
+                ("alphabet", ctypes.c_int32), ("base_rows", ctypes.c_int32),
+                ("tile", ctypes.c_int32), ("slots", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class ServerDesc(ctypes.Structure):
+    _fields_ = [("max_len", ctypes.c_int32), ("alphabet", ctypes.c_int32),
+                ("base_rows", ctypes.c_int32), ("tile", ctypes.c_int32),
+                ("slots", ctypes.c_int32), ("max_queue", ctypes.c_int32),
+                ("flags", ctypes.c_uint32)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_int64), ("status", ctypes.c_int32), ("length", ctypes.c_int32),
+                ("wit_off", ctypes.c_int64), ("t_submit", ctypes.c_double),
+                ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double)]
+
+
+_lib = None
+
+_P = ctypes.c_void_p
+_I32 = ctypes.c_int32
+_I64 = ctypes.c_int64
+_U32 = ctypes.c_uint32
+_SZ = ctypes.c_size_t
+_PI32 = ctypes.POINTER(ctypes.c_int32)
+_PSZ = ctypes.POINTER(ctypes.c_size_t)
+
+PROTOTYPES = {
+    "lcs_status_string": (ctypes.c_char_p, [_I32]),
+    "lcs_plan": (_I32, [ctypes.POINTER(PlanDesc), ctypes.POINTER(_P), _PSZ]),
+    "lcs_plan_workspace": (_I32, [_P, _I32, _I32, _PSZ]),
+    "lcs_plan_destroy": (_I32, [_P]),
+    "lcs_dist_build": (_I32, [_P, _P, _I32, _P, _I32, _P, _SZ, _P]),
+    "lcs_length": (_I32, [_P, _PI32, _P]),
+    "lcs_length_device": (_I32, [_P, _P, _P]),
+    "lcs_trace": (_I32, [_P, _P, _P, _I32, _PI32, _P]),
+    "lcs_plan_levels": (_I32, [_P, _PI32, _PI32]),
+    "lcs_dist_view": (_I32, [_P, _I32, _I32, ctypes.POINTER(_P), _PI32, _PI32, _PI32]),
+    "lcs_batch_plan": (_I32, [ctypes.POINTER(BatchDesc), ctypes.POINTER(_P), _PSZ]),
+    "lcs_batch_destroy": (_I32, [_P]),
+    "lcs_batch_submit": (_I32, [_P, _P, _I32, _P, _I64, _P, _P, _P, _I64, _P, _SZ, _U32, _P]),
+    "lcs_server_open": (_I32, [ctypes.POINTER(ServerDesc), _P, _SZ, _P, _P, _I64, ctypes.POINTER(_P)]),
+    "lcs_server_footprint": (_I32, [_P, _I32, _I32, _PSZ]),
+    "lcs_server_submit": (_I32, [_P, _I64, _P, _I32, _P, _I32, _I32]),
+    "lcs_server_poll": (_I32, [_P, _P, _I32, _PI32]),
+    "lcs_server_pending": (_I32, [_P, _PI32, _PI32]),
+    "lcs_server_close": (_I32, [_P]),
+}
+
+
+def load():
+    """Load liblcs.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("liblcs.so not found at %s; build it with "
+                              "`python -c 'import __graft_entry__ as g; g.build()'`" % LIB_PATH)
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in PROTOTYPES.items():
+            fn = getattr(lib, name, None)
+            if fn is None:
+                continue
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _lib_status(s: int) -> str:
+    try:
+        return load().lcs_status_string(int(s)).decode()
+    except Exception:
+        return STATUS.get(int(s), str(s))
+
+
+def check(status: int, where: str) -> None:
+    if status != LCS_OK:
+        raise LcsError(status, where)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def stream_handle(stream=None) -> ctypes.c_void_p:
+    """hipStream_t of a torch stream (default: the current stream)."""
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(int(s.cuda_stream))
+
+
+def _dptr(t) -> ctypes.c_void_p:
+    if t is None:
+        return ctypes.c_void_p(0)
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return ctypes.c_void_p(int(t.data_ptr()))
+
+
+def device_bytes(x, device="cuda"):
+    """uint8 device tensor from a numpy array / bytes / str."""
+    torch = _torch()
+    if isinstance(x, str):
+        x = x.encode("latin-1")
+    arr = np.frombuffer(bytes(x), dtype=np.uint8) if isinstance(x, (bytes, bytearray)) else np.asarray(x, dtype=np.uint8)
+    t = torch.from_numpy(np.ascontiguousarray(arr).copy())
+    return t.to(device) if t.numel() else torch.zeros(0, dtype=torch.uint8, device=device)
+
+
+def alloc_workspace(nbytes: int, device="cuda"):
+    """A device byte buffer usable as a workspace (torch allocations are 512-byte aligned)."""
+    torch = _torch()
+    t = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+    if t.data_ptr() % 256:
+        raise RuntimeError("workspace allocation is not 256-byte aligned")
+    return t
+
+
+class Plan:
+    """One planned strip recursion (lcs_plan); reusable for any m <= max_m, n <= max_n."""
+
+    def __init__(self, max_m: int, max_n: int, alphabet: int, base_rows: int = 0, tile: int = 0):
+        lib = load()
+        self.desc = PlanDesc(int(max_m), int(max_n), int(alphabet), int(base_rows), int(tile), 0)
+        h = ctypes.c_void_p()
+        ws = ctypes.c_size_t()
+        check(lib.lcs_plan(ctypes.byref(self.desc), ctypes.byref(h), ctypes.byref(ws)), "lcs_plan")
+        self._h = h
+        self.workspace_bytes = int(ws.value)
+        self._keep = None
+
+    def workspace_for(self, m: int, n: int) -> int:
+        ws = ctypes.c_size_t()
+        check(load().lcs_plan_workspace(self._h, int(m), int(n), ctypes.byref(ws)), "lcs_plan_workspace")
+        return int(ws.value)
+
+    def build(self, a, b, ws, stream=None) -> None:
+        """lcs_dist_build on device tensors a (m bytes), b (n bytes), ws (workspace)."""
+        self._keep = (a, b, ws)  # the library keeps raw pointers until the next build
+        check(load().lcs_dist_build(self._h, _dptr(a), int(a.numel()), _dptr(b), int(b.numel()),
+                                    _dptr(ws), int(ws.numel()), stream_handle(stream)),
+              "lcs_dist_build")
+
+    def length(self, stream=None) -> int:
+        out = ctypes.c_int32()
+        check(load().lcs_length(self._h, ctypes.byref(out), stream_handle(stream)), "lcs_length")
+        return int(out.value)
+
+    def length_device(self, out, stream=None) -> None:
+        check(load().lcs_length_device(self._h, _dptr(out), stream_handle(stream)), "lcs_length_device")
+
+    def trace(self, a_idx, b_idx, stream=None) -> int:
+        out = ctypes.c_int32()
+        cap = min(int(a_idx.numel()), int(b_idx.numel()))
+        check(load().lcs_trace(self._h, _dptr(a_idx), _dptr(b_idx), cap, ctypes.byref(out),
+                               stream_handle(stream)), "lcs_trace")
+        return int(out.value)
+
+    def levels(self):
+        nl = ctypes.c_int32()
+        check(load().lcs_plan_levels(self._h, ctypes.byref(nl), None), "lcs_plan_levels")
+        arr = (ctypes.c_int32 * max(nl.value, 1))()
+        check(load().lcs_plan_levels(self._h, ctypes.byref(nl), arr), "lcs_plan_levels")
+        return [int(arr[i]) for i in range(nl.value)]
+
+    def dist(self, level: int, strip: int, ws):
+        """(matrix view (n+2) x (h+1) int32 on the device, first grid row of the strip)."""
+        ptr = ctypes.c_void_p()
+        rows, cols, row0 = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        check(load().lcs_dist_view(self._h, int(level), int(strip), ctypes.byref(ptr),
+                                   ctypes.byref(rows), ctypes.byref(cols), ctypes.byref(row0)),
+              "lcs_dist_view")
+        off = int(ptr.value) - int(ws.data_ptr())
+        nbytes = rows.value * cols.value * 4
+        view = ws[off:off + nbytes].view(_torch().int32).view(rows.value, cols.value)
+        return view, int(row0.value)
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            load().lcs_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def lcs(a, b, alphabet: int, base_rows: int = 0, tile: int = 0, witness: bool = True,
+        device="cuda", stream=None):
+    """LCS of two symbol strings on the GPU: (L, a_idx, b_idx) as numpy arrays."""
+    torch = _torch()
+    ad, bd = device_bytes(a, device), device_bytes(b, device)
+    m, n = int(ad.numel()), int(bd.numel())
+    plan = Plan(m, n, alphabet, base_rows, tile)
+    try:
+        ws = alloc_workspace(plan.workspace_for(m, n), device)
+        plan.build(ad, bd, ws, stream)
+        if not witness:
+            return plan.length(stream), None, None
+        cap = max(1, min(m, n))
+        ai = torch.empty(cap, dtype=torch.int32, device=device)
+        bi = torch.empty(cap, dtype=torch.int32, device=device)
+        L = plan.trace(ai, bi, stream)
+        return L, ai[:L].cpu().numpy(), bi[:L].cpu().numpy()
+    finally:
+        plan.close()

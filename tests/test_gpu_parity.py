@@ -1,0 +1,215 @@
+"""GPU parity: the HIP path against the CPU oracle, through the C ABI.
+
+Breakout matrices are compared cell for cell with the oracle's definition at
+sizes that span several tiles and ragged tails; lengths and witnesses are
+compared exactly (integer results, tolerance 0) up to the 16384 x 16384 pair.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2309_09072_amd import lcs as L
+from paper_2309_09072_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def run_pair(a, b, sigma, base_rows=0, tile=0, check_levels=False, trace=True):
+    import torch
+    a = np.asarray(a, np.uint8)
+    b = np.asarray(b, np.uint8)
+    m, n = a.size, b.size
+    ad, bd = L.device_bytes(a), L.device_bytes(b)
+    plan = L.Plan(m, n, sigma, base_rows, tile)
+    ws = L.alloc_workspace(plan.workspace_for(m, n))
+    plan.build(ad, bd, ws)
+    Lg = plan.length()
+    if check_levels and m > 0 and n > 0:
+        for lv, cnt in enumerate(plan.levels()):
+            for s in range(cnt):
+                D, row0 = plan.dist(lv, s, ws)
+                Dh = D.cpu().numpy()
+                h = Dh.shape[1] - 1
+                want = oracle.dist_rows(a, row0, row0 + h, b)
+                bad = np.argwhere(Dh[: n + 1] != want)
+                assert bad.size == 0, "level %d strip %d (rows %d..%d): first mismatch %s got %d want %d" % (
+                    lv, s, row0, row0 + h, bad[0], Dh[tuple(bad[0])], want[tuple(bad[0])])
+                assert np.all(Dh[n + 1] == n + 1)
+    wit = None
+    if trace:
+        cap = max(1, min(m, n))
+        ai = torch.full((cap,), -1, dtype=torch.int32, device="cuda")
+        bi = torch.full((cap,), -1, dtype=torch.int32, device="cuda")
+        Lt = plan.trace(ai, bi)
+        assert Lt == Lg
+        wit = (ai[:Lt].cpu().numpy(), bi[:Lt].cpu().numpy())
+    return Lg, wit, plan, ws
+
+
+def check_against_oracle(a, b, sigma, **kw):
+    Lg, wit, plan, ws = run_pair(a, b, sigma, **kw)
+    Lo, ao, bo = oracle.lcs_witness(np.asarray(a, np.uint8), np.asarray(b, np.uint8))
+    assert Lg == Lo, "length %d vs oracle %d" % (Lg, Lo)
+    if wit is not None:
+        assert np.array_equal(wit[0], ao), "a_idx differs from the oracle's canonical witness"
+        assert np.array_equal(wit[1], bo), "b_idx differs from the oracle's canonical witness"
+    return Lg, plan, ws
+
+
+# ----------------------------------------------------------------- small, full D
+
+
+@pytest.mark.parametrize("base_rows,tile", [(16, 4), (16, 8), (32, 16), (64, 64), (16, 64)])
+def test_levels_cell_for_cell(base_rows, tile):
+    r = np.random.default_rng(100 + base_rows + tile)
+    shapes = [(200, 150, 4), (129, 203, 2), (97, 64, 20), (65, 257, 4), (16, 31, 1), (250, 9, 3)]
+    for m, n, sig in shapes:
+        a = r.integers(0, sig, m).astype(np.uint8)
+        b = r.integers(0, sig, n).astype(np.uint8)
+        say("levels", base_rows, tile, m, n, sig)
+        check_against_oracle(a, b, sig, base_rows=base_rows, tile=tile, check_levels=True)
+
+
+def test_paper_grid_example():
+    """Fig. 1 grid: rows tcaggatt, columns gatttatgcagg; breakouts of Section II-B-1."""
+    a = np.frombuffer(b"tcaggatt", np.uint8) - ord("a")
+    b = np.frombuffer(b"gatttatgcagg", np.uint8) - ord("a")
+    Lg, wit, plan, ws = run_pair(a, b, 26, base_rows=16, tile=4, check_levels=True)
+    assert Lg == 5
+    top, _ = plan.dist(len(plan.levels()) - 1, 0, ws)
+    top = top.cpu().numpy()
+    assert list(top[0][:6]) == [0, 1, 2, 3, 4, 12]
+    assert top[7][5] == 13
+    assert bytes((a[wit[0]] + ord("a")).astype(np.uint8)) == b"tcagg"
+
+
+def test_three_string_example_pairwise():
+    a = np.frombuffer(b"abccb", np.uint8) - ord("a")
+    b = np.frombuffer(b"abba", np.uint8) - ord("a")
+    Lg, wit, _, _ = run_pair(a, b, 3, base_rows=16, tile=4)
+    assert Lg == 3 and list(wit[0]) == [0, 1, 4] and list(wit[1]) == [0, 1, 2]
+
+
+# ----------------------------------------------------------------- random shapes
+
+
+def test_random_shapes_length_and_witness():
+    r = np.random.default_rng(7)
+    for case in range(40):
+        sig = int(r.choice([1, 2, 4, 20, 256]))
+        m = int(r.integers(0, 3000))
+        n = int(r.integers(0, 3000))
+        if case % 5 == 0:
+            m = int(r.integers(0, 70))
+        base_rows = int(r.choice([16, 32, 64]))
+        tile = int(r.choice([4, 16, 32, 64]))
+        a = r.integers(0, sig, m).astype(np.uint8)
+        if case % 3 == 0 and m > 0:
+            b = synth.fit_length(r, synth.mutate(r, a, sig, 0.1, 0.05, 0.05), max(n, 1), sig)
+        else:
+            b = r.integers(0, sig, n).astype(np.uint8)
+        say("random case", case, m, b.size, sig, base_rows, tile)
+        check_against_oracle(a, b, sig, base_rows=base_rows, tile=tile)
+
+
+def test_edge_cases():
+    r = np.random.default_rng(9)
+    x = r.integers(0, 4, 300).astype(np.uint8)
+    cases = [
+        (np.zeros(0, np.uint8), x, 4), (x, np.zeros(0, np.uint8), 4),
+        (np.zeros(0, np.uint8), np.zeros(0, np.uint8), 4),
+        (x[:1], x, 4), (x, x[:1], 4), (x[:1], x[:1], 4),
+        (x, x, 4),                                            # LCS(x, x) = |x|
+        (np.zeros(100, np.uint8), np.zeros(37, np.uint8), 1),  # unary alphabet
+        (np.zeros(37, np.uint8), np.zeros(100, np.uint8), 1),
+        (x, (x + 4).astype(np.uint8), 8),                     # disjoint alphabets
+        (x[:64], x, 4), (x[:65], x, 4), (x[:63], x, 4),       # around one base strip
+        (x, x[:64], 4), (x, x[:65], 4), (x, x[:63], 4),       # around one tile
+    ]
+    for a, b, sig in cases:
+        say("edge", a.size, b.size, sig)
+        Lg, _, _ = check_against_oracle(a, b, sig)
+        if a is b or (a.size == b.size and np.array_equal(a, b)):
+            assert Lg == a.size
+
+
+def test_bad_symbol_reports_error():
+    a = np.array([0, 1, 2, 9, 1], np.uint8)
+    b = np.array([0, 1, 2, 1], np.uint8)
+    plan = L.Plan(5, 4, 4)
+    ws = L.alloc_workspace(plan.workspace_for(5, 4))
+    plan.build(L.device_bytes(a), L.device_bytes(b), ws)
+    with pytest.raises(L.LcsError) as e:
+        plan.length()
+    assert e.value.status == -5
+
+
+def test_determinism_and_reuse():
+    """Two builds into the same workspace give identical matrices; a plan is reusable."""
+    import torch
+    p = synth.pair_uniform(700, 900, 4, 31)
+    plan = L.Plan(1000, 1000, 4, 16, 16)
+    ws = L.alloc_workspace(plan.workspace_bytes)
+    ad, bd = L.device_bytes(p.a), L.device_bytes(p.b)
+    plan.build(ad, bd, ws)
+    L1 = plan.length()
+    top1 = plan.dist(len(plan.levels()) - 1, 0, ws)[0].clone()
+    q = synth.pair_uniform(300, 200, 4, 32)          # something else in between
+    plan.build(L.device_bytes(q.a), L.device_bytes(q.b), ws)
+    assert plan.length() == oracle.lcs_length(q.a, q.b)
+    plan.build(ad, bd, ws)
+    assert plan.length() == L1 == oracle.lcs_length(p.a, p.b)
+    top2 = plan.dist(len(plan.levels()) - 1, 0, ws)[0]
+    assert torch.equal(top1, top2)
+
+
+# ----------------------------------------------------------------- the named workloads
+
+
+def _top_rows_check(a, b, plan, ws, verts):
+    top, row0 = plan.dist(len(plan.levels()) - 1, 0, ws)
+    assert row0 == 0
+    got = top[list(verts)].cpu().numpy()
+    want = oracle.dist_rows(a, 0, a.size, b, verts)
+    assert np.array_equal(got[:, :], want)
+
+
+def test_config_small_256():
+    p = synth.config_small()
+    say("pair 256x256")
+    Lg, plan, ws = check_against_oracle(p.a, p.b, p.sigma, base_rows=64, check_levels=True)
+
+
+def test_config_4096():
+    p = synth.config_4096()
+    say("pair 4096x4096")
+    Lg, plan, ws = check_against_oracle(p.a, p.b, p.sigma, base_rows=64)
+    # sampled rows of the top matrix (the oracle computes one row per dynamic program)
+    _top_rows_check(p.a, p.b, plan, ws, [0, 1, 63, 64, 65, 2048, 4000, 4095, 4096])
+    # sampled rows of every level's first and last strip
+    for lv, cnt in enumerate(plan.levels()):
+        for s in sorted({0, cnt - 1}):
+            D, row0 = plan.dist(lv, s, ws)
+            h = D.shape[1] - 1
+            verts = [0, 777, 4033, 4096]
+            got = D[verts].cpu().numpy()
+            assert np.array_equal(got, oracle.dist_rows(p.a, row0, row0 + h, p.b, verts)), (lv, s)
+
+
+def test_config_16384_mutated():
+    p = synth.config_16384()
+    say("pair 16384x16384 mutated, alphabet 20")
+    Lg, plan, ws = check_against_oracle(p.a, p.b, p.sigma, base_rows=64)
+    top, _ = plan.dist(len(plan.levels()) - 1, 0, ws)
+    row = oracle.lcs_last_row(p.a, p.b)                 # C[m][k] for every k
+    D0 = top[0].cpu().numpy()
+    for k in range(0, p.b.size + 1, 97):
+        assert int(np.sum(D0 <= k)) - 1 == row[k]
+    _top_rows_check(p.a, p.b, plan, ws, [16300, 16383, 16384])
