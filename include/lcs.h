@@ -72,9 +72,11 @@ typedef struct lcs_plan_desc {
     int32_t base_rows; /* rows per base strip (Section II-B-3 generalised to
                           base_rows rows): 16, 32 or 64; 0 selects 64 */
     int32_t tile;      /* vertices per search tile of the combine: power of two
-                          in 4..128; 0 selects the tuned default */
-    uint32_t flags;    /* reserved, must be 0 */
+                          in 4..32; 0 selects the default (32) */
+    uint32_t flags;    /* 0 or LCS_PLAN_PROFILE */
 } lcs_plan_desc;
+
+#define LCS_PLAN_PROFILE 1u /* record HIP events around every kernel of a build/trace */
 
 /*
  * Plan the breakout-matrix recursion for strings up to max_m x max_n.
@@ -83,7 +85,7 @@ typedef struct lcs_plan_desc {
  * sizes: every level of the strip recursion (all kept for the trace), a
  * sentinel row per matrix, the next-match tables and search/trace scratch.
  * Errors: LCS_E_INVAL (null pointer, negative size, alphabet outside 1..256,
- * unsupported base_rows or tile), LCS_E_TOO_BIG (a matrix would have 2^31 or
+ * unsupported base_rows or tile), LCS_E_TOO_BIG (a matrix would have 2^30 or
  * more cells), LCS_E_NOMEM.
  */
 int32_t lcs_plan(const lcs_plan_desc *desc, lcs_plan_t *out, size_t *workspace_bytes);
@@ -140,6 +142,43 @@ int32_t lcs_length_device(lcs_plan_t plan, int32_t *length_dev, void *stream);
  */
 int32_t lcs_trace(lcs_plan_t plan, int32_t *a_idx, int32_t *b_idx, int32_t capacity,
                   int32_t *length_host, void *stream);
+
+/*
+ * Witness of the last build, enqueued only (no synchronisation; usable inside
+ * a captured graph).  Writes L to device memory *length_dev; a_idx and b_idx
+ * as for lcs_trace.  Errors are the argument errors of lcs_trace; a device
+ * error is reported by the next lcs_length.
+ */
+int32_t lcs_trace_device(lcs_plan_t plan, int32_t *a_idx, int32_t *b_idx, int32_t capacity,
+                         int32_t *length_dev, void *stream);
+
+/*
+ * Per-kernel timing of a plan made with LCS_PLAN_PROFILE: one record per
+ * launch of every build and trace since the records were last read, in launch
+ * order, measured with HIP events recorded on the caller's stream right
+ * before and after the launch (at most 32768 records are kept).
+ * `bytes` is the launch's algorithmic traffic: the breakout-matrix cells (and
+ * tables) it must read and write once, 4 bytes each.  For a combine level
+ * each parent row i costs row i of D_U, row i of D_L and row i of D_G; the
+ * anchor kernel owns the anchor rows and the bracket kernel the others.
+ * Waits for the recorded events.  Returns at most max records; *count
+ * receives the number available.  When all of them fit (max >= *count) the
+ * records are cleared, so the next read starts with the next launch.
+ */
+#define LCS_PHASE_NEXTMATCH 0
+#define LCS_PHASE_BASE 1
+#define LCS_PHASE_ANCHOR 2
+#define LCS_PHASE_BRACKET 3
+#define LCS_PHASE_LENGTH 4
+#define LCS_PHASE_TRACE_SPLIT 5
+#define LCS_PHASE_TRACE_LEAF 6
+typedef struct lcs_phase_time {
+    int32_t kind;  /* LCS_PHASE_* */
+    int32_t level; /* recursion level of the launch (0 = base strips) */
+    float ms;      /* elapsed time between the two events */
+    int64_t bytes; /* algorithmic bytes of the launch */
+} lcs_phase_time;
+int32_t lcs_plan_profile(lcs_plan_t plan, lcs_phase_time *out, int32_t max, int32_t *count);
 
 /*
  * Inspection of the last build (for tests and debugging).

@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <new>
+#include <vector>
 
 #include "lcs.h"
 #include "lcs_launch.h"
@@ -13,7 +14,56 @@
 
 using namespace lcs;
 
+namespace lcs {
+
+// Optional per-launch timing: HIP events recorded around each launch.
+struct Recorder {
+    struct Rec {
+        int32_t kind, level;
+        int64_t bytes;
+        hipEvent_t beg, end;
+        bool ended;
+    };
+    static constexpr size_t kMaxRecords = 1 << 15;
+    std::vector<hipEvent_t> pool;
+    std::vector<Rec> recs;
+    size_t used = 0;
+    hipStream_t s = nullptr;
+    bool on = false;
+
+    hipEvent_t take() {
+        if (used == pool.size()) {
+            hipEvent_t e = nullptr;
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            pool.push_back(e);
+        }
+        return pool[used++];
+    }
+    void reset(hipStream_t st) {
+        recs.clear();
+        used = 0;
+        s = st;
+    }
+    void begin(int32_t kind, int32_t level, int64_t bytes) {
+        if (!on || recs.size() >= kMaxRecords) return;
+        Rec r{kind, level, bytes, take(), take(), false};
+        if (r.beg) hipEventRecord(r.beg, s);
+        recs.push_back(r);
+    }
+    void end() {
+        if (!on || recs.empty() || recs.back().ended) return;
+        recs.back().ended = true;
+        if (recs.back().end) hipEventRecord(recs.back().end, s);
+    }
+    ~Recorder() {
+        for (hipEvent_t e : pool) hipEventDestroy(e);
+    }
+};
+
+}  // namespace lcs
+
 struct lcs_plan_s {
+    Recorder rec;
     lcs_plan_desc d{};
     Layout lay;
     bool built = false;
@@ -45,7 +95,7 @@ namespace lcs {
 // shared with the batch and serving code
 bool valid_shape(int32_t base_rows, int32_t tile) {
     if (base_rows != 16 && base_rows != 32 && base_rows != 64) return false;
-    if (tile < 4 || tile > 64 || (tile & (tile - 1))) return false;
+    if (tile < 4 || tile > 32 || (tile & (tile - 1))) return false;
     return true;
 }
 
@@ -54,44 +104,92 @@ int32_t resolve(int32_t v, int32_t dflt) { return v == 0 ? dflt : v; }
 static int32_t hip_status(hipError_t e) { return e == hipSuccess ? LCS_OK : LCS_E_HIP; }
 
 // Enqueue the whole build for layout L on workspace ws.
+// Algorithmic bytes of one combine level, split by parent rows: each row i of
+// the parent costs row i of D_U and D_L (read) and row i of D_G (written).
+static void level_bytes(const Layout &L, size_t l, int64_t *anchor, int64_t *bracket) {
+    const LevelGeom &c = L.lev[l - 1];
+    int64_t per_row = 0;  // summed over the pairs of the level
+    for (int32_t p = 0; p < L.lev[l].npairs; ++p) {
+        const int32_t hU = c.hfull;
+        const int32_t hL = (2 * p + 1 == c.nstrips - 1) ? c.hlast : c.hfull;
+        per_row += 4 * (int64_t)((hU + 1) + (hL + 1) + (hU + hL + 1));
+    }
+    *anchor = per_row * L.nanch;
+    *bracket = per_row * (L.n + 2 - L.nanch);
+}
+
+int64_t build_bytes(const Layout &L) {
+    if (L.lev.empty()) return 0;
+    int64_t t = L.lev[0].bytes + L.m;
+    for (size_t l = 1; l < L.lev.size(); ++l) {
+        int64_t a, b;
+        level_bytes(L, l, &a, &b);
+        t += a + b;
+    }
+    return t;
+}
+
 int32_t enqueue_build(const Layout &L, uint8_t *ws, const uint8_t *a, const uint8_t *b,
-                      hipStream_t s) {
+                      hipStream_t s, Recorder *rec) {
+    Recorder dummy;
+    Recorder &R = rec ? *rec : dummy;
     int32_t *hdr = reinterpret_cast<int32_t *>(ws + L.off_hdr);
     int32_t *nm = reinterpret_cast<int32_t *>(ws + L.off_nm);
     hipError_t e = launch_clear(hdr, kHeaderWords, s);
     if (e != hipSuccess || L.lev.empty()) return hip_status(e);
+    R.begin(LCS_PHASE_NEXTMATCH, 0, (int64_t)L.sigma * L.n + 4 * (int64_t)L.sigma * (L.n + 2));
     e = launch_nextmatch(b, L.n, L.sigma, nm, s);
+    R.end();
     if (e != hipSuccess) return LCS_E_HIP;
     const LevelGeom &g0 = L.lev[0];
+    R.begin(LCS_PHASE_BASE, 0, g0.bytes + L.m);
     e = launch_base(L.h0, a, L.n, L.sigma, nm, reinterpret_cast<int32_t *>(ws + g0.base),
                     reinterpret_cast<int32_t *>(ws + g0.last_off), g0.nstrips, g0.hlast, hdr, s);
+    R.end();
     if (e != hipSuccess) return LCS_E_HIP;
     for (size_t l = 1; l < L.lev.size(); ++l) {
-        e = launch_combine(combine_args(L, ws, l), L.lev[l].npairs, s);
+        int64_t ba, bb;
+        level_bytes(L, l, &ba, &bb);
+        const CombineArgs ca = combine_args(L, ws, l);
+        R.begin(LCS_PHASE_ANCHOR, (int32_t)l, ba);
+        e = launch_anchor(ca, L.lev[l].npairs, s);
+        R.end();
+        if (e != hipSuccess) return LCS_E_HIP;
+        R.begin(LCS_PHASE_BRACKET, (int32_t)l, bb);
+        e = launch_bracket(ca, L.lev[l].npairs, s);
+        R.end();
         if (e != hipSuccess) return LCS_E_HIP;
     }
     const LevelGeom &top = L.lev.back();
+    R.begin(LCS_PHASE_LENGTH, (int32_t)L.lev.size() - 1, 4 * (int64_t)(L.m + 1));
     e = launch_length(reinterpret_cast<const int32_t *>(ws + top.last_off), L.m, L.n, hdr,
                       reinterpret_cast<int4 *>(ws + L.node_off.back()), s);
+    R.end();
     return hip_status(e);
 }
 
 // Enqueue the witness trace of a finished build.
 int32_t enqueue_trace(const Layout &L, uint8_t *ws, const uint8_t *a, int32_t *a_idx,
-                      int32_t *b_idx, hipStream_t s) {
+                      int32_t *b_idx, hipStream_t s, Recorder *rec) {
+    Recorder dummy;
+    Recorder &R = rec ? *rec : dummy;
     if (L.lev.empty()) return LCS_OK;
     int32_t *hdr = reinterpret_cast<int32_t *>(ws + L.off_hdr);
     int32_t *nm = reinterpret_cast<int32_t *>(ws + L.off_nm);
     for (size_t l = L.lev.size() - 1; l >= 1; --l) {
+        R.begin(LCS_PHASE_TRACE_SPLIT, (int32_t)l, 8 * (int64_t)L.lev[l].nstrips * (L.lev[l - 1].hfull + 1));
         hipError_t e = launch_trace_split(combine_args(L, ws, l), L.lev[l].nstrips,
                                           reinterpret_cast<const int4 *>(ws + L.node_off[l]),
                                           reinterpret_cast<int4 *>(ws + L.node_off[l - 1]), hdr, s);
+        R.end();
         if (e != hipSuccess) return LCS_E_HIP;
     }
     const LevelGeom &g0 = L.lev[0];
+    R.begin(LCS_PHASE_TRACE_LEAF, 0, (int64_t)L.m + 8 * (int64_t)L.m);
     hipError_t e = launch_trace_leaf(L.h0, a, L.n, L.sigma, nm, g0.nstrips, g0.hlast,
                                      reinterpret_cast<const int4 *>(ws + L.node_off[0]), a_idx,
                                      b_idx, hdr, s);
+    R.end();
     return hip_status(e);
 }
 
@@ -103,7 +201,8 @@ extern "C" int32_t lcs_plan(const lcs_plan_desc *desc, lcs_plan_t *out, size_t *
     lcs_plan_desc d = *desc;
     d.base_rows = resolve(d.base_rows, kDefaultBaseRows);
     d.tile = resolve(d.tile, kDefaultTile);
-    if (d.max_m < 0 || d.max_n < 0 || d.alphabet < 1 || d.alphabet > 256 || d.flags != 0)
+    if (d.max_m < 0 || d.max_n < 0 || d.alphabet < 1 || d.alphabet > 256 ||
+        (d.flags & ~LCS_PLAN_PROFILE) != 0)
         return LCS_E_INVAL;
     if (!valid_shape(d.base_rows, d.tile)) return LCS_E_INVAL;
     if (d.max_n > 0x7ffffff0 || d.max_m > 0x7ffffff0) return LCS_E_TOO_BIG;
@@ -112,6 +211,7 @@ extern "C" int32_t lcs_plan(const lcs_plan_desc *desc, lcs_plan_t *out, size_t *
     lcs_plan_s *p = new (std::nothrow) lcs_plan_s();
     if (!p) return LCS_E_NOMEM;
     p->d = d;
+    p->rec.on = (d.flags & LCS_PLAN_PROFILE) != 0;
     *workspace_bytes = (size_t)L.total;
     *out = p;
     return LCS_OK;
@@ -148,7 +248,8 @@ extern "C" int32_t lcs_dist_build(lcs_plan_t p, const uint8_t *a, int32_t m, con
     p->a = a;
     p->b = b;
     p->empty = (m == 0 || n == 0);
-    const int32_t rc = enqueue_build(L, p->ws, a, b, static_cast<hipStream_t>(stream));
+    p->rec.s = static_cast<hipStream_t>(stream);
+    const int32_t rc = enqueue_build(L, p->ws, a, b, static_cast<hipStream_t>(stream), &p->rec);
     if (rc != LCS_OK) return rc;
     p->built = true;
     return LCS_OK;
@@ -201,7 +302,8 @@ extern "C" int32_t lcs_trace(lcs_plan_t p, int32_t *a_idx, int32_t *b_idx, int32
     }
     if (!a_idx || !b_idx) return LCS_E_INVAL;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const int32_t rc = enqueue_trace(p->lay, p->ws, p->a, a_idx, b_idx, s);
+    p->rec.s = s;
+    const int32_t rc = enqueue_trace(p->lay, p->ws, p->a, a_idx, b_idx, s, &p->rec);
     if (rc != LCS_OK) return rc;
     int32_t h[3];
     const int32_t rc2 = read_header(p, s, h);
@@ -232,5 +334,44 @@ extern "C" int32_t lcs_dist_view(lcs_plan_t p, int32_t level, int32_t strip, con
     *rows = p->lay.n + 2;
     *cols = (last ? g.hlast : g.hfull) + 1;
     *row0 = strip * g.hfull;
+    return LCS_OK;
+}
+
+extern "C" int32_t lcs_trace_device(lcs_plan_t p, int32_t *a_idx, int32_t *b_idx, int32_t capacity,
+                                    int32_t *length_dev, void *stream) {
+    if (!p || !length_dev) return LCS_E_INVAL;
+    if (!p->built) return LCS_E_STATE;
+    const int32_t need = p->lay.m < p->lay.n ? p->lay.m : p->lay.n;
+    if (capacity < need) return LCS_E_CAPACITY;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (!p->empty) {
+        if (!a_idx || !b_idx) return LCS_E_INVAL;
+        p->rec.s = s;
+        const int32_t rc = enqueue_trace(p->lay, p->ws, p->a, a_idx, b_idx, s, &p->rec);
+        if (rc != LCS_OK) return rc;
+    }
+    return launch_copy_len(reinterpret_cast<const int32_t *>(p->ws + p->lay.off_hdr), length_dev, s) ==
+                   hipSuccess
+               ? LCS_OK
+               : LCS_E_HIP;
+}
+
+extern "C" int32_t lcs_plan_profile(lcs_plan_t p, lcs_phase_time *out, int32_t max, int32_t *count) {
+    if (!p || !count || (max > 0 && !out)) return LCS_E_INVAL;
+    if (!p->rec.on) return LCS_E_STATE;
+    const int32_t nrec = (int32_t)p->rec.recs.size();
+    *count = nrec;
+    for (int32_t i = 0; i < nrec && i < max; ++i) {
+        const Recorder::Rec &r = p->rec.recs[i];
+        float ms = 0.f;
+        if (!r.beg || !r.end) return LCS_E_HIP;
+        if (hipEventSynchronize(r.end) != hipSuccess) return LCS_E_HIP;
+        if (hipEventElapsedTime(&ms, r.beg, r.end) != hipSuccess) return LCS_E_HIP;
+        out[i].kind = r.kind;
+        out[i].level = r.level;
+        out[i].ms = ms;
+        out[i].bytes = r.bytes;
+    }
+    if (max >= nrec) p->rec.reset(p->rec.s);  // every record delivered: start afresh
     return LCS_OK;
 }

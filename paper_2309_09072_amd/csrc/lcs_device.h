@@ -17,8 +17,9 @@ namespace lcs {
 constexpr int kBlock = 256;  // threads per work-group for every task
 constexpr int kWave = 64;
 constexpr int kWaves = kBlock / kWave;
-constexpr int kJChunk = 64;  // weights per bracket block (a block may take kJChunk + 1)
-constexpr int kMaxTile = 64;
+constexpr int kJChunk = 32;  // weights per bracket block (a block may take kJChunk + 1)
+constexpr int kBatch = 4;    // candidates whose loads are issued together
+constexpr int kMaxTile = 32;
 
 __host__ __device__ __forceinline__ int32_t imin(int32_t a, int32_t b) { return a < b ? a : b; }
 __host__ __device__ __forceinline__ int32_t imax(int32_t a, int32_t b) { return a > b ? a : b; }
@@ -149,6 +150,102 @@ __device__ void base_strip_block(const uint8_t *__restrict__ arow, int32_t h, in
 }
 
 // ---------------------------------------------------------------------------
+// Candidate scan of the combine equation for one output (vertex row urow of
+// D_U, weight j): candidates k = lo, lo+step, ... <= hi in increasing order,
+// value D_L(D_U(i, k), j - k).  Loads are issued kBatch candidates at a time
+// (the D_U values first, then the D_L lookups of the candidates that survive
+// the filters), so one round trip to memory serves several candidates; the
+// decisions are then taken one candidate at a time in increasing k, which
+// keeps the smallest minimising k.  Filters and exits:
+//   x < xa: skip the candidate (its crossing lies left of the bracket);
+//   x > xb: stop (every later crossing lies right of it; xb <= n);
+//   x - k >= best - j: stop, since D_L(x, w) >= x + w;
+//   value == vlo (a proven lower bound of the result): stop.
+// With step > 1 the thread owns every step-th candidate; its local result is
+// still exact for those candidates and the exits remain valid.
+__device__ __forceinline__ void scan_candidates(const int32_t *__restrict__ urow,
+                                                const int32_t *__restrict__ L, int32_t ldL,
+                                                int32_t j, int32_t lo, int32_t hi, int32_t step,
+                                                int32_t xa, int32_t xb, int32_t vlo, int32_t n,
+                                                int32_t &best, int32_t &bk, int32_t &bx) {
+    best = n + 2;
+    bk = -1;
+    bx = n + 1;
+    for (int32_t k0 = lo; k0 <= hi; k0 += kBatch * step) {
+        int32_t xs[kBatch], vs[kBatch];
+#pragma unroll
+        for (int t = 0; t < kBatch; ++t) {
+            const int32_t k = k0 + t * step;
+            xs[t] = (k <= hi) ? urow[k] : 0x7fffffff;
+        }
+#pragma unroll
+        for (int t = 0; t < kBatch; ++t) {
+            const int32_t k = k0 + t * step;
+            const int32_t x = xs[t];
+            const bool want = (k <= hi) && x >= xa && x <= xb && !(best <= n && x - k >= best - j);
+            vs[t] = want ? L[(size_t)x * ldL + (j - k)] : 0x7fffffff;
+        }
+        bool stop = false;
+#pragma unroll
+        for (int t = 0; t < kBatch; ++t) {
+            const int32_t k = k0 + t * step;
+            const int32_t x = xs[t];
+            if (!stop && x >= xa) {
+                if (k > hi || x > xb || (best <= n && x - k >= best - j)) {
+                    stop = true;
+                } else if (vs[t] < best) {
+                    best = vs[t];
+                    bk = k;
+                    bx = x;
+                    if (best == vlo) stop = true;
+                }
+            }
+        }
+        if (stop) break;
+    }
+    if (best > n) {
+        best = n + 1;
+        bk = -1;
+        bx = n + 1;
+    }
+}
+
+// One batch of scan_candidates for a unit-step scan starting at k0: returns
+// true when the scan is finished (exit taken or window exhausted); otherwise
+// the caller resumes at k0 + kBatch with the same best/bk/bx.
+__device__ __forceinline__ bool scan_batch(const int32_t *__restrict__ urow,
+                                           const int32_t *__restrict__ L, int32_t ldL, int32_t j,
+                                           int32_t k0, int32_t hi, int32_t xa, int32_t xb,
+                                           int32_t vlo, int32_t n, int32_t &best, int32_t &bk,
+                                           int32_t &bx) {
+    int32_t xs[kBatch], vs[kBatch];
+#pragma unroll
+    for (int t = 0; t < kBatch; ++t) xs[t] = (k0 + t <= hi) ? urow[k0 + t] : 0x7fffffff;
+#pragma unroll
+    for (int t = 0; t < kBatch; ++t) {
+        const int32_t k = k0 + t, x = xs[t];
+        const bool want = (k <= hi) && x >= xa && x <= xb && !(best <= n && x - k >= best - j);
+        vs[t] = want ? L[(uint32_t)x * (uint32_t)ldL + (uint32_t)(j - k)] : 0x7fffffff;
+    }
+    bool stop = false;
+#pragma unroll
+    for (int t = 0; t < kBatch; ++t) {
+        const int32_t k = k0 + t, x = xs[t];
+        if (!stop && x >= xa) {
+            if (k > hi || x > xb || (best <= n && x - k >= best - j)) {
+                stop = true;
+            } else if (vs[t] < best) {
+                best = vs[t];
+                bk = k;
+                bx = x;
+                if (best == vlo) stop = true;
+            }
+        }
+    }
+    return stop || k0 + kBatch > hi;
+}
+
+// ---------------------------------------------------------------------------
 // Combine, anchor vertex (Alg. 1 with Alg. 2's tie rule).  For the vertex
 // `vtx` of parent G = U (+) L, every column j of D_G(vtx, .) is
 //     min over k of D_L(D_U(vtx, k), j - k),  max(0, j-hL) <= k <= min(j, hU)
@@ -207,17 +304,8 @@ __device__ void anchor_block(const int32_t *__restrict__ U, int32_t hU,
                 if (!dead) {
                     const int32_t lo = imax(kl, imax(c - hL, 0));
                     const int32_t hi = imin(kr, imin(c, hU));
-                    int32_t best = INF + 1, bk = -1;
-                    for (int32_t k = lo + gl; k <= hi; k += g) {
-                        const int32_t x = urow[k];
-                        if (x > n) break;
-                        if (best <= n && x - k >= best - c) break;
-                        const int32_t v = L[(size_t)x * ldL + (c - k)];
-                        if (v < best) {
-                            best = v;
-                            bk = k;
-                        }
-                    }
+                    int32_t best, bk, bx;
+                    scan_candidates(urow, L, ldL, c, lo + gl, hi, g, 0, n, -1, n, best, bk, bx);
                     if (best <= n) key = ((unsigned long long)(uint32_t)best << 32) | (uint32_t)bk;
                 }
             }
@@ -256,15 +344,49 @@ __device__ void anchor_block(const int32_t *__restrict__ U, int32_t hU,
 // If D_G(ia, j) is unreachable so is D_G(i, j); if only D_G(ib, j) is, the
 // upper bound falls back to min(j, hU).
 //
-// One block solves tile vertices i0..i0+len (both ends already solved, e.g.
-// anchors) for weights j0..j0+jn-1, bisecting the tile (vertex len/2 first,
-// then the quarter points, ...).  Per-vertex state (k*, x*, value) for the
-// block's weights lives in LDS; values reach D_G in contiguous row segments.
+// One block solves tile vertices i0..i0+len (both ends already solved) for
+// weights j0..j0+jn-1, bisecting the tile (vertex len/2 first, then the
+// quarter points, ...).  Per-vertex state (k*, x*, value) for the block's
+// weights lives in LDS; values reach D_G in contiguous row segments.
+// SIMD efficiency: within a bisection level every output first runs exactly
+// one batch of candidates; the few that are not finished are queued in LDS and
+// completed by all threads together, so a wave never waits for its slowest lane
+// during the common case.
 struct BracketSmem {
     int32_t k[(kMaxTile + 1) * (kJChunk + 1)];
     int32_t x[(kMaxTile + 1) * (kJChunk + 1)];
     int32_t v[(kMaxTile + 1) * (kJChunk + 1)];
+    int32_t nk[(kMaxTile + 1) * (kJChunk + 1)];  // resume point of a queued output
+    int32_t q[(kMaxTile + 1) * (kJChunk + 1)];   // queued outputs (slot * S + jj)
+    int32_t qn;
 };
+
+struct BracketWindow {
+    int32_t lo, hi, xa, xb, vlo;
+    bool dead;
+};
+
+__device__ __forceinline__ BracketWindow bracket_window(const BracketSmem &sm, int32_t v,
+                                                        int32_t va, int32_t vb, int32_t jj,
+                                                        int32_t j, int32_t hU, int32_t hL,
+                                                        int32_t n) {
+    constexpr int32_t S = kJChunk + 1;
+    BracketWindow w;
+    const int32_t ka = sm.k[va * S + jj];
+    w.dead = ka < 0;
+    const int32_t kb = sm.k[vb * S + jj];
+    if (kb >= 0) {
+        w.hi = imin(kb + (vb - v), imin(j, hU));
+        w.xb = sm.x[vb * S + jj];
+    } else {
+        w.hi = imin(j, hU);
+        w.xb = n;
+    }
+    w.lo = imax(ka - (v - va), imax(j - hL, 0));
+    w.xa = sm.x[va * S + jj];
+    w.vlo = sm.v[va * S + jj];
+    return w;
+}
 
 __device__ void bracket_block(const int32_t *__restrict__ U, int32_t hU,
                               const int32_t *__restrict__ L, int32_t hL, int32_t *__restrict__ G,
@@ -272,80 +394,90 @@ __device__ void bracket_block(const int32_t *__restrict__ U, int32_t hU,
                               const int32_t *__restrict__ Ka, const int32_t *__restrict__ Kb,
                               BracketSmem &sm) {
     if (len < 2 || jn <= 0) return;
+    constexpr int32_t S = kJChunk + 1;  // LDS row stride (weights)
+    constexpr int32_t kHalf = 32;       // threads per vertex in a pass
     const int32_t INF = n + 1;
     const int32_t H = hU + hL + 1;
     const int32_t ldU = hU + 1, ldL = hL + 1;
-    const int32_t S = kJChunk + 1;  // LDS row stride (weights)
-    const int lane = __lane_id();
-    const int w = threadIdx.x / kWave;
+    const int32_t hl = threadIdx.x & (kHalf - 1);
+    const int32_t grp = threadIdx.x / kHalf;
+    constexpr int32_t ngrp = kBlock / kHalf;
     // the two solved ends of the tile
-    for (int32_t e = threadIdx.x; e < 2 * jn; e += kBlock) {
-        const int32_t side = e / jn, jj = e - side * jn;
+    for (int32_t side = 0; side < 2; ++side) {
         const int32_t slot = side ? len : 0;
         const int32_t vert = i0 + slot;
-        const int32_t k = (side ? Kb : Ka)[j0 + jj];
-        sm.k[slot * S + jj] = k;
-        sm.v[slot * S + jj] = G[(size_t)vert * H + j0 + jj];
-        sm.x[slot * S + jj] = (k >= 0) ? U[(size_t)vert * ldU + k] : INF;
+        const int32_t *K = side ? Kb : Ka;
+        for (int32_t jj = threadIdx.x; jj < jn; jj += kBlock) {
+            const int32_t k = K[j0 + jj];
+            sm.k[slot * S + jj] = k;
+            sm.v[slot * S + jj] = G[(size_t)vert * H + j0 + jj];
+            sm.x[slot * S + jj] = (k >= 0) ? U[(size_t)vert * ldU + k] : INF;
+        }
     }
+    if (threadIdx.x == 0) sm.qn = 0;
     __syncthreads();
     int32_t P2 = 1;
     while (P2 < len) P2 <<= 1;
     for (int32_t st = P2; st >= 2; st >>= 1) {
         const int32_t half = st >> 1;
         const int32_t nv = (len > half) ? (len - half + st - 1) / st : 0;
-        for (int32_t t = w; t < nv; t += kWaves) {
+        // pass 1: one batch per output
+        for (int32_t t = grp; t < nv; t += ngrp) {
             const int32_t v = half + t * st;
-            const int32_t va = v - half;
-            const int32_t vb = imin(v + half, len);
-            const int32_t i = i0 + v;
-            const int32_t *__restrict__ urow = U + (size_t)i * ldU;
-            for (int32_t jj = lane; jj < jn; jj += kWave) {
+            const int32_t va = v - half, vb = imin(v + half, len);
+            const int32_t *__restrict__ urow = U + (size_t)(i0 + v) * ldU;
+            for (int32_t jj = hl; jj < jn; jj += kHalf) {
                 const int32_t j = j0 + jj;
-                const int32_t ka = sm.k[va * S + jj];
-                int32_t best = INF + 1, bk = -1, bx = INF;
-                if (ka >= 0) {
-                    const int32_t xa = sm.x[va * S + jj];
-                    const int32_t vlo = sm.v[va * S + jj];
-                    const int32_t kb = sm.k[vb * S + jj];
-                    int32_t hi, xb;
-                    if (kb >= 0) {
-                        hi = imin(kb + (vb - v), imin(j, hU));
-                        xb = sm.x[vb * S + jj];
-                    } else {
-                        hi = imin(j, hU);
-                        xb = n;
-                    }
-                    const int32_t lo = imax(ka - (v - va), imax(j - hL, 0));
-                    for (int32_t k = lo; k <= hi; ++k) {
-                        const int32_t x = urow[k];
-                        if (x < xa) continue;
-                        if (x > xb) break;
-                        if (best <= n && x - k >= best - j) break;
-                        const int32_t val = L[(size_t)x * ldL + (j - k)];
-                        if (val < best) {
-                            best = val;
-                            bk = k;
-                            bx = x;
-                            if (val == vlo) break;
-                        }
-                    }
+                const BracketWindow w = bracket_window(sm, v, va, vb, jj, j, hU, hL, n);
+                int32_t best = n + 2, bk = -1, bx = INF;
+                bool done = w.dead;
+                if (!done) done = scan_batch(urow, L, ldL, j, w.lo, w.hi, w.xa, w.xb, w.vlo, n, best, bk, bx);
+                const int32_t id = v * S + jj;
+                sm.k[id] = bk;
+                sm.x[id] = bx;
+                sm.v[id] = best;
+                if (!done) {
+                    sm.nk[id] = w.lo + kBatch;
+                    sm.q[atomicAdd(&sm.qn, 1)] = id;
                 }
-                if (best > n) {
-                    best = INF;
-                    bk = -1;
-                    bx = INF;
-                }
-                sm.k[v * S + jj] = bk;
-                sm.x[v * S + jj] = bx;
-                sm.v[v * S + jj] = best;
             }
         }
         __syncthreads();
+        // pass 2: the queued outputs, one per thread
+        const int32_t qn = sm.qn;
+        for (int32_t e = threadIdx.x; e < qn; e += kBlock) {
+            const int32_t id = sm.q[e];
+            const int32_t v = id / S, jj = id - v * S;
+            const int32_t va = v - half, vb = imin(v + half, len);
+            const int32_t j = j0 + jj;
+            const BracketWindow w = bracket_window(sm, v, va, vb, jj, j, hU, hL, n);
+            const int32_t *__restrict__ urow = U + (size_t)(i0 + v) * ldU;
+            int32_t best = sm.v[id], bk = sm.k[id], bx = sm.x[id];
+            for (int32_t k0 = sm.nk[id];; k0 += kBatch)
+                if (scan_batch(urow, L, ldL, j, k0, w.hi, w.xa, w.xb, w.vlo, n, best, bk, bx)) break;
+            sm.k[id] = bk;
+            sm.x[id] = bx;
+            sm.v[id] = best;
+        }
+        __syncthreads();
+        // normalise unreachable results
+        for (int32_t t = grp; t < nv; t += ngrp) {
+            const int32_t v = half + t * st;
+            for (int32_t jj = hl; jj < jn; jj += kHalf) {
+                const int32_t id = v * S + jj;
+                if (sm.v[id] > n) {
+                    sm.v[id] = INF;
+                    sm.k[id] = -1;
+                    sm.x[id] = INF;
+                }
+            }
+        }
+        if (threadIdx.x == 0) sm.qn = 0;
+        __syncthreads();
     }
-    for (int32_t t = w + 1; t < len; t += kWaves) {
+    for (int32_t t = 1 + grp; t < len; t += ngrp) {
         int32_t *grow = G + (size_t)(i0 + t) * H + j0;
-        for (int32_t jj = lane; jj < jn; jj += kWave) grow[jj] = sm.v[t * S + jj];
+        for (int32_t jj = hl; jj < jn; jj += kHalf) grow[jj] = sm.v[t * S + jj];
     }
     __syncthreads();
 }

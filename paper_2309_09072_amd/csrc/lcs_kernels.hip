@@ -135,16 +135,16 @@ hipError_t launch_base(int32_t h0, const uint8_t *a, int32_t n, int32_t sigma, c
     return hipGetLastError();
 }
 
-hipError_t launch_combine(const CombineArgs &c, int32_t npairs, hipStream_t s) {
+hipError_t launch_anchor(const CombineArgs &c, int32_t npairs, hipStream_t s) {
     hipLaunchKernelGGL(k_anchor, dim3(c.nanch, npairs), dim3(kBlock), 0, s, c);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    return hipGetLastError();
+}
+
+hipError_t launch_bracket(const CombineArgs &c, int32_t npairs, hipStream_t s) {
     const int32_t ntiles = (c.n + c.tile - 1) / c.tile;
-    if (ntiles > 0) {
-        hipLaunchKernelGGL(k_bracket, dim3(ntiles * c.nchunks, npairs), dim3(kBlock), 0, s, c);
-        e = hipGetLastError();
-    }
-    return e;
+    if (ntiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bracket, dim3(ntiles * c.nchunks, npairs), dim3(kBlock), 0, s, c);
+    return hipGetLastError();
 }
 
 hipError_t launch_length(const int32_t *top, int32_t m, int32_t n, int32_t *hdr, int4 *root,

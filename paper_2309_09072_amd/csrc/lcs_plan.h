@@ -12,7 +12,7 @@
 namespace lcs {
 
 constexpr int32_t kDefaultBaseRows = 64;
-constexpr int32_t kDefaultTile = 64;
+constexpr int32_t kDefaultTile = 32;
 constexpr int32_t kHeaderWords = 64;  // hdr[0] error bits, hdr[1] L, hdr[2] end column
 
 struct Layout {
@@ -26,7 +26,7 @@ struct Layout {
 inline int64_t align256(int64_t x) { return (x + 255) & ~(int64_t)255; }
 
 // Workspace layout for one pair of sizes (m, n).  Returns false when a strip
-// matrix would have 2^31 or more cells.
+// matrix would have 2^30 or more cells.
 inline bool make_layout(int32_t m, int32_t n, int32_t sigma, int32_t h0, int32_t tile, Layout &L) {
     L = Layout();
     L.m = m;
@@ -34,7 +34,8 @@ inline bool make_layout(int32_t m, int32_t n, int32_t sigma, int32_t h0, int32_t
     L.sigma = sigma;
     L.h0 = h0;
     L.tile = tile;
-    if ((int64_t)(n + 2) * (int64_t)(m + 1) >= ((int64_t)1 << 31)) return false;
+    // every matrix has fewer than 2^30 cells, so a byte offset inside one fits in 32 bits
+    if ((int64_t)(n + 2) * (int64_t)(m + 1) >= ((int64_t)1 << 30)) return false;
     int64_t off = 0;
     L.off_hdr = off;
     off += 4 * kHeaderWords;
@@ -107,7 +108,7 @@ inline CombineArgs combine_args(const Layout &L, uint8_t *ws, size_t l) {
     a.nanch = L.nanch;
     a.hs = 2 * c.hfull + 1;
     a.anch = reinterpret_cast<int32_t *>(ws + L.off_anch);
-    a.jchunk = 64;
+    a.jchunk = 32;
     const int32_t H = 2 * c.hfull + 1;
     a.nchunks = (H - 1 + a.jchunk - 1) / a.jchunk;
     if (a.nchunks < 1) a.nchunks = 1;

@@ -54,6 +54,16 @@ class ServerDesc(ctypes.Structure):
                 ("flags", ctypes.c_uint32)]
 
 
+class PhaseTime(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("level", ctypes.c_int32), ("ms", ctypes.c_float),
+                ("bytes", ctypes.c_int64)]
+
+
+PHASES = {0: "nextmatch", 1: "base", 2: "anchor", 3: "bracket", 4: "length", 5: "trace_split",
+          6: "trace_leaf"}
+PLAN_PROFILE = 1
+
+
 class Result(ctypes.Structure):
     _fields_ = [("tag", ctypes.c_int64), ("status", ctypes.c_int32), ("length", ctypes.c_int32),
                 ("wit_off", ctypes.c_int64), ("t_submit", ctypes.c_double),
@@ -79,6 +89,8 @@ PROTOTYPES = {
     "lcs_length": (_I32, [_P, _PI32, _P]),
     "lcs_length_device": (_I32, [_P, _P, _P]),
     "lcs_trace": (_I32, [_P, _P, _P, _I32, _PI32, _P]),
+    "lcs_trace_device": (_I32, [_P, _P, _P, _I32, _P, _P]),
+    "lcs_plan_profile": (_I32, [_P, _P, _I32, _PI32]),
     "lcs_plan_levels": (_I32, [_P, _PI32, _PI32]),
     "lcs_dist_view": (_I32, [_P, _I32, _I32, ctypes.POINTER(_P), _PI32, _PI32, _PI32]),
     "lcs_batch_plan": (_I32, [ctypes.POINTER(BatchDesc), ctypes.POINTER(_P), _PSZ]),
@@ -167,9 +179,11 @@ def alloc_workspace(nbytes: int, device="cuda"):
 class Plan:
     """One planned strip recursion (lcs_plan); reusable for any m <= max_m, n <= max_n."""
 
-    def __init__(self, max_m: int, max_n: int, alphabet: int, base_rows: int = 0, tile: int = 0):
+    def __init__(self, max_m: int, max_n: int, alphabet: int, base_rows: int = 0, tile: int = 0,
+                 profile: bool = False):
         lib = load()
-        self.desc = PlanDesc(int(max_m), int(max_n), int(alphabet), int(base_rows), int(tile), 0)
+        self.desc = PlanDesc(int(max_m), int(max_n), int(alphabet), int(base_rows), int(tile),
+                             PLAN_PROFILE if profile else 0)
         h = ctypes.c_void_p()
         ws = ctypes.c_size_t()
         check(lib.lcs_plan(ctypes.byref(self.desc), ctypes.byref(h), ctypes.byref(ws)), "lcs_plan")
@@ -203,6 +217,23 @@ class Plan:
         check(load().lcs_trace(self._h, _dptr(a_idx), _dptr(b_idx), cap, ctypes.byref(out),
                                stream_handle(stream)), "lcs_trace")
         return int(out.value)
+
+    def trace_device(self, a_idx, b_idx, length_dev, stream=None) -> None:
+        """Enqueue the witness trace without synchronising; L goes to length_dev (int32[1])."""
+        cap = min(int(a_idx.numel()), int(b_idx.numel()))
+        check(load().lcs_trace_device(self._h, _dptr(a_idx), _dptr(b_idx), cap, _dptr(length_dev),
+                                      stream_handle(stream)), "lcs_trace_device")
+
+    def profile(self):
+        """Per-launch records since the last read: list of (phase, level, ms, bytes)."""
+        lib = load()
+        cnt = ctypes.c_int32()
+        check(lib.lcs_plan_profile(self._h, None, 0, ctypes.byref(cnt)), "lcs_plan_profile")
+        arr = (PhaseTime * max(cnt.value, 1))()
+        check(lib.lcs_plan_profile(self._h, ctypes.cast(arr, ctypes.c_void_p), cnt.value,
+                                   ctypes.byref(cnt)), "lcs_plan_profile")
+        return [(PHASES.get(arr[i].kind, str(arr[i].kind)), int(arr[i].level), float(arr[i].ms),
+                 int(arr[i].bytes)) for i in range(cnt.value)]
 
     def levels(self):
         nl = ctypes.c_int32()

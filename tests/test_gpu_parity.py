@@ -66,7 +66,7 @@ def check_against_oracle(a, b, sigma, **kw):
 # ----------------------------------------------------------------- small, full D
 
 
-@pytest.mark.parametrize("base_rows,tile", [(16, 4), (16, 8), (32, 16), (64, 64), (16, 64)])
+@pytest.mark.parametrize("base_rows,tile", [(16, 4), (16, 8), (32, 16), (64, 32), (16, 32)])
 def test_levels_cell_for_cell(base_rows, tile):
     r = np.random.default_rng(100 + base_rows + tile)
     shapes = [(200, 150, 4), (129, 203, 2), (97, 64, 20), (65, 257, 4), (16, 31, 1), (250, 9, 3)]
@@ -109,7 +109,7 @@ def test_random_shapes_length_and_witness():
         if case % 5 == 0:
             m = int(r.integers(0, 70))
         base_rows = int(r.choice([16, 32, 64]))
-        tile = int(r.choice([4, 16, 32, 64]))
+        tile = int(r.choice([4, 8, 16, 32]))
         a = r.integers(0, sig, m).astype(np.uint8)
         if case % 3 == 0 and m > 0:
             b = synth.fit_length(r, synth.mutate(r, a, sig, 0.1, 0.05, 0.05), max(n, 1), sig)
