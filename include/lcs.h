@@ -241,7 +241,9 @@ int32_t lcs_batch_destroy(lcs_batch_t batch);
  *              when witness_capacity is 0.
  *   mode       LCS_BATCH_PERSISTENT or LCS_BATCH_PER_PAIR, optionally OR
  *              LCS_BATCH_GRAPH.
- * Asynchronous on `stream`.  Errors: LCS_E_INVAL, LCS_E_TOO_BIG,
+ * Asynchronous on `stream`.  Submits of one batch handle must not overlap:
+ * the call waits until the previous submit has consumed its staged pair
+ * records.  Errors: LCS_E_INVAL, LCS_E_TOO_BIG,
  * LCS_E_WORKSPACE, LCS_E_CAPACITY, LCS_E_NOMEM, LCS_E_HIP.  A bad symbol sets
  * the length of its pair to LCS_E_SYMBOL.
  */
@@ -249,6 +251,13 @@ int32_t lcs_batch_submit(lcs_batch_t batch, const lcs_pair_desc *pairs, int32_t 
                          const uint8_t *symbols, int64_t symbols_len, int32_t *lengths,
                          int32_t *a_idx, int32_t *b_idx, int64_t witness_capacity,
                          void *workspace, size_t workspace_bytes, uint32_t mode, void *stream);
+
+/*
+ * Outcome of the last persistent submit on `workspace`: LCS_OK, or LCS_E_HIP
+ * if a work-group gave up waiting for a task it depends on (a bounded wait
+ * that only a library defect can exhaust).  Synchronises the stream.
+ */
+int32_t lcs_batch_status(lcs_batch_t batch, void *workspace, void *stream);
 
 /* ============================================================== serving */
 

@@ -1,0 +1,624 @@
+// Batches of string pairs (lcs_batch_plan / lcs_batch_submit).
+//
+// LCS_BATCH_PER_PAIR runs the per-level kernels of the single-pair path pair
+// after pair on one stream (the one-pair-per-launch baseline).
+//
+// LCS_BATCH_PERSISTENT runs the whole batch -- every pair's next-match tables,
+// base strips, combine levels, length and witness trace -- in ONE launch of a
+// persistent kernel: as many work-groups as fit on the device at once pop task
+// indices from a device counter in increasing order.  Tasks are numbered pair
+// by pair in dependency order, and every task waits (bounded spin) only on
+// counters raised by tasks with smaller numbers, which were popped earlier by
+// running work-groups; so the queue always drains.  Pair p uses workspace slot
+// p mod slots, and its first task also waits until pair p - slots has finished
+// its trace, which bounds the memory of a batch of any size.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "lcs.h"
+#include "lcs_device.h"
+#include "lcs_launch.h"
+#include "lcs_plan.h"
+#include "lcs_sched.h"
+
+namespace lcs {
+
+bool valid_shape(int32_t base_rows, int32_t tile);
+int32_t resolve(int32_t v, int32_t dflt);
+struct Recorder;
+int32_t enqueue_build(const Layout &L, uint8_t *ws, const uint8_t *a, const uint8_t *b,
+                      hipStream_t s, Recorder *rec);
+int32_t enqueue_trace(const Layout &L, uint8_t *ws, const uint8_t *a, int32_t *a_idx,
+                      int32_t *b_idx, hipStream_t s, Recorder *rec);
+
+struct BatchArgs {
+    const PairRec *pairs;
+    int32_t npairs;
+    int32_t slots;
+    int64_t ntasks;
+    uint8_t *ws;
+    const uint8_t *symbols;
+    int32_t *lengths;
+    int32_t *a_idx;
+    int32_t *b_idx;
+    int32_t *ctr;          // all pair counters
+    unsigned long long *next;  // task dispenser
+    int32_t *gerr;         // bit 0: a dependency wait timed out
+    int32_t sigma;
+    int32_t tile;
+};
+
+constexpr uint32_t kSpinLimit = 1u << 22;  // ~ seconds: a dependency bug ends as an error, not a hang
+
+__device__ __forceinline__ int32_t ld_acq(const int32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// thread 0 only; false when the bounded wait ran out
+__device__ bool wait_ge(const int32_t *p, int32_t target, int32_t *gerr) {
+    uint32_t spins = 0;
+    while (ld_acq(p) < target) {
+        __builtin_amdgcn_s_sleep(4);
+        if (++spins > kSpinLimit) {
+            atomicOr(gerr, 1);
+            return false;
+        }
+    }
+    return true;
+}
+
+__device__ __forceinline__ void signal(int32_t *p) {
+    __threadfence();
+    __hip_atomic_fetch_add(p, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ CombineArgs pair_combine_args(const PairRec &P, uint8_t *ws, int32_t l,
+                                                         int32_t tile) {
+    const LevelGeom &c = P.lev[l - 1], &p = P.lev[l];
+    CombineArgs a;
+    a.cbase = reinterpret_cast<const int32_t *>(ws + c.base);
+    a.clast = reinterpret_cast<const int32_t *>(ws + c.last_off);
+    a.hc = c.hfull;
+    a.hclast = c.hlast;
+    a.nc = c.nstrips;
+    a.pbase = reinterpret_cast<int32_t *>(ws + p.base);
+    a.plast = reinterpret_cast<int32_t *>(ws + p.last_off);
+    a.np = p.nstrips;
+    a.n = P.n;
+    a.tile = tile;
+    a.nanch = P.nanch;
+    a.hs = 2 * c.hfull + 1;
+    a.anch = reinterpret_cast<int32_t *>(ws + P.off_anch);
+    a.jchunk = kJChunk;
+    a.nchunks = 0;
+    return a;
+}
+
+union PersistentSmem {
+    int32_t nm[kWaves];
+    int32_t base[kWave * 65];
+    unsigned long long anchor[kBlock];
+    BracketSmem bracket;
+    int32_t len[1];
+    int32_t split[1];
+    int32_t leaf[65 * 65];
+};
+
+template <int H0>
+__global__ void __launch_bounds__(kBlock) k_persistent(BatchArgs A) {
+    __shared__ PersistentSmem sm;
+    __shared__ Task s_task;
+    __shared__ int32_t s_ok;
+    for (;;) {
+        if (threadIdx.x == 0) {
+            const long long t = (long long)atomicAdd(A.next, 1ull);
+            s_task.kind = -1;
+            if (t < A.ntasks) {
+                s_task = decode_task(A.pairs, A.npairs, A.slots, t);
+                // wait for the inputs (bounded); on a timeout the task is skipped
+                int32_t ok = 1;
+                for (int32_t w = 0; w < s_task.nwait; ++w)
+                    ok &= wait_ge(A.ctr + s_task.wait_idx[w], s_task.wait_tgt[w], A.gerr);
+                s_ok = ok;
+            }
+        }
+        __syncthreads();
+        const int32_t kind = s_task.kind;
+        if (kind < 0) break;
+        const int32_t p = s_task.pair, l = s_task.level, u = s_task.u;
+        const PairRec &P = A.pairs[p];
+        uint8_t *ws = A.ws + P.ws_off;
+        int32_t *hdr = reinterpret_cast<int32_t *>(ws + P.off_hdr);
+        int32_t *nm = reinterpret_cast<int32_t *>(ws + P.off_nm);
+        const uint8_t *a = A.symbols + P.a_off;
+        const uint8_t *b = A.symbols + P.b_off;
+        if (s_ok) switch (kind) {
+            case ST_EMPTY:
+                if (threadIdx.x == 0) A.lengths[p] = 0;
+                break;
+            case ST_NM:
+                for (int32_t i = threadIdx.x; i < kHeaderWords; i += kBlock) hdr[i] = 0;
+                for (int32_t x = 0; x < A.sigma; ++x)
+                    nextmatch_block(b, P.n, x, nm + (size_t)x * (size_t)(P.n + 2), sm.nm);
+                break;
+            case ST_BASE: {
+                const LevelGeom &g = P.lev[0];
+                const bool last = (u == g.nstrips - 1);
+                const int32_t h = last ? g.hlast : H0;
+                int32_t *out = reinterpret_cast<int32_t *>(ws + (last ? g.last_off : g.base)) +
+                               (last ? 0 : (size_t)u * strip_elems(P.n, H0));
+                for (int32_t v0 = 0; v0 < P.n + 2; v0 += kBlock)
+                    base_strip_block<H0>(a + (size_t)u * H0, h, P.n, A.sigma, nm, out, v0, hdr, sm.base);
+                break;
+            }
+            case ST_ANCHOR: {
+                const CombineArgs c = pair_combine_args(P, ws, l, A.tile);
+                const int32_t q = u / P.nanch, an = u - q * P.nanch;
+                const StripRef U = child_strip(c, 2 * q), L = child_strip(c, 2 * q + 1);
+                int32_t *G = parent_strip(c, q);
+                anchor_block(U.d, U.h, L.d, L.h, G, P.n, anchor_vertex(an, A.tile, P.n),
+                             c.anch + ((size_t)q * c.nanch + an) * (size_t)c.hs, sm.anchor);
+                if (an == c.nanch - 1) {
+                    const int32_t H = U.h + L.h + 1;
+                    int32_t *srow = G + (size_t)(P.n + 1) * H;
+                    for (int32_t j = threadIdx.x; j < H; j += kBlock) srow[j] = P.n + 1;
+                }
+                break;
+            }
+            case ST_BRACKET: {
+                const CombineArgs c = pair_combine_args(P, ws, l, A.tile);
+                const int32_t ntile = P.nanch - 1;
+                const int32_t q = u / ntile, tl = u - q * ntile;
+                const StripRef U = child_strip(c, 2 * q), L = child_strip(c, 2 * q + 1);
+                int32_t *G = parent_strip(c, q);
+                const int32_t H = U.h + L.h + 1;
+                const int32_t nch = imax(1, (H - 1 + kJChunk - 1) / kJChunk);
+                const int32_t i0 = tl * A.tile;
+                const int32_t len = imin(A.tile, P.n - i0);
+                const int32_t *Ka = c.anch + ((size_t)q * c.nanch + tl) * (size_t)c.hs;
+                const int32_t *Kb = c.anch + ((size_t)q * c.nanch + tl + 1) * (size_t)c.hs;
+                for (int32_t ch = 0; ch < nch; ++ch) {
+                    const int32_t j0 = ch * kJChunk;
+                    const int32_t jn = (ch == nch - 1) ? H - j0 : kJChunk;
+                    bracket_block(U.d, U.h, L.d, L.h, G, P.n, i0, len, j0, jn, Ka, Kb, sm.bracket);
+                }
+                break;
+            }
+            case ST_LENGTH: {
+                const LevelGeom &top = P.lev[P.nlev - 1];
+                length_block(reinterpret_cast<const int32_t *>(ws + top.last_off), P.m, P.n, hdr,
+                             reinterpret_cast<int4 *>(ws + P.node_off[P.nlev - 1]), sm.len);
+                if (threadIdx.x == 0) A.lengths[p] = (hdr[0] & kErrSymbol) ? LCS_E_SYMBOL : hdr[1];
+                break;
+            }
+            case ST_SPLIT: {
+                const CombineArgs c = pair_combine_args(P, ws, l, A.tile);
+                const int4 *nin = reinterpret_cast<const int4 *>(ws + P.node_off[l]);
+                int4 *nout = reinterpret_cast<int4 *>(ws + P.node_off[l - 1]);
+                const int4 node = nin[u];
+                if (2 * u + 1 >= c.nc) {
+                    if (threadIdx.x == 0) nout[2 * u] = node;
+                } else {
+                    const StripRef U = child_strip(c, 2 * u), L = child_strip(c, 2 * u + 1);
+                    trace_split_block(U.d, U.h, L.d, L.h, P.n, node, nout + 2 * u, nout + 2 * u + 1,
+                                      hdr, sm.split);
+                }
+                break;
+            }
+            case ST_LEAF: {
+                const LevelGeom &g = P.lev[0];
+                const int32_t h = (u == g.nstrips - 1) ? g.hlast : H0;
+                const int4 *nodes = reinterpret_cast<const int4 *>(ws + P.node_off[0]);
+                trace_leaf_block<H0>(a + (size_t)u * H0, h, P.n, A.sigma, nm, nodes[u], u * H0,
+                                     A.a_idx + P.wit_off, A.b_idx + P.wit_off,
+                                     P.m < P.n ? P.m : P.n, hdr, sm.leaf);
+                break;
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x == 0)
+            for (int32_t i = 0; i < s_task.nsig; ++i) signal(A.ctr + s_task.sig_idx[i]);
+        __syncthreads();
+    }
+}
+
+__global__ void k_fill(int32_t *p, int64_t count, int32_t value) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = value;
+}
+
+__global__ void k_finish_pair(const int32_t *hdr, int32_t *len_out) {
+    if (threadIdx.x == 0) *len_out = (hdr[0] & kErrSymbol) ? LCS_E_SYMBOL : hdr[1];
+}
+
+}  // namespace lcs
+
+using namespace lcs;
+
+struct lcs_batch_s {
+    lcs_batch_desc d{};
+    int64_t slot_bytes = 0;
+    int32_t ctr_per_pair = 0;
+    int64_t off_ctl = 0, off_pairs = 0, off_ctr = 0, off_slots = 0, total = 0;
+    PairRec *host_pairs = nullptr;  // pinned staging of the pair records
+    int32_t resident = 0;           // work-groups of the persistent kernel that fit at once
+    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr;
+    uint64_t gkey = 0;
+    hipEvent_t copied = nullptr;    // the last copy out of host_pairs has run
+};
+
+static int32_t counters_per_pair(int32_t max_len, int32_t h0) {
+    // 2 + 3 * sum over levels of the strip count
+    int32_t s = (max_len + h0 - 1) / h0, tot = 0;
+    if (s < 1) s = 1;
+    for (;;) {
+        tot += s;
+        if (s == 1) break;
+        s = (s + 1) / 2;
+    }
+    return kCtrHead + 3 * tot;
+}
+
+// Sizes of a batch plan (no device calls).
+static int32_t plan_sizes(const lcs_batch_desc *desc, lcs_batch_s *b) {
+    lcs_batch_desc d = *desc;
+    d.base_rows = resolve(d.base_rows, kDefaultBaseRows);
+    d.tile = resolve(d.tile, kDefaultTile);
+    if (d.max_pairs < 1 || d.max_len < 1 || d.alphabet < 1 || d.alphabet > 256 || d.flags != 0 ||
+        d.slots < 0)
+        return LCS_E_INVAL;
+    if (!valid_shape(d.base_rows, d.tile)) return LCS_E_INVAL;
+    if (d.slots == 0 || d.slots > d.max_pairs) d.slots = d.max_pairs;
+    Layout L;
+    if (!make_layout(d.max_len, d.max_len, d.alphabet, d.base_rows, d.tile, L)) return LCS_E_TOO_BIG;
+    if ((int32_t)L.lev.size() > kMaxLev) return LCS_E_TOO_BIG;
+    b->d = d;
+    b->slot_bytes = align256(L.total);
+    b->ctr_per_pair = counters_per_pair(d.max_len, d.base_rows);
+    int64_t off = 0;
+    b->off_ctl = off;
+    off += 256;
+    b->off_pairs = off;
+    off = align256(off + (int64_t)sizeof(PairRec) * d.max_pairs);
+    b->off_ctr = off;
+    off = align256(off + 4 * (int64_t)b->ctr_per_pair * d.max_pairs);
+    b->off_slots = off;
+    off += b->slot_bytes * d.slots;
+    b->total = off;
+    return LCS_OK;
+}
+
+extern "C" int32_t lcs_batch_plan(const lcs_batch_desc *desc, lcs_batch_t *out, size_t *ws_bytes) {
+    if (!desc || !out || !ws_bytes) return LCS_E_INVAL;
+    *out = nullptr;
+    lcs_batch_s *b = new (std::nothrow) lcs_batch_s();
+    if (!b) return LCS_E_NOMEM;
+    const int32_t rc = plan_sizes(desc, b);
+    if (rc != LCS_OK) {
+        delete b;
+        return rc;
+    }
+    if (hipHostMalloc(reinterpret_cast<void **>(&b->host_pairs), sizeof(PairRec) * b->d.max_pairs,
+                      hipHostMallocDefault) != hipSuccess) {
+        delete b;
+        return LCS_E_NOMEM;
+    }
+    int dev = 0, ncu = 0, per = 0;
+    hipGetDevice(&dev);
+    hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    hipError_t e = hipSuccess;
+    switch (b->d.base_rows) {
+        case 16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_persistent<16>, kBlock, 0); break;
+        case 32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_persistent<32>, kBlock, 0); break;
+        default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_persistent<64>, kBlock, 0); break;
+    }
+    if (e != hipSuccess || per < 1 || ncu < 1) {
+        hipHostFree(b->host_pairs);
+        delete b;
+        return LCS_E_HIP;
+    }
+    b->resident = per * ncu;
+    if (hipEventCreateWithFlags(&b->copied, hipEventDisableTiming) != hipSuccess) {
+        hipHostFree(b->host_pairs);
+        delete b;
+        return LCS_E_HIP;
+    }
+    *ws_bytes = (size_t)b->total;
+    *out = b;
+    return LCS_OK;
+}
+
+extern "C" int32_t lcs_batch_destroy(lcs_batch_t b) {
+    if (!b) return LCS_OK;
+    if (b->gexec) hipGraphExecDestroy(b->gexec);
+    if (b->graph) hipGraphDestroy(b->graph);
+    if (b->copied) {
+        hipEventSynchronize(b->copied);
+        hipEventDestroy(b->copied);
+    }
+    if (b->host_pairs) hipHostFree(b->host_pairs);
+    delete b;
+    return LCS_OK;
+}
+
+// Pair record: layout inside the slot, counters and task stages.
+static bool make_pair(const lcs_batch_s *B, const lcs_pair_desc &pd, int32_t p, int64_t wit_off,
+                      int64_t task_base, PairRec &R) {
+    memset(&R, 0, sizeof(R));
+    Layout L;
+    if (!make_layout(pd.m, pd.n, B->d.alphabet, B->d.base_rows, B->d.tile, L)) return false;
+    if ((int32_t)L.lev.size() > kMaxLev) return false;
+    R.ws_off = B->off_slots + (int64_t)(p % B->d.slots) * B->slot_bytes;
+    R.a_off = pd.a_off;
+    R.b_off = pd.b_off;
+    R.wit_off = wit_off;
+    R.task_base = task_base;
+    R.off_hdr = L.off_hdr;
+    R.off_nm = L.off_nm;
+    R.off_anch = L.off_anch;
+    R.total = L.total;
+    R.m = pd.m;
+    R.n = pd.n;
+    R.nlev = (int32_t)L.lev.size();
+    R.nanch = L.nanch;
+    R.ctr_base = p * B->ctr_per_pair;
+    int32_t c = kCtrHead;
+    for (int32_t l = 0; l < R.nlev; ++l) {
+        R.lev[l] = L.lev[l];
+        R.node_off[l] = L.node_off[l];
+        R.ctr_lev[l] = c;
+        c += 3 * L.lev[l].nstrips;
+    }
+    int32_t ns = 0, start = 0;
+    auto add = [&](int32_t kind, int32_t level, int32_t count) {
+        R.stage_kind[ns] = kind;
+        R.stage_level[ns] = level;
+        R.stage_start[ns] = start;
+        start += count;
+        ++ns;
+    };
+    if (R.nlev == 0) {
+        add(ST_EMPTY, 0, 1);
+    } else {
+        add(ST_NM, 0, 1);
+        add(ST_BASE, 0, L.lev[0].nstrips);
+        for (int32_t l = 1; l < R.nlev; ++l) {
+            add(ST_ANCHOR, l, L.lev[l].npairs * L.nanch);
+            add(ST_BRACKET, l, L.lev[l].npairs * (L.nanch - 1));
+        }
+        add(ST_LENGTH, R.nlev - 1, 1);
+        for (int32_t l = R.nlev - 1; l >= 1; --l) add(ST_SPLIT, l, L.lev[l].nstrips);
+        add(ST_LEAF, 0, L.lev[0].nstrips);
+    }
+    R.stage_start[ns] = start;
+    R.nstages = ns;
+    R.ntasks = start;
+    R.nctr = c;
+    return R.nctr <= B->ctr_per_pair && R.total <= B->slot_bytes;
+}
+
+static uint64_t mix(uint64_t h, uint64_t v) { return (h ^ v) * 0x100000001b3ull; }
+
+extern "C" int32_t lcs_batch_submit(lcs_batch_t B, const lcs_pair_desc *pairs, int32_t count,
+                                    const uint8_t *symbols, int64_t symbols_len, int32_t *lengths,
+                                    int32_t *a_idx, int32_t *b_idx, int64_t witness_capacity,
+                                    void *workspace, size_t workspace_bytes, uint32_t mode,
+                                    void *stream) {
+    if (!B || (count > 0 && (!pairs || !lengths)) || count < 0 || !workspace) return LCS_E_INVAL;
+    if (count > B->d.max_pairs) return LCS_E_TOO_BIG;
+    if ((mode & ~(uint32_t)(LCS_BATCH_PER_PAIR | LCS_BATCH_GRAPH)) != 0) return LCS_E_INVAL;
+    if ((size_t)B->total > workspace_bytes) return LCS_E_WORKSPACE;
+    if (reinterpret_cast<uintptr_t>(workspace) & 255) return LCS_E_INVAL;
+    int64_t wit = 0;
+    for (int32_t p = 0; p < count; ++p) {
+        const lcs_pair_desc &pd = pairs[p];
+        if (pd.m < 0 || pd.n < 0 || pd.a_off < 0 || pd.b_off < 0) return LCS_E_INVAL;
+        if (pd.m > B->d.max_len || pd.n > B->d.max_len) return LCS_E_TOO_BIG;
+        if (pd.a_off + pd.m > symbols_len || pd.b_off + pd.n > symbols_len) return LCS_E_INVAL;
+        wit += pd.m < pd.n ? pd.m : pd.n;
+    }
+    if (wit > witness_capacity) return LCS_E_CAPACITY;
+    if (wit > 0 && (!a_idx || !b_idx)) return LCS_E_INVAL;
+    if (count > 0 && !symbols) return LCS_E_INVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    uint8_t *ws = static_cast<uint8_t *>(workspace);
+    if (count == 0) return LCS_OK;
+
+    if (mode & LCS_BATCH_PER_PAIR) {
+        int64_t woff = 0;
+        for (int32_t p = 0; p < count; ++p) {
+            const lcs_pair_desc &pd = pairs[p];
+            Layout L;
+            if (!make_layout(pd.m, pd.n, B->d.alphabet, B->d.base_rows, B->d.tile, L)) return LCS_E_TOO_BIG;
+            uint8_t *slot = ws + B->off_slots + (int64_t)(p % B->d.slots) * B->slot_bytes;
+            int32_t rc = enqueue_build(L, slot, symbols + pd.a_off, symbols + pd.b_off, s, nullptr);
+            if (rc == LCS_OK)
+                rc = enqueue_trace(L, slot, symbols + pd.a_off, a_idx + woff, b_idx + woff, s, nullptr);
+            if (rc != LCS_OK) return rc;
+            hipLaunchKernelGGL(k_finish_pair, dim3(1), dim3(64), 0, s,
+                               reinterpret_cast<const int32_t *>(slot + L.off_hdr), lengths + p);
+            if (hipGetLastError() != hipSuccess) return LCS_E_HIP;
+            woff += pd.m < pd.n ? pd.m : pd.n;
+        }
+        return LCS_OK;
+    }
+
+    // persistent: pair records, counters, one launch.  The previous submit's
+    // copy of the staging records must have run before they are rewritten.
+    if (hipEventSynchronize(B->copied) != hipSuccess) return LCS_E_HIP;
+    int64_t woff = 0, tbase = 0;
+    uint64_t key = 0xcbf29ce484222325ull;
+    for (int32_t p = 0; p < count; ++p) {
+        if (!make_pair(B, pairs[p], p, woff, tbase, B->host_pairs[p])) return LCS_E_TOO_BIG;
+        woff += pairs[p].m < pairs[p].n ? pairs[p].m : pairs[p].n;
+        tbase += B->host_pairs[p].ntasks;
+    }
+    BatchArgs A;
+    A.pairs = reinterpret_cast<const PairRec *>(ws + B->off_pairs);
+    A.npairs = count;
+    A.slots = B->d.slots;
+    A.ntasks = tbase;
+    A.ws = ws;
+    A.symbols = symbols;
+    A.lengths = lengths;
+    A.a_idx = a_idx;
+    A.b_idx = b_idx;
+    A.ctr = reinterpret_cast<int32_t *>(ws + B->off_ctr);
+    A.next = reinterpret_cast<unsigned long long *>(ws + B->off_ctl);
+    A.gerr = reinterpret_cast<int32_t *>(ws + B->off_ctl + 8);
+    A.sigma = B->d.alphabet;
+    A.tile = B->d.tile;
+    const int64_t nctr = (int64_t)B->ctr_per_pair * count;
+    const int32_t grid = B->resident;
+
+    auto enqueue = [&](hipStream_t st) -> int32_t {
+        if (hipMemcpyAsync(ws + B->off_pairs, B->host_pairs, sizeof(PairRec) * count,
+                           hipMemcpyHostToDevice, st) != hipSuccess)
+            return LCS_E_HIP;
+        if (hipEventRecord(B->copied, st) != hipSuccess) return LCS_E_HIP;
+        hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, st, reinterpret_cast<int32_t *>(ws + B->off_ctl),
+                           (int64_t)16, 0);
+        hipLaunchKernelGGL(k_fill, dim3((unsigned)((nctr + 255) / 256 < 1024 ? (nctr + 255) / 256 : 1024)),
+                           dim3(256), 0, st, A.ctr, nctr, 0);
+        switch (B->d.base_rows) {
+            case 16: hipLaunchKernelGGL(k_persistent<16>, dim3(grid), dim3(kBlock), 0, st, A); break;
+            case 32: hipLaunchKernelGGL(k_persistent<32>, dim3(grid), dim3(kBlock), 0, st, A); break;
+            default: hipLaunchKernelGGL(k_persistent<64>, dim3(grid), dim3(kBlock), 0, st, A); break;
+        }
+        return hipGetLastError() == hipSuccess ? LCS_OK : LCS_E_HIP;
+    };
+
+    if (!(mode & LCS_BATCH_GRAPH)) return enqueue(s);
+
+    // graph: captured once per (count, buffers, tasks), replayed afterwards
+    key = mix(key, (uint64_t)count);
+    key = mix(key, (uint64_t)(uintptr_t)ws);
+    key = mix(key, (uint64_t)(uintptr_t)symbols);
+    key = mix(key, (uint64_t)(uintptr_t)lengths);
+    key = mix(key, (uint64_t)(uintptr_t)a_idx);
+    key = mix(key, (uint64_t)tbase);
+    if (!B->gexec || B->gkey != key) {
+        if (B->gexec) hipGraphExecDestroy(B->gexec);
+        if (B->graph) hipGraphDestroy(B->graph);
+        B->gexec = nullptr;
+        B->graph = nullptr;
+        hipStream_t cs;
+        if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return LCS_E_HIP;
+        if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+            hipStreamDestroy(cs);
+            return LCS_E_HIP;
+        }
+        const int32_t rc = enqueue(cs);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(cs, &g);
+        hipStreamDestroy(cs);
+        if (rc != LCS_OK || e != hipSuccess) {
+            if (g) hipGraphDestroy(g);
+            return LCS_E_HIP;
+        }
+        if (hipGraphInstantiate(&B->gexec, g, nullptr, nullptr, 0) != hipSuccess) {
+            hipGraphDestroy(g);
+            return LCS_E_HIP;
+        }
+        B->graph = g;
+        B->gkey = key;
+    }
+    return hipGraphLaunch(B->gexec, s) == hipSuccess ? LCS_OK : LCS_E_HIP;
+}
+
+// status of the last persistent run (device word written by the kernel)
+extern "C" int32_t lcs_batch_status(lcs_batch_t B, void *workspace, void *stream) {
+    if (!B || !workspace) return LCS_E_INVAL;
+    int32_t err = 0;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (hipMemcpyAsync(&err, static_cast<uint8_t *>(workspace) + B->off_ctl + 8, 4,
+                       hipMemcpyDeviceToHost, s) != hipSuccess)
+        return LCS_E_HIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return LCS_E_HIP;
+    return err ? LCS_E_HIP : LCS_OK;
+}
+
+// Host simulation of the persistent schedule for a batch (no device work):
+// builds the pair records exactly as lcs_batch_submit does, then checks that
+//  - every counter index a task waits on or raises lies inside the counters of
+//    its own pair (or, for the slot-reuse wait, of the pair it waits for);
+//  - run one task at a time in task-number order, every wait is already met
+//    (so every dependency points to a smaller task number: the queue drains);
+//  - every wait's target equals the total number of raises of its counter
+//    (a met wait proves that all of its producers have finished);
+//  - every task of a pair is an ancestor of that pair's finishing tasks, so
+//    the slot-reuse wait orders ALL work of the previous occupant of a slot
+//    before the new pair's first task;
+//  - each pair's layout fits its slot.
+// Returns LCS_OK or LCS_E_STATE (schedule defect), LCS_E_INVAL, LCS_E_TOO_BIG.
+extern "C" int32_t lcs_batch_selftest(const lcs_batch_desc *desc, const lcs_pair_desc *pairs,
+                                      int32_t count) {
+    if (!desc || (count > 0 && !pairs) || count < 0) return LCS_E_INVAL;
+    lcs_batch_s b;
+    const int32_t rc = plan_sizes(desc, &b);
+    if (rc != LCS_OK) return rc;
+    if (count > b.d.max_pairs) return LCS_E_TOO_BIG;
+    std::vector<PairRec> R((size_t)count);
+    int64_t woff = 0, tbase = 0;
+    for (int32_t p = 0; p < count; ++p) {
+        if (pairs[p].m < 0 || pairs[p].n < 0 || pairs[p].m > b.d.max_len || pairs[p].n > b.d.max_len)
+            return LCS_E_TOO_BIG;
+        if (!make_pair(&b, pairs[p], p, woff, tbase, R[p])) return LCS_E_STATE;
+        woff += pairs[p].m < pairs[p].n ? pairs[p].m : pairs[p].n;
+        tbase += R[p].ntasks;
+    }
+    const int64_t nctr = (int64_t)b.ctr_per_pair * count;
+    std::vector<int32_t> ctr((size_t)nctr, 0), total((size_t)nctr, 0);
+    std::vector<Task> tasks((size_t)tbase);
+    for (int64_t t = 0; t < tbase; ++t) {
+        tasks[t] = decode_task(R.data(), count, b.d.slots, t);
+        const Task &T = tasks[t];
+        const PairRec &P = R[T.pair];
+        for (int32_t i = 0; i < T.nsig; ++i) {
+            const int32_t c = T.sig_idx[i];
+            if (c < P.ctr_base || c >= P.ctr_base + P.nctr) return LCS_E_STATE;
+            ++total[c];
+        }
+    }
+    // consumers of each counter, for the ancestor check
+    std::vector<std::vector<int64_t>> consumers((size_t)nctr);
+    for (int64_t t = 0; t < tbase; ++t) {
+        const Task &T = tasks[t];
+        const PairRec &P = R[T.pair];
+        for (int32_t w = 0; w < T.nwait; ++w) {
+            const int32_t c = T.wait_idx[w];
+            if (c < 0 || c >= nctr) return LCS_E_STATE;
+            const bool own = c >= P.ctr_base && c < P.ctr_base + P.nctr;
+            const bool prev = (T.kind == ST_NM || T.kind == ST_EMPTY) && T.pair >= b.d.slots &&
+                              c == R[T.pair - b.d.slots].ctr_base + kCtrLeaves;
+            if (!own && !prev) return LCS_E_STATE;
+            if (ctr[c] < T.wait_tgt[w]) return LCS_E_STATE;       // not met in task order
+            if (T.wait_tgt[w] != total[c]) return LCS_E_STATE;    // met before all producers ran
+            if (own) consumers[c].push_back(t);
+        }
+        for (int32_t i = 0; i < T.nsig; ++i) ++ctr[T.sig_idx[i]];
+    }
+    // every task must lead (through its own pair's counters) to a finishing task
+    std::vector<char> reach((size_t)tbase, 0);
+    for (int64_t t = tbase - 1; t >= 0; --t) {
+        const Task &T = tasks[t];
+        if (T.kind == ST_LEAF || T.kind == ST_EMPTY) {
+            reach[t] = 1;
+            continue;
+        }
+        for (int32_t i = 0; i < T.nsig && !reach[t]; ++i)
+            for (int64_t c : consumers[T.sig_idx[i]])
+                if (reach[c]) {
+                    reach[t] = 1;
+                    break;
+                }
+        if (!reach[t]) return LCS_E_STATE;
+    }
+    return LCS_OK;
+}

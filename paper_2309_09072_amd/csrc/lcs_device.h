@@ -23,6 +23,11 @@ constexpr int kMaxTile = 32;
 
 __host__ __device__ __forceinline__ int32_t imin(int32_t a, int32_t b) { return a < b ? a : b; }
 __host__ __device__ __forceinline__ int32_t imax(int32_t a, int32_t b) { return a > b ? a : b; }
+// min of two values read as unsigned: a stray negative value can never win,
+// so a row index stays inside [0, bound] even if its input were corrupt
+__device__ __forceinline__ int32_t umin(int32_t a, int32_t b) {
+    return (int32_t)((uint32_t)a < (uint32_t)b ? (uint32_t)a : (uint32_t)b);
+}
 
 // ---------------------------------------------------------------------------
 // Wave-level inclusive suffix minimum: lane l receives min(v[l..63]).
@@ -97,7 +102,9 @@ __device__ void nextmatch_block(const uint8_t *__restrict__ b, int32_t n, int32_
 // the next-match table of that row's symbol, so
 //     D'(i, j) = min(D(i, j), nm_{a[r]}[D(i, j - 1)])        (j = r+1 .. 1).
 // The finished rows go through LDS so the store to HBM is contiguous: rows
-// v..v+63 of a strip matrix are adjacent in memory.  lds: kWaves*64*(H0+1).
+// v..v+63 of a strip matrix are adjacent in memory.  The waves take turns on
+// one 64-row buffer, and all 256 threads copy each turn out.
+// lds: kWave*(H0+1) int32.
 template <int H0>
 __device__ void base_strip_block(const uint8_t *__restrict__ arow, int32_t h, int32_t n,
                                  int32_t sigma, const int32_t *__restrict__ nm,
@@ -119,130 +126,98 @@ __device__ void base_strip_block(const uint8_t *__restrict__ arow, int32_t h, in
             if (x < sigma) {
                 const int32_t *__restrict__ nmx = nm + (size_t)x * (size_t)(n + 2);
 #pragma unroll
-                for (int j = r + 1; j >= 1; --j) D[j] = imin(D[j], nmx[D[j - 1]]);
+                for (int j = r + 1; j >= 1; --j) D[j] = umin(D[j], nmx[D[j - 1]]);
             } else {
                 bad = true;
             }
         }
     }
     if (bad && threadIdx.x == 0) atomicOr(err, kErrSymbol);
-    int32_t *buf = lds + w * kWave * (H0 + 1);
+    const int32_t hp1 = h + 1;
+    for (int w2 = 0; w2 < kWaves; ++w2) {
+        if (w == w2) {
 #pragma unroll
-    for (int j = 0; j <= H0; ++j) buf[lane * (H0 + 1) + j] = D[j];
-    __syncthreads();
-    const int32_t wv0 = v0 + w * kWave;
-    const int32_t nrows = imin(kWave, n + 2 - wv0);
-    if (nrows > 0) {
-        int32_t *dst = out + (size_t)wv0 * (size_t)(h + 1);
-        if (h == H0) {
-            const int32_t total = nrows * (H0 + 1);
-            for (int32_t e = lane; e < total; e += kWave) dst[e] = buf[e];
-        } else {
-            const int32_t hp1 = h + 1;
-            const int32_t total = nrows * hp1;
-            for (int32_t e = lane; e < total; e += kWave) {
-                const int32_t rr = e / hp1;
-                dst[e] = buf[rr * (H0 + 1) + (e - rr * hp1)];
+            for (int j = 0; j <= H0; ++j) lds[lane * (H0 + 1) + j] = D[j];
+        }
+        __syncthreads();
+        const int32_t wv0 = v0 + w2 * kWave;
+        const int32_t nrows = imin(kWave, n + 2 - wv0);
+        if (nrows > 0) {
+            int32_t *dst = out + (size_t)wv0 * (size_t)hp1;
+            if (h == H0) {
+                for (int32_t e = threadIdx.x; e < nrows * (H0 + 1); e += kBlock) dst[e] = lds[e];
+            } else {
+                for (int32_t e = threadIdx.x; e < nrows * hp1; e += kBlock) {
+                    const int32_t rr = e / hp1;
+                    dst[e] = lds[rr * (H0 + 1) + (e - rr * hp1)];
+                }
             }
         }
+        __syncthreads();
     }
-    __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
 // Candidate scan of the combine equation for one output (vertex row urow of
-// D_U, weight j): candidates k = lo, lo+step, ... <= hi in increasing order,
-// value D_L(D_U(i, k), j - k).  Loads are issued kBatch candidates at a time
-// (the D_U values first, then the D_L lookups of the candidates that survive
-// the filters), so one round trip to memory serves several candidates; the
-// decisions are then taken one candidate at a time in increasing k, which
-// keeps the smallest minimising k.  Filters and exits:
-//   x < xa: skip the candidate (its crossing lies left of the bracket);
-//   x > xb: stop (every later crossing lies right of it; xb <= n);
-//   x - k >= best - j: stop, since D_L(x, w) >= x + w;
-//   value == vlo (a proven lower bound of the result): stop.
-// With step > 1 the thread owns every step-th candidate; its local result is
-// still exact for those candidates and the exits remain valid.
+// D_U, weight j): candidates k = k0, k0+step, ... in increasing order, value
+// D_L(D_U(i, k), j - k).  Every k with max(0, j-hL) <= k <= min(j, hU) is a
+// term of the equation, so a value of ANY such candidate is >= the true
+// minimum, and no candidate below the smallest minimising k reaches it.
+// Hence a batch may evaluate candidates outside the search window freely:
+// taking the first strict minimum over the batch keeps the exact value and
+// the smallest argmin.  The search-window tests only decide whether the scan
+// may stop, and each of them is monotone in k:
+//   k > hi;  x = D_U(i, k) > xb (crossings right of the bracket);
+//   x - k >= best - j (then D_L(x, w) >= x + w > best for every later k);
+//   best == vlo, a proven lower bound of the result.
+// So they are tested once, on the last candidate of the batch.  The batch has
+// no branches: indices are clamped into the window (the loads stay in bounds,
+// a row x = n + 1 is the all-unreachable sentinel row) and results selected.
+// Returns true when the scan is finished; otherwise it resumes at
+// k0 + kBatch * step.  best starts at n + 2 ("nothing yet").
+__device__ __forceinline__ bool scan_batch(const int32_t *__restrict__ urow,
+                                           const int32_t *__restrict__ L, int32_t ldL, int32_t j,
+                                           int32_t k0, int32_t step, int32_t hi, int32_t xb,
+                                           int32_t vlo, int32_t n, int32_t &best, int32_t &bk,
+                                           int32_t &bx) {
+    int32_t xs[kBatch], vs[kBatch];
+#pragma unroll
+    for (int t = 0; t < kBatch; ++t) xs[t] = umin(urow[imin(k0 + t * step, hi)], n + 1);
+#pragma unroll
+    for (int t = 0; t < kBatch; ++t) {
+        const int32_t kc = imin(k0 + t * step, hi);
+        const int32_t v = L[(uint32_t)xs[t] * (uint32_t)ldL + (uint32_t)(j - kc)];
+        vs[t] = (k0 + t * step <= hi) ? v : 0x7fffffff;
+    }
+#pragma unroll
+    for (int t = 0; t < kBatch; ++t) {
+        const bool upd = vs[t] < best;
+        best = upd ? vs[t] : best;
+        bk = upd ? k0 + t * step : bk;
+        bx = upd ? xs[t] : bx;
+    }
+    const int32_t klast = k0 + (kBatch - 1) * step;
+    const int32_t xl = xs[kBatch - 1];
+    return (klast >= hi) | (xl > xb) | (best == vlo) | ((best <= n) & (xl - klast >= best - j));
+}
+
+// Whole scan over [lo, hi] with stride step (loop of batches).
 __device__ __forceinline__ void scan_candidates(const int32_t *__restrict__ urow,
                                                 const int32_t *__restrict__ L, int32_t ldL,
                                                 int32_t j, int32_t lo, int32_t hi, int32_t step,
-                                                int32_t xa, int32_t xb, int32_t vlo, int32_t n,
-                                                int32_t &best, int32_t &bk, int32_t &bx) {
+                                                int32_t xb, int32_t vlo, int32_t n, int32_t &best,
+                                                int32_t &bk, int32_t &bx) {
     best = n + 2;
     bk = -1;
     bx = n + 1;
-    for (int32_t k0 = lo; k0 <= hi; k0 += kBatch * step) {
-        int32_t xs[kBatch], vs[kBatch];
-#pragma unroll
-        for (int t = 0; t < kBatch; ++t) {
-            const int32_t k = k0 + t * step;
-            xs[t] = (k <= hi) ? urow[k] : 0x7fffffff;
-        }
-#pragma unroll
-        for (int t = 0; t < kBatch; ++t) {
-            const int32_t k = k0 + t * step;
-            const int32_t x = xs[t];
-            const bool want = (k <= hi) && x >= xa && x <= xb && !(best <= n && x - k >= best - j);
-            vs[t] = want ? L[(size_t)x * ldL + (j - k)] : 0x7fffffff;
-        }
-        bool stop = false;
-#pragma unroll
-        for (int t = 0; t < kBatch; ++t) {
-            const int32_t k = k0 + t * step;
-            const int32_t x = xs[t];
-            if (!stop && x >= xa) {
-                if (k > hi || x > xb || (best <= n && x - k >= best - j)) {
-                    stop = true;
-                } else if (vs[t] < best) {
-                    best = vs[t];
-                    bk = k;
-                    bx = x;
-                    if (best == vlo) stop = true;
-                }
-            }
-        }
-        if (stop) break;
-    }
+    if (lo <= hi)
+        for (int32_t k0 = lo;; k0 += kBatch * step)
+            if (scan_batch(urow, L, ldL, j, k0, step, hi, xb, vlo, n, best, bk, bx)) break;
     if (best > n) {
         best = n + 1;
         bk = -1;
         bx = n + 1;
     }
-}
-
-// One batch of scan_candidates for a unit-step scan starting at k0: returns
-// true when the scan is finished (exit taken or window exhausted); otherwise
-// the caller resumes at k0 + kBatch with the same best/bk/bx.
-__device__ __forceinline__ bool scan_batch(const int32_t *__restrict__ urow,
-                                           const int32_t *__restrict__ L, int32_t ldL, int32_t j,
-                                           int32_t k0, int32_t hi, int32_t xa, int32_t xb,
-                                           int32_t vlo, int32_t n, int32_t &best, int32_t &bk,
-                                           int32_t &bx) {
-    int32_t xs[kBatch], vs[kBatch];
-#pragma unroll
-    for (int t = 0; t < kBatch; ++t) xs[t] = (k0 + t <= hi) ? urow[k0 + t] : 0x7fffffff;
-#pragma unroll
-    for (int t = 0; t < kBatch; ++t) {
-        const int32_t k = k0 + t, x = xs[t];
-        const bool want = (k <= hi) && x >= xa && x <= xb && !(best <= n && x - k >= best - j);
-        vs[t] = want ? L[(uint32_t)x * (uint32_t)ldL + (uint32_t)(j - k)] : 0x7fffffff;
-    }
-    bool stop = false;
-#pragma unroll
-    for (int t = 0; t < kBatch; ++t) {
-        const int32_t k = k0 + t, x = xs[t];
-        if (!stop && x >= xa) {
-            if (k > hi || x > xb || (best <= n && x - k >= best - j)) {
-                stop = true;
-            } else if (vs[t] < best) {
-                best = vs[t];
-                bk = k;
-                bx = x;
-                if (best == vlo) stop = true;
-            }
-        }
-    }
-    return stop || k0 + kBatch > hi;
 }
 
 // ---------------------------------------------------------------------------
@@ -305,7 +280,7 @@ __device__ void anchor_block(const int32_t *__restrict__ U, int32_t hU,
                     const int32_t lo = imax(kl, imax(c - hL, 0));
                     const int32_t hi = imin(kr, imin(c, hU));
                     int32_t best, bk, bx;
-                    scan_candidates(urow, L, ldL, c, lo + gl, hi, g, 0, n, -1, n, best, bk, bx);
+                    scan_candidates(urow, L, ldL, c, lo + gl, hi, g, n, -1, n, best, bk, bx);
                     if (best <= n) key = ((unsigned long long)(uint32_t)best << 32) | (uint32_t)bk;
                 }
             }
@@ -362,7 +337,7 @@ struct BracketSmem {
 };
 
 struct BracketWindow {
-    int32_t lo, hi, xa, xb, vlo;
+    int32_t lo, hi, xb, vlo;
     bool dead;
 };
 
@@ -373,17 +348,15 @@ __device__ __forceinline__ BracketWindow bracket_window(const BracketSmem &sm, i
     constexpr int32_t S = kJChunk + 1;
     BracketWindow w;
     const int32_t ka = sm.k[va * S + jj];
-    w.dead = ka < 0;
     const int32_t kb = sm.k[vb * S + jj];
+    w.dead = ka < 0;
+    w.hi = imin(j, hU);
+    w.xb = n;
     if (kb >= 0) {
-        w.hi = imin(kb + (vb - v), imin(j, hU));
+        w.hi = imin(kb + (vb - v), w.hi);
         w.xb = sm.x[vb * S + jj];
-    } else {
-        w.hi = imin(j, hU);
-        w.xb = n;
     }
     w.lo = imax(ka - (v - va), imax(j - hL, 0));
-    w.xa = sm.x[va * S + jj];
     w.vlo = sm.v[va * S + jj];
     return w;
 }
@@ -394,14 +367,11 @@ __device__ void bracket_block(const int32_t *__restrict__ U, int32_t hU,
                               const int32_t *__restrict__ Ka, const int32_t *__restrict__ Kb,
                               BracketSmem &sm) {
     if (len < 2 || jn <= 0) return;
-    constexpr int32_t S = kJChunk + 1;  // LDS row stride (weights)
-    constexpr int32_t kHalf = 32;       // threads per vertex in a pass
+    constexpr int32_t S = kJChunk + 1;  // LDS row stride (weights); item slots per vertex
     const int32_t INF = n + 1;
     const int32_t H = hU + hL + 1;
     const int32_t ldU = hU + 1, ldL = hL + 1;
-    const int32_t hl = threadIdx.x & (kHalf - 1);
-    const int32_t grp = threadIdx.x / kHalf;
-    constexpr int32_t ngrp = kBlock / kHalf;
+    const int32_t lane = __lane_id();
     // the two solved ends of the tile
     for (int32_t side = 0; side < 2; ++side) {
         const int32_t slot = side ? len : 0;
@@ -421,24 +391,40 @@ __device__ void bracket_block(const int32_t *__restrict__ U, int32_t hU,
     for (int32_t st = P2; st >= 2; st >>= 1) {
         const int32_t half = st >> 1;
         const int32_t nv = (len > half) ? (len - half + st - 1) / st : 0;
-        // pass 1: one batch per output
-        for (int32_t t = grp; t < nv; t += ngrp) {
+        // pass 1: one batch per output; item e -> (vertex t, weight jj)
+        const int32_t nitems = nv * S;
+        for (int32_t base = 0; base < nitems; base += kBlock) {
+            const int32_t e = base + threadIdx.x;
+            const int32_t t = e / S, jj = e - t * S;
             const int32_t v = half + t * st;
-            const int32_t va = v - half, vb = imin(v + half, len);
-            const int32_t *__restrict__ urow = U + (size_t)(i0 + v) * ldU;
-            for (int32_t jj = hl; jj < jn; jj += kHalf) {
+            const bool act = (e < nitems) && (jj < jn);
+            bool queued = false;
+            if (act) {
+                const int32_t va = v - half, vb = imin(v + half, len);
                 const int32_t j = j0 + jj;
                 const BracketWindow w = bracket_window(sm, v, va, vb, jj, j, hU, hL, n);
                 int32_t best = n + 2, bk = -1, bx = INF;
-                bool done = w.dead;
-                if (!done) done = scan_batch(urow, L, ldL, j, w.lo, w.hi, w.xa, w.xb, w.vlo, n, best, bk, bx);
+                bool done = w.dead || w.lo > w.hi;
+                if (!done)
+                    done = scan_batch(U + (size_t)(i0 + v) * ldU, L, ldL, j, w.lo, 1, w.hi, w.xb,
+                                      w.vlo, n, best, bk, bx);
                 const int32_t id = v * S + jj;
                 sm.k[id] = bk;
                 sm.x[id] = bx;
                 sm.v[id] = best;
-                if (!done) {
-                    sm.nk[id] = w.lo + kBatch;
-                    sm.q[atomicAdd(&sm.qn, 1)] = id;
+                sm.nk[id] = w.lo + kBatch;
+                queued = !done;
+            }
+            // reserve queue slots with one LDS atomic per wave
+            const unsigned long long mask = __ballot(queued);
+            if (mask) {
+                const int32_t leader = __ffsll((long long)mask) - 1;
+                int32_t qbase = 0;
+                if (lane == leader) qbase = atomicAdd(&sm.qn, __popcll(mask));
+                qbase = __shfl(qbase, leader, kWave);
+                if (queued) {
+                    const unsigned long long below = mask & ((1ull << lane) - 1ull);
+                    sm.q[qbase + __popcll(below)] = v * S + jj;
                 }
             }
         }
@@ -454,30 +440,28 @@ __device__ void bracket_block(const int32_t *__restrict__ U, int32_t hU,
             const int32_t *__restrict__ urow = U + (size_t)(i0 + v) * ldU;
             int32_t best = sm.v[id], bk = sm.k[id], bx = sm.x[id];
             for (int32_t k0 = sm.nk[id];; k0 += kBatch)
-                if (scan_batch(urow, L, ldL, j, k0, w.hi, w.xa, w.xb, w.vlo, n, best, bk, bx)) break;
+                if (scan_batch(urow, L, ldL, j, k0, 1, w.hi, w.xb, w.vlo, n, best, bk, bx)) break;
             sm.k[id] = bk;
             sm.x[id] = bx;
             sm.v[id] = best;
         }
         __syncthreads();
         // normalise unreachable results
-        for (int32_t t = grp; t < nv; t += ngrp) {
-            const int32_t v = half + t * st;
-            for (int32_t jj = hl; jj < jn; jj += kHalf) {
-                const int32_t id = v * S + jj;
-                if (sm.v[id] > n) {
-                    sm.v[id] = INF;
-                    sm.k[id] = -1;
-                    sm.x[id] = INF;
-                }
+        for (int32_t e = threadIdx.x; e < nitems; e += kBlock) {
+            const int32_t t = e / S, jj = e - t * S;
+            const int32_t id = (half + t * st) * S + jj;
+            if (jj < jn && sm.v[id] > n) {
+                sm.v[id] = INF;
+                sm.k[id] = -1;
+                sm.x[id] = INF;
             }
         }
         if (threadIdx.x == 0) sm.qn = 0;
         __syncthreads();
     }
-    for (int32_t t = 1 + grp; t < len; t += ngrp) {
-        int32_t *grow = G + (size_t)(i0 + t) * H + j0;
-        for (int32_t jj = hl; jj < jn; jj += kHalf) grow[jj] = sm.v[t * S + jj];
+    for (int32_t e = threadIdx.x; e < (len - 1) * S; e += kBlock) {
+        const int32_t t = 1 + e / S, jj = e - (t - 1) * S;
+        if (jj < jn) G[(size_t)(i0 + t) * H + j0 + jj] = sm.v[t * S + jj];
     }
     __syncthreads();
 }
@@ -496,7 +480,7 @@ __device__ void length_block(const int32_t *__restrict__ top, int32_t m, int32_t
     atomicAdd(lds, cnt);
     __syncthreads();
     if (threadIdx.x == 0) {
-        const int32_t L = lds[0] - 1;
+        const int32_t L = imax(lds[0] - 1, 0);
         const int32_t y = top[L];
         hdr[1] = L;
         hdr[2] = y;
@@ -515,7 +499,7 @@ __device__ void length_block(const int32_t *__restrict__ top, int32_t m, int32_t
 __device__ void trace_split_block(const int32_t *__restrict__ U, int32_t hU,
                                   const int32_t *__restrict__ L, int32_t hL, int32_t n, int4 node,
                                   int4 *outU, int4 *outL, int32_t *err, int32_t *lds) {
-    const int32_t s = node.x, w = node.y, e = node.z, off = node.w;
+    const int32_t s = umin(node.x, n), w = node.y, e = node.z, off = node.w;
     const int32_t lo = imax(0, w - hL), hi = imin(w, hU);
     const int32_t *__restrict__ urow = U + (size_t)s * (hU + 1);
     const int32_t ldL = hL + 1;
@@ -526,7 +510,7 @@ __device__ void trace_split_block(const int32_t *__restrict__ U, int32_t hU,
         const int32_t k = base + (int32_t)threadIdx.x;
         if (k <= hi) {
             const int32_t x = urow[k];
-            if (x <= n && L[(size_t)x * ldL + (w - k)] == e) atomicMin(lds, k);
+            if ((uint32_t)x <= (uint32_t)n && L[(size_t)x * ldL + (w - k)] == e) atomicMin(lds, k);
         }
         __syncthreads();
         found = lds[0];
@@ -539,7 +523,7 @@ __device__ void trace_split_block(const int32_t *__restrict__ U, int32_t hU,
             *outU = make_int4(s, 0, s, off);
             *outL = make_int4(s, 0, s, off);
         } else {
-            const int32_t x = urow[found];
+            const int32_t x = umin(urow[found], n);
             *outU = make_int4(s, found, x, off);
             *outL = make_int4(x, w - found, e, off + found);
         }
@@ -554,15 +538,17 @@ __device__ void trace_split_block(const int32_t *__restrict__ U, int32_t hU,
 // split with the smaller upper weight is the one where row r-1 contributes a
 // match, taken when nm_{a[r-1]}[D_{r-1}(s, w-1)] == e (match (row0 + r - 1,
 // e - 1)); otherwise the path enters row r at the same column.  Matches are
-// written at witness offsets off .. off + w - 1 in increasing order.
+// written at witness offsets off .. off + w - 1 in increasing order; wcap
+// (= min(m, n)) bounds every write.
 // lds: (H0+1)*(H0+1) int32.
 template <int H0>
 __device__ void trace_leaf_block(const uint8_t *__restrict__ arow, int32_t h, int32_t n,
                                  int32_t sigma, const int32_t *__restrict__ nm, int4 node,
                                  int32_t row0, int32_t *__restrict__ a_idx,
-                                 int32_t *__restrict__ b_idx, int32_t *err, int32_t *lds) {
+                                 int32_t *__restrict__ b_idx, int32_t wcap, int32_t *err,
+                                 int32_t *lds) {
     const int32_t INF = n + 1;
-    const int32_t s = node.x;
+    const int32_t s = umin(node.x, n);
     const int32_t S = H0 + 1;
     const int32_t tid = threadIdx.x;
     if (tid <= h) lds[tid] = (tid == 0) ? s : INF;
@@ -571,21 +557,23 @@ __device__ void trace_leaf_block(const uint8_t *__restrict__ arow, int32_t h, in
         const int32_t x = arow[r];
         if (tid <= h) {
             int32_t d = lds[r * S + tid];
-            if (tid >= 1 && x < sigma) d = imin(d, nm[(size_t)x * (n + 2) + lds[r * S + tid - 1]]);
+            if (tid >= 1 && x < sigma) d = umin(d, nm[(size_t)x * (n + 2) + lds[r * S + tid - 1]]);
             lds[(r + 1) * S + tid] = d;
         }
         __syncthreads();
     }
     if (tid == 0) {
-        int32_t w = node.y, e = node.z;
-        const int32_t off = node.w;
+        int32_t w = imin(imax(node.y, 0), h), e = node.z;
+        const int32_t off = imax(node.w, 0);
         for (int32_t r = h; r >= 1; --r) {
             const int32_t x = arow[r - 1];
             if (w >= 1 && x < sigma) {
                 const int32_t p = lds[(r - 1) * S + (w - 1)];
                 if (p <= n && nm[(size_t)x * (n + 2) + p] == e) {
-                    a_idx[off + w - 1] = row0 + r - 1;
-                    b_idx[off + w - 1] = e - 1;
+                    if (off + w <= wcap) {
+                        a_idx[off + w - 1] = row0 + r - 1;
+                        b_idx[off + w - 1] = e - 1;
+                    }
                     e = p;
                     --w;
                 }

@@ -20,7 +20,7 @@ template <int H0>
 __global__ void __launch_bounds__(kBlock) k_base(const uint8_t *a, int32_t n, int32_t sigma,
                                                  const int32_t *nm, int32_t *base0, int32_t *last,
                                                  int32_t nstrips, int32_t hlast, int32_t *err) {
-    __shared__ int32_t lds[kWaves * kWave * (H0 + 1)];
+    __shared__ int32_t lds[kWave * (H0 + 1)];
     const int32_t s = blockIdx.y;
     const bool is_last = (s == nstrips - 1);
     const int32_t h = is_last ? hlast : H0;
@@ -87,12 +87,12 @@ __global__ void __launch_bounds__(kBlock) k_trace_leaf(const uint8_t *a, int32_t
                                                        const int32_t *nm, int32_t nstrips,
                                                        int32_t hlast, const int4 *nodes,
                                                        int32_t *a_idx, int32_t *b_idx,
-                                                       int32_t *err) {
+                                                       int32_t wcap, int32_t *err) {
     __shared__ int32_t lds[(H0 + 1) * (H0 + 1)];
     const int32_t s = blockIdx.x;
     const int32_t h = (s == nstrips - 1) ? hlast : H0;
-    trace_leaf_block<H0>(a + (size_t)s * H0, h, n, sigma, nm, nodes[s], s * H0, a_idx, b_idx, err,
-                         lds);
+    trace_leaf_block<H0>(a + (size_t)s * H0, h, n, sigma, nm, nodes[s], s * H0, a_idx, b_idx, wcap,
+                         err, lds);
 }
 
 __global__ void k_copy_len(const int32_t *hdr, int32_t *dst) {
@@ -161,19 +161,20 @@ hipError_t launch_trace_split(const CombineArgs &c, int32_t nparent, const int4 
 
 hipError_t launch_trace_leaf(int32_t h0, const uint8_t *a, int32_t n, int32_t sigma,
                              const int32_t *nm, int32_t nstrips, int32_t hlast, const int4 *nodes,
-                             int32_t *a_idx, int32_t *b_idx, int32_t *err, hipStream_t s) {
+                             int32_t *a_idx, int32_t *b_idx, int32_t wcap, int32_t *err,
+                             hipStream_t s) {
     switch (h0) {
         case 16:
             hipLaunchKernelGGL(k_trace_leaf<16>, dim3(nstrips), dim3(kBlock), 0, s, a, n, sigma, nm,
-                               nstrips, hlast, nodes, a_idx, b_idx, err);
+                               nstrips, hlast, nodes, a_idx, b_idx, wcap, err);
             break;
         case 32:
             hipLaunchKernelGGL(k_trace_leaf<32>, dim3(nstrips), dim3(kBlock), 0, s, a, n, sigma, nm,
-                               nstrips, hlast, nodes, a_idx, b_idx, err);
+                               nstrips, hlast, nodes, a_idx, b_idx, wcap, err);
             break;
         case 64:
             hipLaunchKernelGGL(k_trace_leaf<64>, dim3(nstrips), dim3(kBlock), 0, s, a, n, sigma, nm,
-                               nstrips, hlast, nodes, a_idx, b_idx, err);
+                               nstrips, hlast, nodes, a_idx, b_idx, wcap, err);
             break;
         default:
             return hipErrorInvalidValue;

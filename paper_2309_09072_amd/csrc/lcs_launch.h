@@ -20,7 +20,8 @@ hipError_t launch_trace_split(const CombineArgs &c, int32_t nparent, const int4 
                               int4 *nodes_out, int32_t *err, hipStream_t s);
 hipError_t launch_trace_leaf(int32_t h0, const uint8_t *a, int32_t n, int32_t sigma,
                              const int32_t *nm, int32_t nstrips, int32_t hlast, const int4 *nodes,
-                             int32_t *a_idx, int32_t *b_idx, int32_t *err, hipStream_t s);
+                             int32_t *a_idx, int32_t *b_idx, int32_t wcap, int32_t *err,
+                             hipStream_t s);
 hipError_t launch_copy_len(const int32_t *hdr, int32_t *dst, hipStream_t s);
 
 }  // namespace lcs

@@ -95,6 +95,8 @@ PROTOTYPES = {
     "lcs_dist_view": (_I32, [_P, _I32, _I32, ctypes.POINTER(_P), _PI32, _PI32, _PI32]),
     "lcs_batch_plan": (_I32, [ctypes.POINTER(BatchDesc), ctypes.POINTER(_P), _PSZ]),
     "lcs_batch_destroy": (_I32, [_P]),
+    "lcs_batch_status": (_I32, [_P, _P, _P]),
+    "lcs_batch_selftest": (_I32, [ctypes.POINTER(BatchDesc), _P, _I32]),
     "lcs_batch_submit": (_I32, [_P, _P, _I32, _P, _I64, _P, _P, _P, _I64, _P, _SZ, _U32, _P]),
     "lcs_server_open": (_I32, [ctypes.POINTER(ServerDesc), _P, _SZ, _P, _P, _I64, ctypes.POINTER(_P)]),
     "lcs_server_footprint": (_I32, [_P, _I32, _I32, _PSZ]),
@@ -285,3 +287,90 @@ def lcs(a, b, alphabet: int, base_rows: int = 0, tile: int = 0, witness: bool = 
         return L, ai[:L].cpu().numpy(), bi[:L].cpu().numpy()
     finally:
         plan.close()
+
+
+class Batch:
+    """A planned batch (lcs_batch_plan): many pairs per submit, one persistent launch."""
+
+    def __init__(self, max_pairs: int, max_len: int, alphabet: int, base_rows: int = 0,
+                 tile: int = 0, slots: int = 0):
+        lib = load()
+        self.desc = BatchDesc(int(max_pairs), int(max_len), int(alphabet), int(base_rows),
+                              int(tile), int(slots), 0)
+        h = ctypes.c_void_p()
+        ws = ctypes.c_size_t()
+        check(lib.lcs_batch_plan(ctypes.byref(self.desc), ctypes.byref(h), ctypes.byref(ws)),
+              "lcs_batch_plan")
+        self._h = h
+        self.workspace_bytes = int(ws.value)
+
+    @staticmethod
+    def witness_offsets(m, n):
+        mn = np.minimum(np.asarray(m, np.int64), np.asarray(n, np.int64))
+        off = np.zeros(mn.size + 1, np.int64)
+        np.cumsum(mn, out=off[1:])
+        return off
+
+    def submit(self, symbols, a_off, b_off, m, n, ws, lengths, a_idx, b_idx,
+               mode: int = BATCH_PERSISTENT, stream=None) -> None:
+        """Enqueue every pair; symbols is a device uint8 tensor, the rest host arrays /
+        device output tensors (lengths int32[count], a_idx/b_idx int32[sum min(m,n)])."""
+        count = int(len(m))
+        descs = (PairDesc * max(count, 1))()
+        for p in range(count):
+            descs[p].a_off, descs[p].b_off = int(a_off[p]), int(b_off[p])
+            descs[p].m, descs[p].n = int(m[p]), int(n[p])
+        self._keep = (symbols, ws, lengths, a_idx, b_idx, descs)
+        cap = 0 if a_idx is None else min(int(a_idx.numel()), int(b_idx.numel()))
+        check(load().lcs_batch_submit(self._h, ctypes.cast(descs, ctypes.c_void_p), count,
+                                      _dptr(symbols), int(symbols.numel()), _dptr(lengths),
+                                      _dptr(a_idx), _dptr(b_idx), cap, _dptr(ws), int(ws.numel()),
+                                      int(mode), stream_handle(stream)), "lcs_batch_submit")
+
+    def status(self, ws, stream=None) -> None:
+        check(load().lcs_batch_status(self._h, _dptr(ws), stream_handle(stream)), "lcs_batch_status")
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            load().lcs_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def batch_selftest(m, n, alphabet: int, base_rows: int = 0, tile: int = 0, slots: int = 0,
+                   max_len: int = 0) -> int:
+    """Host simulation of the persistent schedule (lcs_batch_selftest); returns the status."""
+    count = len(m)
+    max_len = max_len or int(max(max(m, default=1), max(n, default=1), 1))
+    desc = BatchDesc(max(count, 1), max_len, int(alphabet), int(base_rows), int(tile), int(slots), 0)
+    descs = (PairDesc * max(count, 1))()
+    off = 0
+    for p in range(count):
+        descs[p].a_off, descs[p].b_off, descs[p].m, descs[p].n = off, off + m[p], int(m[p]), int(n[p])
+        off += m[p] + n[p]
+    return int(load().lcs_batch_selftest(ctypes.byref(desc), ctypes.cast(descs, ctypes.c_void_p), count))
+
+
+def run_batch(batch, mode: int = BATCH_PERSISTENT, base_rows: int = 0, tile: int = 0,
+              slots: int = 0, device="cuda", planned=None, ws=None):
+    """Lengths and witnesses of every pair of a synth.Batch on the GPU (numpy results)."""
+    torch = _torch()
+    b = planned or Batch(batch.count, int(max(batch.m.max(initial=1), batch.n.max(initial=1))),
+                         batch.sigma, base_rows, tile, slots)
+    if ws is None:
+        ws = alloc_workspace(b.workspace_bytes, device)
+    sym = device_bytes(batch.symbols, device) if batch.symbols.size else torch.zeros(1, dtype=torch.uint8, device=device)
+    off = Batch.witness_offsets(batch.m, batch.n)
+    lengths = torch.full((batch.count,), -99, dtype=torch.int32, device=device)
+    ai = torch.full((max(int(off[-1]), 1),), -1, dtype=torch.int32, device=device)
+    bi = torch.full((max(int(off[-1]), 1),), -1, dtype=torch.int32, device=device)
+    b.submit(sym, batch.a_off, batch.b_off, batch.m, batch.n, ws, lengths, ai, bi, mode)
+    torch.cuda.synchronize()
+    if not (mode & BATCH_PER_PAIR):
+        b.status(ws)
+    return lengths.cpu().numpy(), ai.cpu().numpy(), bi.cpu().numpy(), off

@@ -1,0 +1,85 @@
+"""Batches on the GPU: every pair's length and witness equals the oracle's, for
+the persistent single launch, its graph replay and the one-pair-per-launch
+mode, including slot reuse, empty pairs and a bad symbol."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2309_09072_amd import lcs as L
+from paper_2309_09072_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def mixed_small(count, seed, maxlen=300, sigma=4):
+    r = np.random.default_rng(seed)
+    pairs = []
+    for p in range(count):
+        m = int(r.integers(0, maxlen)) if p % 11 else 0
+        n = int(r.integers(0, maxlen)) if p % 13 else 0
+        a = r.integers(0, sigma, m).astype(np.uint8)
+        if p % 3 == 1 and m > 0:
+            b = synth.fit_length(r, synth.mutate(r, a, sigma, 0.1, 0.05, 0.05), max(n, 1), sigma)
+        else:
+            b = r.integers(0, sigma, n).astype(np.uint8)
+        pairs.append((a, b))
+    return synth.batch_from_pairs(pairs, sigma, seed, "mixed")
+
+
+def check(batch, lengths, ai, bi, off, skip=()):
+    for p in range(batch.count):
+        if p in skip:
+            continue
+        a, b = batch.pair(p)
+        Lo, ao, bo = oracle.lcs_witness(a, b)
+        assert lengths[p] == Lo, "pair %d (%dx%d): %d vs oracle %d" % (p, a.size, b.size, lengths[p], Lo)
+        assert np.array_equal(ai[off[p]:off[p] + Lo], ao), "pair %d a_idx" % p
+        assert np.array_equal(bi[off[p]:off[p] + Lo], bo), "pair %d b_idx" % p
+
+
+@pytest.mark.parametrize("base_rows,tile,slots", [(16, 8, 7), (32, 32, 0), (64, 16, 3)])
+def test_persistent_matches_oracle(base_rows, tile, slots):
+    batch = mixed_small(60, 40 + base_rows)
+    say("persistent", base_rows, tile, slots)
+    res = L.run_batch(batch, L.BATCH_PERSISTENT, base_rows, tile, slots)
+    check(batch, *res)
+
+
+def test_per_pair_and_graph_agree():
+    batch = mixed_small(40, 77)
+    plan = L.Batch(batch.count, 300, 4, 32, 16, 5)
+    ws = L.alloc_workspace(plan.workspace_bytes)
+    r1 = L.run_batch(batch, L.BATCH_PER_PAIR, planned=plan, ws=ws)
+    check(batch, *r1)
+    for rep in range(3):   # graph capture, then replays with eager work in between
+        r2 = L.run_batch(batch, L.BATCH_PERSISTENT | L.BATCH_GRAPH, planned=plan, ws=ws)
+        for x, y in zip(r1, r2):
+            assert np.array_equal(x, y), "replay %d differs" % rep
+        r3 = L.run_batch(batch, L.BATCH_PERSISTENT, planned=plan, ws=ws)
+        for x, y in zip(r1, r3):
+            assert np.array_equal(x, y)
+
+
+def test_bad_symbol_only_fails_its_pair():
+    r = np.random.default_rng(5)
+    pairs = [(r.integers(0, 4, 100).astype(np.uint8), r.integers(0, 4, 90).astype(np.uint8))
+             for _ in range(6)]
+    pairs[3] = (np.array([0, 1, 7, 2], np.uint8), np.array([0, 1, 2], np.uint8))
+    batch = synth.batch_from_pairs(pairs, 4)
+    lengths, ai, bi, off = L.run_batch(batch, L.BATCH_PERSISTENT, 16, 8, 2)
+    assert lengths[3] == -5
+    check(batch, lengths, ai, bi, off, skip=(3,))
+
+
+def test_mixed_workload_sample():
+    """512 pairs of the 64..2048 mixed workload (half unrelated, half mutated copies)."""
+    batch = synth.batch_mixed(count=512, seed=synth.SEED_BASE + 40)
+    say("mixed 512 pairs, cells", batch.cells)
+    res = L.run_batch(batch, L.BATCH_PERSISTENT, 64, 32, 0)
+    check(batch, *res)
