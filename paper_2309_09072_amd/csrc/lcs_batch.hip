@@ -92,7 +92,7 @@ __device__ __forceinline__ CombineArgs pair_combine_args(const PairRec &P, uint8
     a.tile = tile;
     a.nanch = P.nanch;
     a.hs = 2 * c.hfull + 1;
-    a.anch = reinterpret_cast<int32_t *>(ws + P.off_anch);
+    a.anch = reinterpret_cast<int32_t *>(ws + P.anch_off[l]);
     a.jchunk = kJChunk;
     a.nchunks = 0;
     return a;
@@ -361,7 +361,6 @@ static bool make_pair(const lcs_batch_s *B, const lcs_pair_desc &pd, int32_t p, 
     R.task_base = task_base;
     R.off_hdr = L.off_hdr;
     R.off_nm = L.off_nm;
-    R.off_anch = L.off_anch;
     R.total = L.total;
     R.m = pd.m;
     R.n = pd.n;
@@ -372,6 +371,7 @@ static bool make_pair(const lcs_batch_s *B, const lcs_pair_desc &pd, int32_t p, 
     for (int32_t l = 0; l < R.nlev; ++l) {
         R.lev[l] = L.lev[l];
         R.node_off[l] = L.node_off[l];
+        R.anch_off[l] = L.anch_off[l];
         R.ctr_lev[l] = c;
         c += 3 * L.lev[l].nstrips;
     }

@@ -19,7 +19,8 @@ struct Layout {
     int32_t m = 0, n = 0, sigma = 0, h0 = 0, tile = 0;
     std::vector<LevelGeom> lev;      // level 0 = base strips, back() = whole grid
     std::vector<int64_t> node_off;   // per level: trace nodes (int4 per strip)
-    int64_t off_hdr = 0, off_nm = 0, off_anch = 0, total = 0;
+    std::vector<int64_t> anch_off;   // per level: anchor argmin rows of its combines
+    int64_t off_hdr = 0, off_nm = 0, total = 0;
     int32_t nanch = 0;
 };
 
@@ -75,14 +76,14 @@ inline bool make_layout(int32_t m, int32_t n, int32_t sigma, int32_t h0, int32_t
             off = align256(off + q.bytes);
             L.lev.push_back(q);
         }
+        // One region per level: in a persistent launch, combines of two levels
+        // can be in flight at the same time.
         L.nanch = (n + tile - 1) / tile + 1;
-        int64_t anch = 0;
+        L.anch_off.push_back(0);
         for (size_t l = 1; l < L.lev.size(); ++l) {
-            const int64_t b = 4 * (int64_t)L.lev[l].npairs * L.nanch * (2 * L.lev[l - 1].hfull + 1);
-            if (b > anch) anch = b;
+            L.anch_off.push_back(off);
+            off = align256(off + 4 * (int64_t)L.lev[l].npairs * L.nanch * (2 * L.lev[l - 1].hfull + 1));
         }
-        L.off_anch = off;
-        off = align256(off + anch);
         for (size_t l = 0; l < L.lev.size(); ++l) {
             L.node_off.push_back(off);
             off = align256(off + 16 * (int64_t)L.lev[l].nstrips);
@@ -107,7 +108,7 @@ inline CombineArgs combine_args(const Layout &L, uint8_t *ws, size_t l) {
     a.tile = L.tile;
     a.nanch = L.nanch;
     a.hs = 2 * c.hfull + 1;
-    a.anch = reinterpret_cast<int32_t *>(ws + L.off_anch);
+    a.anch = reinterpret_cast<int32_t *>(ws + L.anch_off[l]);
     a.jchunk = 32;
     const int32_t H = 2 * c.hfull + 1;
     a.nchunks = (H - 1 + a.jchunk - 1) / a.jchunk;

@@ -33,8 +33,9 @@ struct PairRec {
     int64_t ws_off;  // byte offset of this pair's slot in the workspace
     int64_t a_off, b_off, wit_off;
     int64_t task_base;  // first global task number of the pair
-    int64_t off_hdr, off_nm, off_anch, total;
+    int64_t off_hdr, off_nm, total;
     int64_t node_off[kMaxLev];
+    int64_t anch_off[kMaxLev];
     LevelGeom lev[kMaxLev];
     int32_t ctr_lev[kMaxLev];  // first counter of level l (relative to ctr_base)
     int32_t stage_start[kMaxStages + 1];
