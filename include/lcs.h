@@ -259,65 +259,97 @@ int32_t lcs_batch_submit(lcs_batch_t batch, const lcs_pair_desc *pairs, int32_t 
  */
 int32_t lcs_batch_status(lcs_batch_t batch, void *workspace, void *stream);
 
+/*
+ * Host simulation of the persistent schedule for `count` pairs (no device
+ * work; for tests): builds the task records as lcs_batch_submit does and
+ * checks, running the tasks one at a time in task order, that every wait is
+ * already met, that every wait target equals the number of producers of its
+ * counter, that every task of a pair leads to the pair's finish (so reuse of
+ * a workspace slot is ordered after all work of its previous pair) and that
+ * each pair's layout fits its slot.  LCS_OK, or LCS_E_STATE on a defect.
+ */
+int32_t lcs_batch_selftest(const lcs_batch_desc *desc, const lcs_pair_desc *pairs, int32_t count);
+
 /* ============================================================== serving */
 
 typedef struct lcs_server_s *lcs_server_t;
 
 typedef struct lcs_server_desc {
-    int32_t max_len;      /* largest m and n of a request */
-    int32_t alphabet;     /* largest alphabet of a request, 1..256 */
-    int32_t base_rows;    /* as in lcs_plan_desc */
-    int32_t tile;         /* as in lcs_plan_desc */
-    int32_t slots;        /* requests that may run on the device at once */
-    int32_t max_queue;    /* waiting requests held on the host */
-    uint32_t flags;       /* reserved, must be 0 */
+    int32_t max_len;   /* largest m and n of a request */
+    int32_t alphabet;  /* largest alphabet of a request, 1..256 */
+    int32_t base_rows; /* as in lcs_plan_desc */
+    int32_t tile;      /* as in lcs_plan_desc */
+    int32_t slots;     /* requests that may run on the device at once (1..64) */
+    int32_t max_queue; /* waiting requests held on the host */
+    uint32_t flags;    /* reserved, must be 0 */
 } lcs_server_desc;
 
 typedef struct lcs_result {
-    int64_t tag;          /* caller's tag from lcs_server_submit */
-    int32_t status;       /* LCS_OK or an error code */
-    int32_t length;       /* LCS length */
-    int64_t wit_off;      /* where the witness was written in the caller's arrays */
-    double t_submit;      /* host clock (s) at submit, admission and completion */
-    double t_admit;
-    double t_done;
+    int64_t tag;      /* caller's tag from lcs_server_submit */
+    int32_t status;   /* LCS_OK or an error code (LCS_E_SYMBOL, LCS_E_HIP) */
+    int32_t length;   /* LCS length */
+    double t_submit;  /* host clock, seconds since lcs_server_open */
+    double t_admit;   /* when its device work was enqueued */
+    double t_done;    /* when poll observed its completion */
 } lcs_result;
 
 /*
  * Open a continuous-batching server over a caller-owned device arena of
- * arena_bytes (the memory budget for breakout matrices).  Requests wait on the
- * host until both a slot and enough arena memory are free; each admitted
- * request runs on its slot's stream, so requests overlap on the device.
- * Witnesses go to the caller's device arrays a_idx/b_idx (capacity entries).
+ * arena_bytes: the memory budget for the inputs and breakout matrices of the
+ * requests in flight.  Requests wait on the host in arrival order; the head of
+ * the queue is admitted as soon as a slot is free AND a block of its footprint
+ * can be carved out of the arena (first fit), so requests that arrive while
+ * others run join them on the device, each on its own stream.  The arena and
+ * the outputs stay the caller's; the server holds streams, events, pinned
+ * staging buffers and one plan per slot.
  */
 int32_t lcs_server_open(const lcs_server_desc *desc, void *arena, size_t arena_bytes,
-                        int32_t *a_idx, int32_t *b_idx, int64_t capacity, lcs_server_t *out);
+                        lcs_server_t *out);
 
-/* Device bytes a request of sizes (m, n) occupies while it runs. */
+/* Arena bytes a request of sizes (m, n) occupies while it runs. */
 int32_t lcs_server_footprint(lcs_server_t server, int32_t m, int32_t n, size_t *bytes);
 
 /*
- * Queue one request; a and b are HOST strings (copied at submit).  Returns
- * LCS_E_BUDGET if the request can never fit the arena, LCS_E_AGAIN if the
- * host queue is full.
+ * Queue one request.  a and b are HOST strings (copied at submit); a_idx and
+ * b_idx are device int32 arrays of at least min(m, n) entries that receive the
+ * witness (both NULL: length only).  The request runs on a stream of the
+ * server, so the caller must have no pending device work on a_idx / b_idx
+ * when it submits (e.g. synchronise the stream that allocated or cleared them).  Returns LCS_E_BUDGET if the request can
+ * never fit the arena, LCS_E_AGAIN if the host queue is full, LCS_E_INVAL /
+ * LCS_E_TOO_BIG on bad arguments.
  */
 int32_t lcs_server_submit(lcs_server_t server, int64_t tag, const uint8_t *a, int32_t m,
-                          const uint8_t *b, int32_t n, int32_t alphabet);
+                          const uint8_t *b, int32_t n, int32_t alphabet, int32_t *a_idx,
+                          int32_t *b_idx);
 
 /*
- * Make progress: collect finished requests, then admit waiting ones in
- * arrival order while a slot and arena memory are free.  Up to max_results
- * finished requests are written to results; *count receives how many.
- * Never blocks on the device.
+ * Make progress without blocking on the device: collect finished requests
+ * (their witnesses are then complete in the caller's arrays), then admit
+ * waiting requests in arrival order while a slot and arena memory are free.
+ * Up to max_results finished requests are written to results; *count
+ * receives how many (the others are returned by later polls).
  */
 int32_t lcs_server_poll(lcs_server_t server, lcs_result *results, int32_t max_results,
                         int32_t *count);
 
-/* Requests admitted and not yet collected, and requests still waiting. */
-int32_t lcs_server_pending(lcs_server_t server, int32_t *running, int32_t *waiting);
+/* Requests on the device, requests waiting, arena bytes in use and peak use. */
+int32_t lcs_server_pending(lcs_server_t server, int32_t *running, int32_t *waiting,
+                           size_t *arena_used, size_t *arena_peak);
 
 /* Wait for every running request, then release the server (not the arena). */
 int32_t lcs_server_close(lcs_server_t server);
+
+/*
+ * The admission policy alone, under a virtual clock (no device; for tests):
+ * `count` requests with arrival times, footprints and service times (seconds)
+ * go through the same FIFO queue and first-fit arena as the server, with
+ * `slots` concurrent executions whose completions are simulated.  Writes each
+ * request's admission and completion time and the peak arena use.
+ */
+int32_t lcs_server_simulate(size_t arena_bytes, int32_t slots, int32_t count,
+                            const double *arrival, const size_t *footprint,
+                            const double *service, double *t_admit, double *t_done,
+                            size_t *peak);
 
 #ifdef __cplusplus
 }

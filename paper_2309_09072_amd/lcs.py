@@ -66,8 +66,8 @@ PLAN_PROFILE = 1
 
 class Result(ctypes.Structure):
     _fields_ = [("tag", ctypes.c_int64), ("status", ctypes.c_int32), ("length", ctypes.c_int32),
-                ("wit_off", ctypes.c_int64), ("t_submit", ctypes.c_double),
-                ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double)]
+                ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
+                ("t_done", ctypes.c_double)]
 
 
 _lib = None
@@ -98,12 +98,13 @@ PROTOTYPES = {
     "lcs_batch_status": (_I32, [_P, _P, _P]),
     "lcs_batch_selftest": (_I32, [ctypes.POINTER(BatchDesc), _P, _I32]),
     "lcs_batch_submit": (_I32, [_P, _P, _I32, _P, _I64, _P, _P, _P, _I64, _P, _SZ, _U32, _P]),
-    "lcs_server_open": (_I32, [ctypes.POINTER(ServerDesc), _P, _SZ, _P, _P, _I64, ctypes.POINTER(_P)]),
+    "lcs_server_open": (_I32, [ctypes.POINTER(ServerDesc), _P, _SZ, ctypes.POINTER(_P)]),
     "lcs_server_footprint": (_I32, [_P, _I32, _I32, _PSZ]),
-    "lcs_server_submit": (_I32, [_P, _I64, _P, _I32, _P, _I32, _I32]),
+    "lcs_server_submit": (_I32, [_P, _I64, _P, _I32, _P, _I32, _I32, _P, _P]),
     "lcs_server_poll": (_I32, [_P, _P, _I32, _PI32]),
-    "lcs_server_pending": (_I32, [_P, _PI32, _PI32]),
+    "lcs_server_pending": (_I32, [_P, _PI32, _PI32, _PSZ, _PSZ]),
     "lcs_server_close": (_I32, [_P]),
+    "lcs_server_simulate": (_I32, [_SZ, _I32, _I32, _P, _P, _P, _P, _P, _PSZ]),
 }
 
 
@@ -374,3 +375,89 @@ def run_batch(batch, mode: int = BATCH_PERSISTENT, base_rows: int = 0, tile: int
     if not (mode & BATCH_PER_PAIR):
         b.status(ws)
     return lengths.cpu().numpy(), ai.cpu().numpy(), bi.cpu().numpy(), off
+
+
+
+class Server:
+    """Continuous-batching server (lcs_server_*) over a device arena tensor."""
+
+    def __init__(self, arena, max_len: int, alphabet: int, slots: int = 8, max_queue: int = 1 << 16,
+                 base_rows: int = 0, tile: int = 0):
+        self.desc = ServerDesc(int(max_len), int(alphabet), int(base_rows), int(tile), int(slots),
+                               int(max_queue), 0)
+        h = ctypes.c_void_p()
+        self.arena = arena
+        check(load().lcs_server_open(ctypes.byref(self.desc), _dptr(arena), int(arena.numel()),
+                                     ctypes.byref(h)), "lcs_server_open")
+        self._h = h
+        self._buf = (Result * 256)()
+        self._outs = {}
+
+    def footprint(self, m: int, n: int) -> int:
+        out = ctypes.c_size_t()
+        check(load().lcs_server_footprint(self._h, int(m), int(n), ctypes.byref(out)), "lcs_server_footprint")
+        return int(out.value)
+
+    def submit(self, tag: int, a, b, alphabet: int, a_idx=None, b_idx=None) -> int:
+        """Returns the status (LCS_E_AGAIN / LCS_E_BUDGET are not raised)."""
+        a = np.ascontiguousarray(a, np.uint8)
+        b = np.ascontiguousarray(b, np.uint8)
+        self._outs[int(tag)] = (a_idx, b_idx)
+        st = load().lcs_server_submit(self._h, int(tag), a.ctypes.data_as(ctypes.c_void_p), a.size,
+                                      b.ctypes.data_as(ctypes.c_void_p), b.size, int(alphabet),
+                                      _dptr(a_idx), _dptr(b_idx))
+        if st not in (LCS_OK, -9, -10):
+            check(st, "lcs_server_submit")
+        if st != LCS_OK:
+            self._outs.pop(int(tag), None)
+        return int(st)
+
+    def poll(self):
+        """List of (tag, status, length, t_submit, t_admit, t_done) finished since the last poll."""
+        out = []
+        while True:
+            cnt = ctypes.c_int32()
+            check(load().lcs_server_poll(self._h, ctypes.cast(self._buf, ctypes.c_void_p), 256,
+                                         ctypes.byref(cnt)), "lcs_server_poll")
+            for i in range(cnt.value):
+                r = self._buf[i]
+                out.append((int(r.tag), int(r.status), int(r.length), r.t_submit, r.t_admit, r.t_done))
+                self._outs.pop(int(r.tag), None)
+            if cnt.value < 256:
+                return out
+
+    def pending(self):
+        r, w = ctypes.c_int32(), ctypes.c_int32()
+        u, p = ctypes.c_size_t(), ctypes.c_size_t()
+        check(load().lcs_server_pending(self._h, ctypes.byref(r), ctypes.byref(w), ctypes.byref(u),
+                                        ctypes.byref(p)), "lcs_server_pending")
+        return int(r.value), int(w.value), int(u.value), int(p.value)
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            load().lcs_server_close(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def server_simulate(arena_bytes: int, slots: int, arrival, footprint, service):
+    """Admission policy under a virtual clock: (t_admit, t_done, peak) numpy arrays."""
+    arrival = np.ascontiguousarray(arrival, np.float64)
+    foot = np.ascontiguousarray(footprint, np.uint64)
+    service = np.ascontiguousarray(service, np.float64)
+    ta = np.zeros_like(arrival)
+    td = np.zeros_like(arrival)
+    peak = ctypes.c_size_t()
+    st = load().lcs_server_simulate(int(arena_bytes), int(slots), int(arrival.size),
+                                    arrival.ctypes.data_as(ctypes.c_void_p),
+                                    foot.ctypes.data_as(ctypes.c_void_p),
+                                    service.ctypes.data_as(ctypes.c_void_p),
+                                    ta.ctypes.data_as(ctypes.c_void_p),
+                                    td.ctypes.data_as(ctypes.c_void_p), ctypes.byref(peak))
+    check(st, "lcs_server_simulate")
+    return ta, td, int(peak.value)
