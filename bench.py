@@ -76,6 +76,129 @@ def cpu_baseline(pair, seconds: float):
                 reps, pair.a.size, pair.b.size, el)}
 
 
+def _oracle_check(args):
+    import numpy as np
+    import oracle
+    a, b, L, ai, bi = args
+    Lo, ao, bo = oracle.lcs_witness(a, b)
+    return L == Lo and np.array_equal(ai, ao) and np.array_equal(bi, bo)
+
+
+def oracle_check_many(items, procs=8):
+    """Every (a, b, L, a_idx, b_idx) against the oracle, on `procs` host processes."""
+    import multiprocessing as mp
+    with mp.get_context("fork").Pool(procs) as pool:
+        return all(pool.imap_unordered(_oracle_check, items, chunksize=16))
+
+
+def bench_batched(reps: int):
+    """Many pairs of uneven length: one persistent launch vs one pair per launch."""
+    import numpy as np
+    import torch
+    import paper_2309_09072_amd.synth as synth
+    from paper_2309_09072_amd import lcs
+    batch = synth.batch_mixed()
+    maxlen = int(max(batch.m.max(), batch.n.max()))
+    plan = lcs.Batch(batch.count, maxlen, batch.sigma, 64, 32, slots=512)
+    ws = lcs.alloc_workspace(plan.workspace_bytes)
+    sym = lcs.device_bytes(batch.symbols)
+    off = lcs.Batch.witness_offsets(batch.m, batch.n)
+    lengths = torch.zeros(batch.count, dtype=torch.int32, device="cuda")
+    ai = torch.zeros(int(off[-1]), dtype=torch.int32, device="cuda")
+    bi = torch.zeros(int(off[-1]), dtype=torch.int32, device="cuda")
+    out = {"workload": batch.name, "pairs": batch.count, "cells": batch.cells, "seed": batch.seed,
+           "slots": 512, "workspace_GB": round(ws.numel() / 1e9, 2)}
+    for name, mode in (("staged_graph", lcs.BATCH_STAGED | lcs.BATCH_GRAPH),
+                       ("persistent_graph", lcs.BATCH_PERSISTENT | lcs.BATCH_GRAPH),
+                       ("one_pair_per_launch", lcs.BATCH_PER_PAIR)):
+        plan.submit(sym, batch.a_off, batch.b_off, batch.m, batch.n, ws, lengths, ai, bi, mode)
+        torch.cuda.synchronize()
+        n = reps if mode & lcs.BATCH_STAGED else 1
+        t0 = time.perf_counter()
+        for _ in range(n):
+            plan.submit(sym, batch.a_off, batch.b_off, batch.m, batch.n, ws, lengths, ai, bi, mode)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / n
+        if not (mode & (lcs.BATCH_PER_PAIR | lcs.BATCH_STAGED)):
+            plan.status(ws)
+        L = lengths.cpu().numpy()
+        A, B = ai.cpu().numpy(), bi.cpu().numpy()
+        items = [(batch.pair(p)[0], batch.pair(p)[1], int(L[p]), A[off[p]:off[p] + L[p]],
+                  B[off[p]:off[p] + L[p]]) for p in range(batch.count)]
+        exact = oracle_check_many(items)
+        out[name] = {"s_per_batch": round(dt, 4), "cells_per_s": batch.cells / dt, "exact_match": exact}
+        log("batched %s: %.3f s per batch, %.3g cells/s, exact=%s" % (name, dt, batch.cells / dt, exact))
+    out["speedup_staged_vs_per_pair"] = round(
+        out["one_pair_per_launch"]["s_per_batch"] / out["staged_graph"]["s_per_batch"], 2)
+    out["speedup_persistent_vs_per_pair"] = round(
+        out["one_pair_per_launch"]["s_per_batch"] / out["persistent_graph"]["s_per_batch"], 2)
+    del ws
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_serving(count: int, budget_gb: float, slots: int):
+    """Poisson arrivals (lengths log-uniform 128..8192, alphabet 4 or 20, 30% related
+    pairs at a 10% edit rate), admission by arena memory; p50/p99 latency + cells/s."""
+    import numpy as np
+    import torch
+    import paper_2309_09072_amd.synth as synth
+    from paper_2309_09072_amd import lcs
+    arena = lcs.alloc_workspace(int(budget_gb * (1 << 30)))
+
+    def run(rate):
+        reqs = synth.serving_requests(count, rate=rate)
+        srv = lcs.Server(arena, 8192, 20, slots=slots, max_queue=count + 1)
+        bufs = {}
+        for r in reqs:
+            cap = max(1, min(r.a.size, r.b.size))
+            bufs[r.rid] = (torch.empty(cap, dtype=torch.int32, device="cuda"),
+                           torch.empty(cap, dtype=torch.int32, device="cuda"))
+        torch.cuda.synchronize()
+        res = {}
+        t0 = time.perf_counter()
+        i = 0
+        while len(res) < len(reqs):
+            now = time.perf_counter() - t0
+            while i < len(reqs) and (rate <= 0 or reqs[i].arrival <= now):
+                r = reqs[i]
+                st = srv.submit(r.rid, r.a, r.b, r.sigma, *bufs[r.rid])
+                assert st == 0, st
+                i += 1
+            for tag, status, length, ts, tadm, tdone in srv.poll():
+                res[tag] = (status, length, ts, tadm, tdone)
+            time.sleep(0.0002)
+        wall = time.perf_counter() - t0
+        peak = srv.pending()[3]
+        srv.close()
+        lat = np.array([res[r.rid][4] - res[r.rid][2] for r in reqs])
+        cells = sum(int(r.a.size) * int(r.b.size) for r in reqs)
+        return reqs, res, bufs, wall, lat, cells, peak
+
+    reqs, res, bufs, wall, lat, cells, peak = run(0.0)      # closed loop: saturation rate
+    r_sat = count / wall
+    out = {"workload": "serving-poisson-128..8192", "requests": count, "slots": slots,
+           "budget_GB": budget_gb, "saturation_req_per_s": round(r_sat, 1),
+           "saturation_cells_per_s": cells / wall}
+    for frac in (0.7,):
+        reqs, res, bufs, wall, lat, cells, peak = run(frac * r_sat)
+        items = []
+        for r in reqs:
+            st, L = res[r.rid][0], res[r.rid][1]
+            ai, bi = bufs[r.rid]
+            items.append((r.a, r.b, L if st == 0 else -1, ai[:L].cpu().numpy(), bi[:L].cpu().numpy()))
+        exact = oracle_check_many(items)
+        out["at_%d_pct" % int(frac * 100)] = {
+            "rate_req_per_s": round(frac * r_sat, 1), "p50_ms": round(1e3 * float(np.percentile(lat, 50)), 3),
+            "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 3), "cells_per_s": cells / wall,
+            "peak_arena_GB": round(peak / 1e9, 3), "exact_match": exact}
+        log("serving at %.0f%% of saturation: p50 %.2f ms p99 %.2f ms, exact=%s" % (
+            frac * 100, 1e3 * np.percentile(lat, 50), 1e3 * np.percentile(lat, 99), exact))
+    del arena
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -86,6 +209,10 @@ def main():
     ap.add_argument("--tile", type=int, default=32)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the batched (4096 pairs) and serving workloads")
+    ap.add_argument("--batch-reps", type=int, default=3)
+    ap.add_argument("--serve-requests", type=int, default=400)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also launch one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -221,6 +348,11 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(pair, args.cpu_seconds)
+    if not args.no_extras:
+        del ws
+        torch.cuda.empty_cache()
+        out["batched"] = bench_batched(args.batch_reps)
+        out["serving"] = bench_serving(args.serve_requests, 64.0, 16)
     print(json.dumps(out), flush=True)
     if not exact:
         sys.exit(1)

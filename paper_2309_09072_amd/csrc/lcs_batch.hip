@@ -3,6 +3,15 @@
 // LCS_BATCH_PER_PAIR runs the per-level kernels of the single-pair path pair
 // after pair on one stream (the one-pair-per-launch baseline).
 //
+// LCS_BATCH_STAGED (the fast mode) runs one launch per step of the method for
+// all pairs at once: next-match tables, base strips, for every combine level
+// its anchors then its bracketed (tile x weight-chunk) blocks, lengths, trace
+// splits level by level, base-strip traces.  Every launch is a queue of
+// independent work-groups over all pairs' items, so pairs of uneven length fill
+// the device together; the kernel boundaries order the steps (no in-kernel
+// waits, no cross-die cache maintenance per item).  Pairs are packed into the
+// arena in waves, and the whole sequence can be replayed as one hipGraph.
+//
 // LCS_BATCH_PERSISTENT runs the whole batch -- every pair's next-match tables,
 // base strips, combine levels, length and witness trace -- in ONE launch of a
 // persistent kernel: as many work-groups as fit on the device at once pop task
@@ -16,6 +25,7 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 #include <vector>
 
@@ -108,6 +118,136 @@ union PersistentSmem {
     int32_t leaf[65 * 65];
 };
 
+// fine-grained task kinds of the staged mode (coarse ones are in lcs_sched.h)
+constexpr int32_t ST_NM_SYM = 16;       // u = symbol
+constexpr int32_t ST_BASE_BLK = 17;     // u = strip * vertex_blocks + block
+constexpr int32_t ST_BRACKET_CH = 18;   // u = (q * tiles + tile) * chunks + chunk
+
+__device__ __forceinline__ int32_t vertex_blocks(int32_t n) { return (n + 2 + kBlock - 1) / kBlock; }
+__device__ __forceinline__ int32_t level_chunks(const PairRec &P, int32_t l) {
+    const int32_t H = 2 * P.lev[l - 1].hfull + 1;
+    return imax(1, (H - 1 + kJChunk - 1) / kJChunk);
+}
+
+// One task of pair p (all threads of the work-group).
+template <int H0>
+__device__ void exec_task(const BatchArgs &A, int32_t p, int32_t kind, int32_t l, int32_t u,
+                          PersistentSmem &sm) {
+    const PairRec &P = A.pairs[p];
+    uint8_t *ws = A.ws + P.ws_off;
+    int32_t *hdr = reinterpret_cast<int32_t *>(ws + P.off_hdr);
+    int32_t *nm = reinterpret_cast<int32_t *>(ws + P.off_nm);
+    const uint8_t *a = A.symbols + P.a_off;
+    const uint8_t *b = A.symbols + P.b_off;
+    switch (kind) {
+        case ST_EMPTY:
+            if (threadIdx.x == 0) A.lengths[p] = 0;
+            break;
+        case ST_NM:
+        case ST_NM_SYM: {
+            if (kind == ST_NM || u == 0)
+                for (int32_t i = threadIdx.x; i < kHeaderWords; i += kBlock) hdr[i] = 0;
+            const int32_t x0 = kind == ST_NM ? 0 : u, x1 = kind == ST_NM ? A.sigma : u + 1;
+            for (int32_t x = x0; x < x1; ++x)
+                nextmatch_block(b, P.n, x, nm + (size_t)x * (size_t)(P.n + 2), sm.nm);
+            break;
+        }
+        case ST_BASE:
+        case ST_BASE_BLK: {
+            const LevelGeom &g = P.lev[0];
+            const int32_t nvb = vertex_blocks(P.n);
+            const int32_t s0 = kind == ST_BASE ? u : u / nvb;
+            const bool last = (s0 == g.nstrips - 1);
+            const int32_t h = last ? g.hlast : H0;
+            int32_t *out = reinterpret_cast<int32_t *>(ws + (last ? g.last_off : g.base)) +
+                           (last ? 0 : (size_t)s0 * strip_elems(P.n, H0));
+            const int32_t vb0 = kind == ST_BASE ? 0 : u - s0 * nvb;
+            const int32_t vb1 = kind == ST_BASE ? nvb : vb0 + 1;
+            for (int32_t vb = vb0; vb < vb1; ++vb)
+                base_strip_block<H0>(a + (size_t)s0 * H0, h, P.n, A.sigma, nm, out, vb * kBlock, hdr,
+                                     sm.base);
+            break;
+        }
+        case ST_ANCHOR: {
+            const CombineArgs c = pair_combine_args(P, ws, l, A.tile);
+            const int32_t q = u / P.nanch, an = u - q * P.nanch;
+            const StripRef U = child_strip(c, 2 * q), L = child_strip(c, 2 * q + 1);
+            int32_t *G = parent_strip(c, q);
+            anchor_block(U.d, U.h, L.d, L.h, G, P.n, anchor_vertex(an, A.tile, P.n),
+                         c.anch + ((size_t)q * c.nanch + an) * (size_t)c.hs, sm.anchor);
+            if (an == c.nanch - 1) {
+                const int32_t H = U.h + L.h + 1;
+                int32_t *srow = G + (size_t)(P.n + 1) * H;
+                for (int32_t j = threadIdx.x; j < H; j += kBlock) srow[j] = P.n + 1;
+            }
+            break;
+        }
+        case ST_BRACKET:
+        case ST_BRACKET_CH: {
+            const CombineArgs c = pair_combine_args(P, ws, l, A.tile);
+            const int32_t ntile = P.nanch - 1;
+            const int32_t nchl = level_chunks(P, l);
+            int32_t q, tl, ch0, ch1;
+            if (kind == ST_BRACKET) {
+                q = u / ntile;
+                tl = u - q * ntile;
+                ch0 = 0;
+                ch1 = 1 << 30;
+            } else {
+                const int32_t qt = u / nchl;
+                q = qt / ntile;
+                tl = qt - q * ntile;
+                ch0 = u - qt * nchl;
+                ch1 = ch0 + 1;
+            }
+            const StripRef U = child_strip(c, 2 * q), L = child_strip(c, 2 * q + 1);
+            int32_t *G = parent_strip(c, q);
+            const int32_t H = U.h + L.h + 1;
+            const int32_t nch = imax(1, (H - 1 + kJChunk - 1) / kJChunk);
+            const int32_t i0 = tl * A.tile;
+            const int32_t len = imin(A.tile, P.n - i0);
+            const int32_t *Ka = c.anch + ((size_t)q * c.nanch + tl) * (size_t)c.hs;
+            const int32_t *Kb = c.anch + ((size_t)q * c.nanch + tl + 1) * (size_t)c.hs;
+            for (int32_t ch = ch0; ch < imin(ch1, nch); ++ch) {
+                const int32_t j0 = ch * kJChunk;
+                const int32_t jn = (ch == nch - 1) ? H - j0 : kJChunk;
+                bracket_block(U.d, U.h, L.d, L.h, G, P.n, i0, len, j0, jn, Ka, Kb, sm.bracket);
+            }
+            break;
+        }
+        case ST_LENGTH: {
+            const LevelGeom &top = P.lev[P.nlev - 1];
+            length_block(reinterpret_cast<const int32_t *>(ws + top.last_off), P.m, P.n, hdr,
+                         reinterpret_cast<int4 *>(ws + P.node_off[P.nlev - 1]), sm.len);
+            if (threadIdx.x == 0) A.lengths[p] = (hdr[0] & kErrSymbol) ? LCS_E_SYMBOL : hdr[1];
+            break;
+        }
+        case ST_SPLIT: {
+            const CombineArgs c = pair_combine_args(P, ws, l, A.tile);
+            const int4 *nin = reinterpret_cast<const int4 *>(ws + P.node_off[l]);
+            int4 *nout = reinterpret_cast<int4 *>(ws + P.node_off[l - 1]);
+            const int4 node = nin[u];
+            if (2 * u + 1 >= c.nc) {
+                if (threadIdx.x == 0) nout[2 * u] = node;
+            } else {
+                const StripRef U = child_strip(c, 2 * u), L = child_strip(c, 2 * u + 1);
+                trace_split_block(U.d, U.h, L.d, L.h, P.n, node, nout + 2 * u, nout + 2 * u + 1, hdr,
+                                  sm.split);
+            }
+            break;
+        }
+        case ST_LEAF: {
+            const LevelGeom &g = P.lev[0];
+            const int32_t h = (u == g.nstrips - 1) ? g.hlast : H0;
+            const int4 *nodes = reinterpret_cast<const int4 *>(ws + P.node_off[0]);
+            trace_leaf_block<H0>(a + (size_t)u * H0, h, P.n, A.sigma, nm, nodes[u], u * H0,
+                                 A.a_idx + P.wit_off, A.b_idx + P.wit_off, P.m < P.n ? P.m : P.n, hdr,
+                                 sm.leaf);
+            break;
+        }
+    }
+}
+
 template <int H0>
 __global__ void __launch_bounds__(kBlock) k_persistent(BatchArgs A) {
     __shared__ PersistentSmem sm;
@@ -129,101 +269,42 @@ __global__ void __launch_bounds__(kBlock) k_persistent(BatchArgs A) {
         __syncthreads();
         const int32_t kind = s_task.kind;
         if (kind < 0) break;
-        const int32_t p = s_task.pair, l = s_task.level, u = s_task.u;
-        const PairRec &P = A.pairs[p];
-        uint8_t *ws = A.ws + P.ws_off;
-        int32_t *hdr = reinterpret_cast<int32_t *>(ws + P.off_hdr);
-        int32_t *nm = reinterpret_cast<int32_t *>(ws + P.off_nm);
-        const uint8_t *a = A.symbols + P.a_off;
-        const uint8_t *b = A.symbols + P.b_off;
-        if (s_ok) switch (kind) {
-            case ST_EMPTY:
-                if (threadIdx.x == 0) A.lengths[p] = 0;
-                break;
-            case ST_NM:
-                for (int32_t i = threadIdx.x; i < kHeaderWords; i += kBlock) hdr[i] = 0;
-                for (int32_t x = 0; x < A.sigma; ++x)
-                    nextmatch_block(b, P.n, x, nm + (size_t)x * (size_t)(P.n + 2), sm.nm);
-                break;
-            case ST_BASE: {
-                const LevelGeom &g = P.lev[0];
-                const bool last = (u == g.nstrips - 1);
-                const int32_t h = last ? g.hlast : H0;
-                int32_t *out = reinterpret_cast<int32_t *>(ws + (last ? g.last_off : g.base)) +
-                               (last ? 0 : (size_t)u * strip_elems(P.n, H0));
-                for (int32_t v0 = 0; v0 < P.n + 2; v0 += kBlock)
-                    base_strip_block<H0>(a + (size_t)u * H0, h, P.n, A.sigma, nm, out, v0, hdr, sm.base);
-                break;
-            }
-            case ST_ANCHOR: {
-                const CombineArgs c = pair_combine_args(P, ws, l, A.tile);
-                const int32_t q = u / P.nanch, an = u - q * P.nanch;
-                const StripRef U = child_strip(c, 2 * q), L = child_strip(c, 2 * q + 1);
-                int32_t *G = parent_strip(c, q);
-                anchor_block(U.d, U.h, L.d, L.h, G, P.n, anchor_vertex(an, A.tile, P.n),
-                             c.anch + ((size_t)q * c.nanch + an) * (size_t)c.hs, sm.anchor);
-                if (an == c.nanch - 1) {
-                    const int32_t H = U.h + L.h + 1;
-                    int32_t *srow = G + (size_t)(P.n + 1) * H;
-                    for (int32_t j = threadIdx.x; j < H; j += kBlock) srow[j] = P.n + 1;
-                }
-                break;
-            }
-            case ST_BRACKET: {
-                const CombineArgs c = pair_combine_args(P, ws, l, A.tile);
-                const int32_t ntile = P.nanch - 1;
-                const int32_t q = u / ntile, tl = u - q * ntile;
-                const StripRef U = child_strip(c, 2 * q), L = child_strip(c, 2 * q + 1);
-                int32_t *G = parent_strip(c, q);
-                const int32_t H = U.h + L.h + 1;
-                const int32_t nch = imax(1, (H - 1 + kJChunk - 1) / kJChunk);
-                const int32_t i0 = tl * A.tile;
-                const int32_t len = imin(A.tile, P.n - i0);
-                const int32_t *Ka = c.anch + ((size_t)q * c.nanch + tl) * (size_t)c.hs;
-                const int32_t *Kb = c.anch + ((size_t)q * c.nanch + tl + 1) * (size_t)c.hs;
-                for (int32_t ch = 0; ch < nch; ++ch) {
-                    const int32_t j0 = ch * kJChunk;
-                    const int32_t jn = (ch == nch - 1) ? H - j0 : kJChunk;
-                    bracket_block(U.d, U.h, L.d, L.h, G, P.n, i0, len, j0, jn, Ka, Kb, sm.bracket);
-                }
-                break;
-            }
-            case ST_LENGTH: {
-                const LevelGeom &top = P.lev[P.nlev - 1];
-                length_block(reinterpret_cast<const int32_t *>(ws + top.last_off), P.m, P.n, hdr,
-                             reinterpret_cast<int4 *>(ws + P.node_off[P.nlev - 1]), sm.len);
-                if (threadIdx.x == 0) A.lengths[p] = (hdr[0] & kErrSymbol) ? LCS_E_SYMBOL : hdr[1];
-                break;
-            }
-            case ST_SPLIT: {
-                const CombineArgs c = pair_combine_args(P, ws, l, A.tile);
-                const int4 *nin = reinterpret_cast<const int4 *>(ws + P.node_off[l]);
-                int4 *nout = reinterpret_cast<int4 *>(ws + P.node_off[l - 1]);
-                const int4 node = nin[u];
-                if (2 * u + 1 >= c.nc) {
-                    if (threadIdx.x == 0) nout[2 * u] = node;
-                } else {
-                    const StripRef U = child_strip(c, 2 * u), L = child_strip(c, 2 * u + 1);
-                    trace_split_block(U.d, U.h, L.d, L.h, P.n, node, nout + 2 * u, nout + 2 * u + 1,
-                                      hdr, sm.split);
-                }
-                break;
-            }
-            case ST_LEAF: {
-                const LevelGeom &g = P.lev[0];
-                const int32_t h = (u == g.nstrips - 1) ? g.hlast : H0;
-                const int4 *nodes = reinterpret_cast<const int4 *>(ws + P.node_off[0]);
-                trace_leaf_block<H0>(a + (size_t)u * H0, h, P.n, A.sigma, nm, nodes[u], u * H0,
-                                     A.a_idx + P.wit_off, A.b_idx + P.wit_off,
-                                     P.m < P.n ? P.m : P.n, hdr, sm.leaf);
-                break;
-            }
-        }
+        if (s_ok) exec_task<H0>(A, s_task.pair, kind, s_task.level, s_task.u, sm);
         __syncthreads();
         if (threadIdx.x == 0)
             for (int32_t i = 0; i < s_task.nsig; ++i) signal(A.ctr + s_task.sig_idx[i]);
         __syncthreads();
     }
+}
+
+// One step of the staged mode: the items of every participating pair, as a
+// queue of work-groups.  Item t belongs to the pair j with
+// first[j] <= t < first[j + 1] (binary search).
+struct StageArgs {
+    int32_t kind, level, npairs;
+    const int32_t *pair;    // participating pairs
+    const int64_t *first;   // their first item, plus the total at [npairs]
+};
+
+template <int H0>
+__global__ void __launch_bounds__(kBlock) k_stage(BatchArgs A, StageArgs S) {
+    __shared__ PersistentSmem sm;
+    __shared__ int32_t s_pu[2];
+    const int64_t t = blockIdx.x;
+    if (threadIdx.x == 0) {
+        int32_t lo = 0, hi = S.npairs - 1;
+        while (lo < hi) {
+            const int32_t mid = (lo + hi + 1) >> 1;
+            if (S.first[mid] <= t)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        s_pu[0] = S.pair[lo];
+        s_pu[1] = (int32_t)(t - S.first[lo]);
+    }
+    __syncthreads();
+    exec_task<H0>(A, s_pu[0], S.kind, S.level, s_pu[1], sm);
 }
 
 __global__ void k_fill(int32_t *p, int64_t count, int32_t value) {
@@ -251,6 +332,8 @@ struct lcs_batch_s {
     hipGraph_t graph = nullptr;
     uint64_t gkey = 0;
     hipEvent_t copied = nullptr;    // the last copy out of host_pairs has run
+    int64_t off_stage = 0, stage_bytes = 0;
+    uint8_t *host_stage = nullptr;  // pinned staging of the staged-mode item tables
 };
 
 static int32_t counters_per_pair(int32_t max_len, int32_t h0) {
@@ -288,6 +371,13 @@ static int32_t plan_sizes(const lcs_batch_desc *desc, lcs_batch_s *b) {
     off = align256(off + (int64_t)sizeof(PairRec) * d.max_pairs);
     b->off_ctr = off;
     off = align256(off + 4 * (int64_t)b->ctr_per_pair * d.max_pairs);
+    // staged mode: per step, the participating pairs (int32) and their first
+    // items (int64, one extra entry per wave)
+    // a pair appears at most once per step; each listing costs 4 + 8 bytes, a
+    // wave adds one 8-byte total and 8 bytes of alignment per step
+    b->stage_bytes = (int64_t)kMaxStages * 32 * ((int64_t)d.max_pairs + 2) + 4096;
+    b->off_stage = off;
+    off = align256(off + b->stage_bytes);
     b->off_slots = off;
     off += b->slot_bytes * d.slots;
     b->total = off;
@@ -306,6 +396,12 @@ extern "C" int32_t lcs_batch_plan(const lcs_batch_desc *desc, lcs_batch_t *out, 
     }
     if (hipHostMalloc(reinterpret_cast<void **>(&b->host_pairs), sizeof(PairRec) * b->d.max_pairs,
                       hipHostMallocDefault) != hipSuccess) {
+        delete b;
+        return LCS_E_NOMEM;
+    }
+    if (hipHostMalloc(reinterpret_cast<void **>(&b->host_stage), b->stage_bytes, hipHostMallocDefault) !=
+        hipSuccess) {
+        hipHostFree(b->host_pairs);
         delete b;
         return LCS_E_NOMEM;
     }
@@ -343,6 +439,7 @@ extern "C" int32_t lcs_batch_destroy(lcs_batch_t b) {
         hipEventDestroy(b->copied);
     }
     if (b->host_pairs) hipHostFree(b->host_pairs);
+    if (b->host_stage) hipHostFree(b->host_stage);
     delete b;
     return LCS_OK;
 }
@@ -412,7 +509,9 @@ extern "C" int32_t lcs_batch_submit(lcs_batch_t B, const lcs_pair_desc *pairs, i
                                     void *stream) {
     if (!B || (count > 0 && (!pairs || !lengths)) || count < 0 || !workspace) return LCS_E_INVAL;
     if (count > B->d.max_pairs) return LCS_E_TOO_BIG;
-    if ((mode & ~(uint32_t)(LCS_BATCH_PER_PAIR | LCS_BATCH_GRAPH)) != 0) return LCS_E_INVAL;
+    if ((mode & ~(uint32_t)(LCS_BATCH_PER_PAIR | LCS_BATCH_GRAPH | LCS_BATCH_STAGED)) != 0 ||
+        ((mode & LCS_BATCH_PER_PAIR) && (mode & LCS_BATCH_STAGED)))
+        return LCS_E_INVAL;
     if ((size_t)B->total > workspace_bytes) return LCS_E_WORKSPACE;
     if (reinterpret_cast<uintptr_t>(workspace) & 255) return LCS_E_INVAL;
     int64_t wit = 0;
@@ -449,8 +548,8 @@ extern "C" int32_t lcs_batch_submit(lcs_batch_t B, const lcs_pair_desc *pairs, i
         return LCS_OK;
     }
 
-    // persistent: pair records, counters, one launch.  The previous submit's
-    // copy of the staging records must have run before they are rewritten.
+    // The previous submit's copy of the staging records must have run before
+    // they are rewritten.
     if (hipEventSynchronize(B->copied) != hipSuccess) return LCS_E_HIP;
     int64_t woff = 0, tbase = 0;
     uint64_t key = 0xcbf29ce484222325ull;
@@ -458,6 +557,85 @@ extern "C" int32_t lcs_batch_submit(lcs_batch_t B, const lcs_pair_desc *pairs, i
         if (!make_pair(B, pairs[p], p, woff, tbase, B->host_pairs[p])) return LCS_E_TOO_BIG;
         woff += pairs[p].m < pairs[p].n ? pairs[p].m : pairs[p].n;
         tbase += B->host_pairs[p].ntasks;
+    }
+    // staged mode: pack the pairs' layouts into the slot area in waves and
+    // list, per step, the items of every pair of the wave
+    struct StageLaunch {
+        int32_t kind, level, npairs;
+        int64_t pair_off, first_off, items;  // byte offsets in the stage tables
+    };
+    std::vector<StageLaunch> launches;
+    if (mode & LCS_BATCH_STAGED) {
+        const int64_t arena = B->slot_bytes * B->d.slots;
+        std::vector<int32_t> wave_start(1, 0);
+        int64_t used = 0;
+        for (int32_t p = 0; p < count; ++p) {
+            PairRec &R = B->host_pairs[p];
+            const int64_t need = align256(R.total);
+            if (used + need > arena) {
+                wave_start.push_back(p);
+                used = 0;
+            }
+            R.ws_off = B->off_slots + used;
+            used += need;
+        }
+        wave_start.push_back(count);
+        int64_t soff = 0;
+        uint8_t *tab = B->host_stage;
+        for (size_t w = 0; w + 1 < wave_start.size(); ++w) {
+            const int32_t p0 = wave_start[w], p1 = wave_start[w + 1];
+            int32_t lmax = 0;
+            for (int32_t p = p0; p < p1; ++p) lmax = std::max(lmax, B->host_pairs[p].nlev - 1);
+            auto add_stage = [&](int32_t kind, int32_t level, auto items_of) {
+                std::vector<int32_t> ps;
+                std::vector<int64_t> fs;
+                int64_t tot = 0;
+                for (int32_t p = p0; p < p1; ++p) {
+                    const int64_t c = items_of(B->host_pairs[p]);
+                    if (c <= 0) continue;
+                    ps.push_back(p);
+                    fs.push_back(tot);
+                    tot += c;
+                }
+                if (ps.empty()) return;
+                fs.push_back(tot);
+                if (soff + 12 * (int64_t)ps.size() + 32 > B->stage_bytes) {
+                    soff = B->stage_bytes + 1;  // reported after the loop; nothing written
+                    return;
+                }
+                StageLaunch sl{kind, level, (int32_t)ps.size(), soff, 0, tot};
+                memcpy(tab + soff, ps.data(), 4 * ps.size());
+                soff = (soff + 4 * (int64_t)ps.size() + 7) & ~(int64_t)7;
+                sl.first_off = soff;
+                memcpy(tab + soff, fs.data(), 8 * fs.size());
+                soff += 8 * (int64_t)fs.size();
+                launches.push_back(sl);
+            };
+            const int32_t sig = B->d.alphabet;
+            add_stage(ST_EMPTY, 0, [](const PairRec &R) -> int64_t { return R.nlev == 0 ? 1 : 0; });
+            add_stage(ST_NM_SYM, 0, [sig](const PairRec &R) -> int64_t { return R.nlev ? sig : 0; });
+            add_stage(ST_BASE_BLK, 0, [](const PairRec &R) -> int64_t {
+                return R.nlev ? (int64_t)R.lev[0].nstrips * ((R.n + 2 + kBlock - 1) / kBlock) : 0;
+            });
+            for (int32_t l = 1; l <= lmax; ++l) {
+                add_stage(ST_ANCHOR, l, [l](const PairRec &R) -> int64_t {
+                    return R.nlev > l ? (int64_t)R.lev[l].npairs * R.nanch : 0;
+                });
+                add_stage(ST_BRACKET_CH, l, [l](const PairRec &R) -> int64_t {
+                    if (R.nlev <= l) return 0;
+                    const int32_t H = 2 * R.lev[l - 1].hfull + 1;
+                    const int32_t nch = std::max(1, (H - 1 + kJChunk - 1) / kJChunk);
+                    return (int64_t)R.lev[l].npairs * (R.nanch - 1) * nch;
+                });
+            }
+            add_stage(ST_LENGTH, 0, [](const PairRec &R) -> int64_t { return R.nlev ? 1 : 0; });
+            for (int32_t l = lmax; l >= 1; --l)
+                add_stage(ST_SPLIT, l, [l](const PairRec &R) -> int64_t {
+                    return R.nlev > l ? R.lev[l].nstrips : 0;
+                });
+            add_stage(ST_LEAF, 0, [](const PairRec &R) -> int64_t { return R.nlev ? R.lev[0].nstrips : 0; });
+        }
+        if (soff > B->stage_bytes) return LCS_E_TOO_BIG;
     }
     BatchArgs A;
     A.pairs = reinterpret_cast<const PairRec *>(ws + B->off_pairs);
@@ -481,6 +659,31 @@ extern "C" int32_t lcs_batch_submit(lcs_batch_t B, const lcs_pair_desc *pairs, i
         if (hipMemcpyAsync(ws + B->off_pairs, B->host_pairs, sizeof(PairRec) * count,
                            hipMemcpyHostToDevice, st) != hipSuccess)
             return LCS_E_HIP;
+        if (mode & LCS_BATCH_STAGED) {
+            int64_t tb = 0;
+            for (const auto &sl : launches) tb = std::max(tb, sl.first_off + 8 * (int64_t)(sl.npairs + 1));
+            if (tb > 0 && hipMemcpyAsync(ws + B->off_stage, B->host_stage, tb, hipMemcpyHostToDevice, st) !=
+                              hipSuccess)
+                return LCS_E_HIP;
+            if (hipEventRecord(B->copied, st) != hipSuccess) return LCS_E_HIP;
+            for (const auto &sl : launches) {
+                StageArgs S;
+                S.kind = sl.kind;
+                S.level = sl.level;
+                S.npairs = sl.npairs;
+                S.pair = reinterpret_cast<const int32_t *>(ws + B->off_stage + sl.pair_off);
+                S.first = reinterpret_cast<const int64_t *>(ws + B->off_stage + sl.first_off);
+                if (sl.items >= (int64_t)1 << 31) return LCS_E_TOO_BIG;
+                const dim3 grid((unsigned)sl.items);
+                switch (B->d.base_rows) {
+                    case 16: hipLaunchKernelGGL(k_stage<16>, grid, dim3(kBlock), 0, st, A, S); break;
+                    case 32: hipLaunchKernelGGL(k_stage<32>, grid, dim3(kBlock), 0, st, A, S); break;
+                    default: hipLaunchKernelGGL(k_stage<64>, grid, dim3(kBlock), 0, st, A, S); break;
+                }
+                if (hipGetLastError() != hipSuccess) return LCS_E_HIP;
+            }
+            return LCS_OK;
+        }
         if (hipEventRecord(B->copied, st) != hipSuccess) return LCS_E_HIP;
         hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, st, reinterpret_cast<int32_t *>(ws + B->off_ctl),
                            (int64_t)16, 0);
@@ -503,6 +706,7 @@ extern "C" int32_t lcs_batch_submit(lcs_batch_t B, const lcs_pair_desc *pairs, i
     key = mix(key, (uint64_t)(uintptr_t)lengths);
     key = mix(key, (uint64_t)(uintptr_t)a_idx);
     key = mix(key, (uint64_t)tbase);
+    key = mix(key, (uint64_t)mode);
     if (!B->gexec || B->gkey != key) {
         if (B->gexec) hipGraphExecDestroy(B->gexec);
         if (B->graph) hipGraphDestroy(B->graph);

@@ -51,6 +51,27 @@ def test_persistent_matches_oracle(base_rows, tile, slots):
     check(batch, *res)
 
 
+@pytest.mark.parametrize("base_rows,tile,slots", [(16, 8, 2), (32, 32, 0), (64, 16, 1)])
+def test_staged_matches_oracle(base_rows, tile, slots):
+    """Staged launches; small slot areas force the pairs into several waves."""
+    batch = mixed_small(60, 50 + base_rows)
+    say("staged", base_rows, tile, slots)
+    res = L.run_batch(batch, L.BATCH_STAGED, base_rows, tile, slots)
+    check(batch, *res)
+
+
+def test_staged_graph_replays():
+    batch = mixed_small(40, 78)
+    plan = L.Batch(batch.count, 300, 4, 32, 16, 4)
+    ws = L.alloc_workspace(plan.workspace_bytes)
+    r1 = L.run_batch(batch, L.BATCH_PER_PAIR, planned=plan, ws=ws)
+    check(batch, *r1)
+    for rep in range(3):
+        r2 = L.run_batch(batch, L.BATCH_STAGED | L.BATCH_GRAPH, planned=plan, ws=ws)
+        for x, y in zip(r1, r2):
+            assert np.array_equal(x, y), "replay %d differs" % rep
+
+
 def test_per_pair_and_graph_agree():
     batch = mixed_small(40, 77)
     plan = L.Batch(batch.count, 300, 4, 32, 16, 5)
@@ -81,5 +102,6 @@ def test_mixed_workload_sample():
     """512 pairs of the 64..2048 mixed workload (half unrelated, half mutated copies)."""
     batch = synth.batch_mixed(count=512, seed=synth.SEED_BASE + 40)
     say("mixed 512 pairs, cells", batch.cells)
-    res = L.run_batch(batch, L.BATCH_PERSISTENT, 64, 32, 0)
-    check(batch, *res)
+    for mode in (L.BATCH_STAGED, L.BATCH_PERSISTENT):
+        res = L.run_batch(batch, mode, 64, 32, 0)
+        check(batch, *res)
