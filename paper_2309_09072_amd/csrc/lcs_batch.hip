@@ -131,7 +131,7 @@ __device__ __forceinline__ int32_t level_chunks(const PairRec &P, int32_t l) {
 
 // One task of pair p (all threads of the work-group).
 template <int H0>
-__device__ void exec_task(const BatchArgs &A, int32_t p, int32_t kind, int32_t l, int32_t u,
+__device__ __forceinline__ void exec_task(const BatchArgs &A, int32_t p, int32_t kind, int32_t l, int32_t u,
                           PersistentSmem &sm) {
     const PairRec &P = A.pairs[p];
     uint8_t *ws = A.ws + P.ws_off;
@@ -286,7 +286,9 @@ struct StageArgs {
     const int64_t *first;   // their first item, plus the total at [npairs]
 };
 
-template <int H0>
+// Instantiated per step kind, so each step gets its own register allocation
+// (a kernel that could run any step would carry the largest one everywhere).
+template <int H0, int KIND>
 __global__ void __launch_bounds__(kBlock) k_stage(BatchArgs A, StageArgs S) {
     __shared__ PersistentSmem sm;
     __shared__ int32_t s_pu[2];
@@ -304,7 +306,23 @@ __global__ void __launch_bounds__(kBlock) k_stage(BatchArgs A, StageArgs S) {
         s_pu[1] = (int32_t)(t - S.first[lo]);
     }
     __syncthreads();
-    exec_task<H0>(A, s_pu[0], S.kind, S.level, s_pu[1], sm);
+    exec_task<H0>(A, s_pu[0], KIND, S.level, s_pu[1], sm);
+}
+
+template <int H0>
+static hipError_t launch_stage(const BatchArgs &A, const StageArgs &S, dim3 grid, hipStream_t st) {
+    switch (S.kind) {
+        case ST_EMPTY: hipLaunchKernelGGL((k_stage<H0, ST_EMPTY>), grid, dim3(kBlock), 0, st, A, S); break;
+        case ST_NM_SYM: hipLaunchKernelGGL((k_stage<H0, ST_NM_SYM>), grid, dim3(kBlock), 0, st, A, S); break;
+        case ST_BASE_BLK: hipLaunchKernelGGL((k_stage<H0, ST_BASE_BLK>), grid, dim3(kBlock), 0, st, A, S); break;
+        case ST_ANCHOR: hipLaunchKernelGGL((k_stage<H0, ST_ANCHOR>), grid, dim3(kBlock), 0, st, A, S); break;
+        case ST_BRACKET_CH: hipLaunchKernelGGL((k_stage<H0, ST_BRACKET_CH>), grid, dim3(kBlock), 0, st, A, S); break;
+        case ST_LENGTH: hipLaunchKernelGGL((k_stage<H0, ST_LENGTH>), grid, dim3(kBlock), 0, st, A, S); break;
+        case ST_SPLIT: hipLaunchKernelGGL((k_stage<H0, ST_SPLIT>), grid, dim3(kBlock), 0, st, A, S); break;
+        case ST_LEAF: hipLaunchKernelGGL((k_stage<H0, ST_LEAF>), grid, dim3(kBlock), 0, st, A, S); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 __global__ void k_fill(int32_t *p, int64_t count, int32_t value) {
@@ -675,12 +693,13 @@ extern "C" int32_t lcs_batch_submit(lcs_batch_t B, const lcs_pair_desc *pairs, i
                 S.first = reinterpret_cast<const int64_t *>(ws + B->off_stage + sl.first_off);
                 if (sl.items >= (int64_t)1 << 31) return LCS_E_TOO_BIG;
                 const dim3 grid((unsigned)sl.items);
+                hipError_t e;
                 switch (B->d.base_rows) {
-                    case 16: hipLaunchKernelGGL(k_stage<16>, grid, dim3(kBlock), 0, st, A, S); break;
-                    case 32: hipLaunchKernelGGL(k_stage<32>, grid, dim3(kBlock), 0, st, A, S); break;
-                    default: hipLaunchKernelGGL(k_stage<64>, grid, dim3(kBlock), 0, st, A, S); break;
+                    case 16: e = launch_stage<16>(A, S, grid, st); break;
+                    case 32: e = launch_stage<32>(A, S, grid, st); break;
+                    default: e = launch_stage<64>(A, S, grid, st); break;
                 }
-                if (hipGetLastError() != hipSuccess) return LCS_E_HIP;
+                if (e != hipSuccess) return LCS_E_HIP;
             }
             return LCS_OK;
         }
