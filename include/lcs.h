@@ -86,7 +86,7 @@ typedef struct lcs_plan_desc {
  * sentinel row per matrix, the next-match tables and search/trace scratch.
  * Errors: LCS_E_INVAL (null pointer, negative size, alphabet outside 1..256,
  * unsupported base_rows or tile), LCS_E_TOO_BIG (a matrix would have 2^30 or
- * more cells), LCS_E_NOMEM.
+ * more cells, or max_n >= 2^24 - 2), LCS_E_NOMEM.
  */
 int32_t lcs_plan(const lcs_plan_desc *desc, lcs_plan_t *out, size_t *workspace_bytes);
 

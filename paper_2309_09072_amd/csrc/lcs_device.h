@@ -18,8 +18,9 @@ constexpr int kBlock = 256;  // threads per work-group for every task
 constexpr int kWave = 64;
 constexpr int kWaves = kBlock / kWave;
 constexpr int kJChunk = 32;  // weights per bracket block (a block may take kJChunk + 1)
-constexpr int kBatch = 4;    // candidates whose loads are issued together
+constexpr int kBatch = 8;    // candidates whose loads are issued together
 constexpr int kMaxTile = 32;
+constexpr int kBracketItems = 2;  // outputs per thread and bisection level, loads interleaved
 
 __host__ __device__ __forceinline__ int32_t imin(int32_t a, int32_t b) { return a < b ? a : b; }
 __host__ __device__ __forceinline__ int32_t imax(int32_t a, int32_t b) { return a > b ? a : b; }
@@ -158,7 +159,7 @@ __device__ void base_strip_block(const uint8_t *__restrict__ arow, int32_t h, in
 }
 
 // ---------------------------------------------------------------------------
-// Candidate scan of the combine equation for one output (vertex row urow of
+// Candidate scan of the combine equation for one output (vertex row at offset urow of
 // D_U, weight j): candidates k = k0, k0+step, ... in increasing order, value
 // D_L(D_U(i, k), j - k).  Every k with max(0, j-hL) <= k <= min(j, hU) is a
 // term of the equation, so a value of ANY such candidate is >= the true
@@ -174,35 +175,72 @@ __device__ void base_strip_block(const uint8_t *__restrict__ arow, int32_t h, in
 // no branches: indices are clamped into the window (the loads stay in bounds,
 // a row x = n + 1 is the all-unreachable sentinel row) and results selected.
 // Returns true when the scan is finished; otherwise it resumes at
-// k0 + kBatch * step.  best starts at n + 2 ("nothing yet").
-__device__ __forceinline__ bool scan_batch(const int32_t *__restrict__ urow,
-                                           const int32_t *__restrict__ L, int32_t ldL, int32_t j,
-                                           int32_t k0, int32_t step, int32_t hi, int32_t xb,
-                                           int32_t vlo, int32_t n, int32_t &best, int32_t &bk,
-                                           int32_t &bx) {
-    int32_t xs[kBatch], vs[kBatch];
+// k0 + kBatch * step.  best starts at n + 2 ("nothing yet").  The three
+// phases (D_U loads, D_L loads, reduction) are separate so that a caller can
+// keep the loads of several outputs in flight together.
+// Element idx of a matrix of fewer than 2^30 cells: the byte offset fits in 32
+// bits, so the load takes a scalar base and one 32-bit vector offset.
+__device__ __forceinline__ int32_t ld_cell(const int32_t *__restrict__ base, uint32_t idx) {
+    return *reinterpret_cast<const int32_t *>(reinterpret_cast<const char *>(base) + (idx << 2));
+}
+// D_U loads of a batch; urow = offset of the vertex row in U
+template <int B = kBatch>
+__device__ __forceinline__ void batch_load_u(const int32_t *__restrict__ U, uint32_t urow,
+                                             int32_t k0, int32_t step, int32_t hi, int32_t n,
+                                             int32_t (&xs)[B]) {
 #pragma unroll
-    for (int t = 0; t < kBatch; ++t) xs[t] = umin(urow[imin(k0 + t * step, hi)], n + 1);
+    for (int t = 0; t < B; ++t)
+        xs[t] = umin(ld_cell(U, urow + (uint32_t)imin(k0 + t * step, hi)), n + 1);
+}
+// D_L loads of a batch.  Row x <= n + 1 and row length ldL are below 2^24
+// (a plan limit), so the row offset is one 24-bit multiply.  A candidate past
+// hi is clamped to hi: with unit step, hi itself comes earlier in the same
+// batch with the same value, so the duplicate can never be a strict minimum
+// and needs no mask; with a larger step it is masked out.
+template <bool kUnitStep, int B = kBatch>
+__device__ __forceinline__ void batch_load_l(const int32_t *__restrict__ L, int32_t ldL, int32_t j,
+                                             int32_t k0, int32_t step, int32_t hi,
+                                             const int32_t (&xs)[B], int32_t (&vs)[B]) {
 #pragma unroll
-    for (int t = 0; t < kBatch; ++t) {
+    for (int t = 0; t < B; ++t) {
         const int32_t kc = imin(k0 + t * step, hi);
-        const int32_t v = L[(uint32_t)xs[t] * (uint32_t)ldL + (uint32_t)(j - kc)];
-        vs[t] = (k0 + t * step <= hi) ? v : 0x7fffffff;
+        const int32_t v =
+            ld_cell(L, __umul24((uint32_t)xs[t], (uint32_t)ldL) + (uint32_t)(j - kc));
+        vs[t] = (kUnitStep || k0 + t * step <= hi) ? v : 0x7fffffff;
     }
+}
+template <int B = kBatch>
+__device__ __forceinline__ bool batch_reduce(int32_t j, int32_t k0, int32_t step, int32_t hi,
+                                             int32_t xb, int32_t vlo, int32_t n,
+                                             const int32_t (&xs)[B], const int32_t (&vs)[B],
+                                             int32_t &best, int32_t &bk, int32_t &bx) {
 #pragma unroll
-    for (int t = 0; t < kBatch; ++t) {
+    for (int t = 0; t < B; ++t) {
         const bool upd = vs[t] < best;
         best = upd ? vs[t] : best;
         bk = upd ? k0 + t * step : bk;
         bx = upd ? xs[t] : bx;
     }
-    const int32_t klast = k0 + (kBatch - 1) * step;
-    const int32_t xl = xs[kBatch - 1];
+    const int32_t klast = k0 + (B - 1) * step;
+    const int32_t xl = xs[B - 1];
     return (klast >= hi) | (xl > xb) | (best == vlo) | ((best <= n) & (xl - klast >= best - j));
+}
+__device__ __forceinline__ bool scan_batch(const int32_t *__restrict__ U, uint32_t urow,
+                                           const int32_t *__restrict__ L, int32_t ldL, int32_t j,
+                                           int32_t k0, int32_t step, int32_t hi, int32_t xb,
+                                           int32_t vlo, int32_t n, int32_t &best, int32_t &bk,
+                                           int32_t &bx) {
+    int32_t xs[kBatch], vs[kBatch];
+    batch_load_u(U, urow, k0, step, hi, n, xs);
+    if (step == 1)
+        batch_load_l<true>(L, ldL, j, k0, step, hi, xs, vs);
+    else
+        batch_load_l<false>(L, ldL, j, k0, step, hi, xs, vs);
+    return batch_reduce(j, k0, step, hi, xb, vlo, n, xs, vs, best, bk, bx);
 }
 
 // Whole scan over [lo, hi] with stride step (loop of batches).
-__device__ __forceinline__ void scan_candidates(const int32_t *__restrict__ urow,
+__device__ __forceinline__ void scan_candidates(const int32_t *__restrict__ U, uint32_t urow,
                                                 const int32_t *__restrict__ L, int32_t ldL,
                                                 int32_t j, int32_t lo, int32_t hi, int32_t step,
                                                 int32_t xb, int32_t vlo, int32_t n, int32_t &best,
@@ -212,7 +250,7 @@ __device__ __forceinline__ void scan_candidates(const int32_t *__restrict__ urow
     bx = n + 1;
     if (lo <= hi)
         for (int32_t k0 = lo;; k0 += kBatch * step)
-            if (scan_batch(urow, L, ldL, j, k0, step, hi, xb, vlo, n, best, bk, bx)) break;
+            if (scan_batch(U, urow, L, ldL, j, k0, step, hi, xb, vlo, n, best, bk, bx)) break;
     if (best > n) {
         best = n + 1;
         bk = -1;
@@ -249,7 +287,7 @@ __device__ void anchor_block(const int32_t *__restrict__ U, int32_t hU,
     const int32_t H = hU + hL + 1;
     int32_t P = 1;
     while (P < H + 1) P <<= 1;
-    const int32_t *__restrict__ urow = U + (size_t)vtx * (size_t)(hU + 1);
+    const uint32_t urow = (uint32_t)vtx * (uint32_t)(hU + 1);
     int32_t *__restrict__ grow = G + (size_t)vtx * (size_t)H;
     const int32_t ldL = hL + 1;
     for (int32_t s = P >> 1; s >= 1; s >>= 1) {
@@ -280,7 +318,7 @@ __device__ void anchor_block(const int32_t *__restrict__ U, int32_t hU,
                     const int32_t lo = imax(kl, imax(c - hL, 0));
                     const int32_t hi = imin(kr, imin(c, hU));
                     int32_t best, bk, bx;
-                    scan_candidates(urow, L, ldL, c, lo + gl, hi, g, n, -1, n, best, bk, bx);
+                    scan_candidates(U, urow, L, ldL, c, lo + gl, hi, g, n, -1, n, best, bk, bx);
                     if (best <= n) key = ((unsigned long long)(uint32_t)best << 32) | (uint32_t)bk;
                 }
             }
@@ -322,18 +360,33 @@ __device__ void anchor_block(const int32_t *__restrict__ U, int32_t hU,
 // One block solves tile vertices i0..i0+len (both ends already solved) for
 // weights j0..j0+jn-1, bisecting the tile (vertex len/2 first, then the
 // quarter points, ...).  Per-vertex state (k*, x*, value) for the block's
-// weights lives in LDS; values reach D_G in contiguous row segments.
-// SIMD efficiency: within a bisection level every output first runs exactly
-// one batch of candidates; the few that are not finished are queued in LDS and
-// completed by all threads together, so a wave never waits for its slowest lane
-// during the common case.
+// weights lives in LDS; values reach D_G as soon as they are final, in
+// contiguous row segments.
+// D_U in LDS: by the window above (applied level by level, and with k*
+// non-decreasing in j) every candidate of vertex i0 + v lies in
+// [k*(i0, j0) - v, k*(i1, jl) + (len - v)], jl the last weight that is
+// reachable from i0.  When that parallelogram is at most kUWin wide and
+// k*(i1, jl) exists, the block first copies it from D_U into LDS and the
+// bisection reads D_U only from there: one HBM round trip per level (the D_L
+// gathers) instead of two.  Otherwise D_U is read from global memory.
+// A block none of whose weights is reachable from i0 writes unreachable
+// everywhere (reachability is monotone in the vertex).
+// Latency: within a bisection level each thread owns up to kBracketItems
+// outputs and issues the loads of all of them before it waits, and every
+// output first runs exactly one batch of candidates; the few that are not
+// finished are queued in LDS and completed by all threads together, so a wave
+// never waits for its slowest lane during the common case.
+// The last weight of a strip, j = hU + hL, has the single candidate k = hU; a
+// block that holds it (jn = kJChunk + 1) evaluates it directly, so the
+// bisection works on at most kJChunk weights.
+constexpr int kUWin = 64;
 struct BracketSmem {
-    int32_t k[(kMaxTile + 1) * (kJChunk + 1)];
-    int32_t x[(kMaxTile + 1) * (kJChunk + 1)];
-    int32_t v[(kMaxTile + 1) * (kJChunk + 1)];
-    int32_t nk[(kMaxTile + 1) * (kJChunk + 1)];  // resume point of a queued output
-    int32_t q[(kMaxTile + 1) * (kJChunk + 1)];   // queued outputs (slot * S + jj)
-    int32_t qn;
+    int32_t k[(kMaxTile + 1) * kJChunk];
+    int32_t x[(kMaxTile + 1) * kJChunk];
+    int32_t v[(kMaxTile + 1) * kJChunk];
+    int32_t u[(kMaxTile + 1) * kUWin];    // D_U parallelogram (row v starts at k*(i0, j0) - v)
+    int32_t q[(kMaxTile / 2) * kJChunk];  // queued outputs of one level (slot * kJChunk + jj)
+    int32_t qn[2];                        // queue lengths, alternating between levels
 };
 
 struct BracketWindow {
@@ -345,7 +398,7 @@ __device__ __forceinline__ BracketWindow bracket_window(const BracketSmem &sm, i
                                                         int32_t va, int32_t vb, int32_t jj,
                                                         int32_t j, int32_t hU, int32_t hL,
                                                         int32_t n) {
-    constexpr int32_t S = kJChunk + 1;
+    constexpr int32_t S = kJChunk;
     BracketWindow w;
     const int32_t ka = sm.k[va * S + jj];
     const int32_t kb = sm.k[vb * S + jj];
@@ -361,108 +414,249 @@ __device__ __forceinline__ BracketWindow bracket_window(const BracketSmem &sm, i
     return w;
 }
 
+// Final result of one output: LDS state for the finer levels and D_G.
+__device__ __forceinline__ void bracket_store(BracketSmem &sm, int32_t id, int32_t *__restrict__ g,
+                                              int32_t n, int32_t best, int32_t bk, int32_t bx) {
+    if (best > n) {
+        best = n + 1;
+        bk = -1;
+        bx = n + 1;
+    }
+    sm.k[id] = bk;
+    sm.x[id] = bx;
+    sm.v[id] = best;
+    *g = best;
+}
+
+// D_U loads of one batch of tile vertex v: from the LDS parallelogram (kLds,
+// k0 >= ubase - v and hi < ubase - v + kUWin) or from global memory.
+template <int B, bool kLds>
+__device__ __forceinline__ void bracket_load_u(const BracketSmem &sm, const int32_t *__restrict__ U,
+                                               int32_t ldU, int32_t i0, int32_t ubase, int32_t v,
+                                               int32_t k0, int32_t hi, int32_t n,
+                                               int32_t (&xs)[B]) {
+    if (kLds) {
+        const int32_t off = v * kUWin - ubase + v;
+#pragma unroll
+        for (int t = 0; t < B; ++t) xs[t] = sm.u[off + imin(k0 + t, hi)];
+    } else {
+        batch_load_u<B>(U, (uint32_t)(i0 + v) * (uint32_t)ldU, k0, 1, hi, n, xs);
+    }
+}
+
+// Pass 1 of one bisection level with R outputs per thread: every output runs
+// one batch of candidates.  The loads carry no branches (an idle output reads
+// vertex i0, weight 0, which is in bounds) so that the loads of all R outputs
+// are in flight together.  Unfinished outputs are queued for pass 2.
+template <int R, int B, bool kLds>
+__device__ __forceinline__ void bracket_pass1(BracketSmem &sm, const int32_t *__restrict__ U,
+                                              int32_t hU, const int32_t *__restrict__ L,
+                                              int32_t hL, int32_t *__restrict__ G, int32_t n,
+                                              int32_t i0, int32_t len, int32_t j0, int32_t js,
+                                              int32_t half, int32_t st, int32_t nitems,
+                                              int32_t par, int32_t ubase) {
+    constexpr int32_t S = kJChunk;
+    // a wave without outputs at this level skips it (no barrier inside)
+    if ((int32_t)(threadIdx.x & ~(kWave - 1)) >= nitems) return;
+    const int32_t INF = n + 1;
+    const int32_t H = hU + hL + 1;
+    const int32_t ldU = hU + 1, ldL = hL + 1;
+    const int32_t lane = __lane_id();
+    int32_t id[R], vr[R], jv[R], lo[R], hi[R], xb[R], vlo[R];
+    bool act[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int32_t e = (int32_t)threadIdx.x + r * kBlock;
+        const int32_t t = e / S, jj = e - t * S;
+        const int32_t v = half + t * st;
+        id[r] = v * S + jj;
+        vr[r] = 0;
+        jv[r] = 0;
+        lo[r] = kLds ? ubase : 0;
+        hi[r] = lo[r];
+        xb[r] = n;
+        vlo[r] = -1;
+        act[r] = false;
+        if ((e < nitems) && (jj < js)) {
+            const int32_t j = j0 + jj;
+            const BracketWindow w = bracket_window(sm, v, v - half, imin(v + half, len), jj, j, hU, hL, n);
+            if (w.dead || w.lo > w.hi) {
+                bracket_store(sm, id[r], G + (size_t)(i0 + v) * H + j, n, INF, -1, INF);
+            } else {
+                act[r] = true;
+                vr[r] = v;
+                jv[r] = j;
+                lo[r] = w.lo;
+                hi[r] = w.hi;
+                xb[r] = w.xb;
+                vlo[r] = w.vlo;
+            }
+        }
+    }
+    int32_t xs[R][B], vs[R][B];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        bracket_load_u<B, kLds>(sm, U, ldU, i0, ubase, vr[r], lo[r], hi[r], n, xs[r]);
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        batch_load_l<true, B>(L, ldL, jv[r], lo[r], 1, hi[r], xs[r], vs[r]);
+    // The loaded values are needed on every path from here: keeps the compiler
+    // from sinking the loads of an idle output into a branch, which would
+    // serialise the outputs' loads again.  (An empty statement, no instruction.)
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int t = 0; t < B; ++t) asm volatile("" : "+v"(vs[r][t]), "+v"(xs[r][t]));
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        int32_t best = n + 2, bk = -1, bx = INF;
+        const bool done =
+            batch_reduce<B>(jv[r], lo[r], 1, hi[r], xb[r], vlo[r], n, xs[r], vs[r], best, bk, bx);
+        bool queued = false;
+        if (act[r]) {
+            if (done) {
+                bracket_store(sm, id[r], G + (size_t)(i0 + vr[r]) * H + jv[r], n, best, bk, bx);
+            } else {  // provisional state; pass 2 resumes at lo + B
+                sm.k[id[r]] = bk;
+                sm.x[id[r]] = bx;
+                sm.v[id[r]] = best;
+                queued = true;
+            }
+        }
+        // reserve queue slots with one LDS atomic per wave
+        const unsigned long long mask = __ballot(queued);
+        if (mask) {
+            const int32_t leader = __ffsll((long long)mask) - 1;
+            int32_t qbase = 0;
+            if (lane == leader) qbase = atomicAdd(&sm.qn[par], __popcll(mask));
+            qbase = __shfl(qbase, leader, kWave);
+            if (queued) {
+                const unsigned long long below = mask & ((1ull << lane) - 1ull);
+                sm.q[qbase + __popcll(below)] = id[r];
+            }
+        }
+    }
+}
+
+template <bool kLds>
+__device__ __forceinline__ void bracket_levels(BracketSmem &sm, const int32_t *__restrict__ U,
+                                               int32_t hU, const int32_t *__restrict__ L,
+                                               int32_t hL, int32_t *__restrict__ G, int32_t n,
+                                               int32_t i0, int32_t len, int32_t j0, int32_t js,
+                                               int32_t ubase) {
+    constexpr int32_t S = kJChunk;
+    const int32_t H = hU + hL + 1;
+    const int32_t ldU = hU + 1, ldL = hL + 1;
+    int32_t P2 = 1;
+    while (P2 < len) P2 <<= 1;
+    int32_t par = 0;
+    for (int32_t st = P2; st >= 2; st >>= 1, par ^= 1) {
+        const int32_t half = st >> 1;
+        const int32_t nv = (len > half) ? (len - half + st - 1) / st : 0;
+        const int32_t nitems = nv * S;
+        if (threadIdx.x == 0) sm.qn[par ^ 1] = 0;  // next level's queue (read after a barrier)
+        // batch of the first pass: 8 candidates where the windows are wide
+        // (the coarse levels), 4 at the fine levels that hold most outputs
+        int32_t b1;
+        if (st >= 8) {
+            b1 = 8;
+            bracket_pass1<1, 8, kLds>(sm, U, hU, L, hL, G, n, i0, len, j0, js, half, st, nitems,
+                                      par, ubase);
+        } else if (nitems > kBlock) {
+            b1 = 4;
+            bracket_pass1<kBracketItems, 4, kLds>(sm, U, hU, L, hL, G, n, i0, len, j0, js, half,
+                                                  st, nitems, par, ubase);
+        } else {
+            b1 = 4;
+            bracket_pass1<1, 4, kLds>(sm, U, hU, L, hL, G, n, i0, len, j0, js, half, st, nitems,
+                                      par, ubase);
+        }
+        __syncthreads();
+        // pass 2: the queued outputs, one per thread
+        const int32_t qn = sm.qn[par];
+        if (qn > 0) {
+            for (int32_t e = threadIdx.x; e < qn; e += kBlock) {
+                const int32_t idq = sm.q[e];
+                const int32_t v = idq / S, jj = idq - v * S;
+                const int32_t j = j0 + jj;
+                const BracketWindow wq =
+                    bracket_window(sm, v, v - half, imin(v + half, len), jj, j, hU, hL, n);
+                int32_t best = sm.v[idq], bk = sm.k[idq], bx = sm.x[idq];
+                for (int32_t k0 = wq.lo + b1;; k0 += kBatch) {
+                    int32_t xs[kBatch], vs[kBatch];
+                    bracket_load_u<kBatch, kLds>(sm, U, ldU, i0, ubase, v, k0, wq.hi, n, xs);
+                    batch_load_l<true>(L, ldL, j, k0, 1, wq.hi, xs, vs);
+                    if (batch_reduce(j, k0, 1, wq.hi, wq.xb, wq.vlo, n, xs, vs, best, bk, bx))
+                        break;
+                }
+                bracket_store(sm, idq, G + (size_t)(i0 + v) * H + j, n, best, bk, bx);
+            }
+            __syncthreads();
+        }
+    }
+}
+
 __device__ void bracket_block(const int32_t *__restrict__ U, int32_t hU,
                               const int32_t *__restrict__ L, int32_t hL, int32_t *__restrict__ G,
                               int32_t n, int32_t i0, int32_t len, int32_t j0, int32_t jn,
                               const int32_t *__restrict__ Ka, const int32_t *__restrict__ Kb,
                               BracketSmem &sm) {
     if (len < 2 || jn <= 0) return;
-    constexpr int32_t S = kJChunk + 1;  // LDS row stride (weights); item slots per vertex
+    constexpr int32_t S = kJChunk;  // LDS row stride; item slots per vertex
+    static_assert((kMaxTile / 2) * kJChunk <= kBracketItems * kBlock,
+                  "a bisection level exceeds kBracketItems outputs per thread");
+    static_assert(kJChunk <= kWave / 2, "tile ends are read by half a wave each");
     const int32_t INF = n + 1;
     const int32_t H = hU + hL + 1;
     const int32_t ldU = hU + 1, ldL = hL + 1;
+    const int32_t js = imin(jn, S);  // weights solved by bisection
     const int32_t lane = __lane_id();
-    // the two solved ends of the tile
-    for (int32_t side = 0; side < 2; ++side) {
+    // Tile ends: in every wave, lanes 0..31 hold k*(i0, j0 + lane) and lanes
+    // 32..63 k*(i1, j0 + lane - 32); wave 0 also stores them in LDS.
+    const int32_t side = lane >> 5, jj0 = lane & 31;
+    const bool lend = jj0 < js;
+    const int32_t kend = lend ? (side ? Kb : Ka)[j0 + jj0] : -1;
+    const unsigned long long live = __ballot(side == 0 && kend >= 0);
+    const int32_t ka0 = __shfl(kend, 0, kWave);  // k*(i0, j0)
+    const int32_t jl = live ? 63 - __clzll((long long)live) : 0;  // last weight reachable from i0
+    const int32_t kbl = __shfl(kend, 32 + jl, kWave);                // k*(i1, jl)
+    if (threadIdx.x < kWave && lend) {
         const int32_t slot = side ? len : 0;
         const int32_t vert = i0 + slot;
-        const int32_t *K = side ? Kb : Ka;
-        for (int32_t jj = threadIdx.x; jj < jn; jj += kBlock) {
-            const int32_t k = K[j0 + jj];
-            sm.k[slot * S + jj] = k;
-            sm.v[slot * S + jj] = G[(size_t)vert * H + j0 + jj];
-            sm.x[slot * S + jj] = (k >= 0) ? U[(size_t)vert * ldU + k] : INF;
+        sm.k[slot * S + jj0] = kend;
+        sm.v[slot * S + jj0] = G[(size_t)vert * H + j0 + jj0];
+        sm.x[slot * S + jj0] = (kend >= 0) ? umin(U[(size_t)vert * ldU + umin(kend, hU)], INF) : INF;
+    }
+    if (threadIdx.x < 2) sm.qn[threadIdx.x] = 0;
+    if (jn > S) {  // weight j0 + S = hU + hL: one candidate, k = hU
+        const int32_t j = j0 + S;
+        for (int32_t v = 1 + (int32_t)threadIdx.x; v < len; v += kBlock) {
+            const int32_t vert = i0 + v;
+            const int32_t x = umin(U[(size_t)vert * ldU + hU], INF);
+            G[(size_t)vert * H + j] = L[(size_t)x * ldL + (j - hU)];
         }
     }
-    if (threadIdx.x == 0) sm.qn = 0;
+    if (!live) {  // nothing reachable from i0: the whole block is unreachable
+        for (int32_t e = threadIdx.x; e < (len - 1) * S; e += kBlock) {
+            const int32_t t = 1 + e / S, jj = e - (t - 1) * S;
+            if (jj < js) G[(size_t)(i0 + t) * H + j0 + jj] = INF;
+        }
+        __syncthreads();
+        return;
+    }
+    const bool lds_u = (kbl >= 0) && (kbl - ka0 + len + 1 <= kUWin);
+    if (lds_u) {  // copy the D_U parallelogram (all rows: an idle output reads row 0)
+        for (int32_t e = threadIdx.x; e < (len + 1) * kUWin; e += kBlock) {
+            const int32_t v = e / kUWin, c = e - v * kUWin;
+            const int32_t k = imin(imax(ka0 - v + c, 0), hU);
+            sm.u[v * kUWin + c] = umin(U[(size_t)(i0 + v) * ldU + k], INF);
+        }
+    }
     __syncthreads();
-    int32_t P2 = 1;
-    while (P2 < len) P2 <<= 1;
-    for (int32_t st = P2; st >= 2; st >>= 1) {
-        const int32_t half = st >> 1;
-        const int32_t nv = (len > half) ? (len - half + st - 1) / st : 0;
-        // pass 1: one batch per output; item e -> (vertex t, weight jj)
-        const int32_t nitems = nv * S;
-        for (int32_t base = 0; base < nitems; base += kBlock) {
-            const int32_t e = base + threadIdx.x;
-            const int32_t t = e / S, jj = e - t * S;
-            const int32_t v = half + t * st;
-            const bool act = (e < nitems) && (jj < jn);
-            bool queued = false;
-            if (act) {
-                const int32_t va = v - half, vb = imin(v + half, len);
-                const int32_t j = j0 + jj;
-                const BracketWindow w = bracket_window(sm, v, va, vb, jj, j, hU, hL, n);
-                int32_t best = n + 2, bk = -1, bx = INF;
-                bool done = w.dead || w.lo > w.hi;
-                if (!done)
-                    done = scan_batch(U + (size_t)(i0 + v) * ldU, L, ldL, j, w.lo, 1, w.hi, w.xb,
-                                      w.vlo, n, best, bk, bx);
-                const int32_t id = v * S + jj;
-                sm.k[id] = bk;
-                sm.x[id] = bx;
-                sm.v[id] = best;
-                sm.nk[id] = w.lo + kBatch;
-                queued = !done;
-            }
-            // reserve queue slots with one LDS atomic per wave
-            const unsigned long long mask = __ballot(queued);
-            if (mask) {
-                const int32_t leader = __ffsll((long long)mask) - 1;
-                int32_t qbase = 0;
-                if (lane == leader) qbase = atomicAdd(&sm.qn, __popcll(mask));
-                qbase = __shfl(qbase, leader, kWave);
-                if (queued) {
-                    const unsigned long long below = mask & ((1ull << lane) - 1ull);
-                    sm.q[qbase + __popcll(below)] = v * S + jj;
-                }
-            }
-        }
-        __syncthreads();
-        // pass 2: the queued outputs, one per thread
-        const int32_t qn = sm.qn;
-        for (int32_t e = threadIdx.x; e < qn; e += kBlock) {
-            const int32_t id = sm.q[e];
-            const int32_t v = id / S, jj = id - v * S;
-            const int32_t va = v - half, vb = imin(v + half, len);
-            const int32_t j = j0 + jj;
-            const BracketWindow w = bracket_window(sm, v, va, vb, jj, j, hU, hL, n);
-            const int32_t *__restrict__ urow = U + (size_t)(i0 + v) * ldU;
-            int32_t best = sm.v[id], bk = sm.k[id], bx = sm.x[id];
-            for (int32_t k0 = sm.nk[id];; k0 += kBatch)
-                if (scan_batch(urow, L, ldL, j, k0, 1, w.hi, w.xb, w.vlo, n, best, bk, bx)) break;
-            sm.k[id] = bk;
-            sm.x[id] = bx;
-            sm.v[id] = best;
-        }
-        __syncthreads();
-        // normalise unreachable results
-        for (int32_t e = threadIdx.x; e < nitems; e += kBlock) {
-            const int32_t t = e / S, jj = e - t * S;
-            const int32_t id = (half + t * st) * S + jj;
-            if (jj < jn && sm.v[id] > n) {
-                sm.v[id] = INF;
-                sm.k[id] = -1;
-                sm.x[id] = INF;
-            }
-        }
-        if (threadIdx.x == 0) sm.qn = 0;
-        __syncthreads();
-    }
-    for (int32_t e = threadIdx.x; e < (len - 1) * S; e += kBlock) {
-        const int32_t t = 1 + e / S, jj = e - (t - 1) * S;
-        if (jj < jn) G[(size_t)(i0 + t) * H + j0 + jj] = sm.v[t * S + jj];
-    }
+    if (lds_u)
+        bracket_levels<true>(sm, U, hU, L, hL, G, n, i0, len, j0, js, ka0);
+    else
+        bracket_levels<false>(sm, U, hU, L, hL, G, n, i0, len, j0, js, ka0);
     __syncthreads();
 }
 

@@ -27,7 +27,7 @@ struct Layout {
 inline int64_t align256(int64_t x) { return (x + 255) & ~(int64_t)255; }
 
 // Workspace layout for one pair of sizes (m, n).  Returns false when a strip
-// matrix would have 2^30 or more cells.
+// matrix would have 2^30 or more cells or n + 2 >= 2^24.
 inline bool make_layout(int32_t m, int32_t n, int32_t sigma, int32_t h0, int32_t tile, Layout &L) {
     L = Layout();
     L.m = m;
@@ -37,6 +37,8 @@ inline bool make_layout(int32_t m, int32_t n, int32_t sigma, int32_t h0, int32_t
     L.tile = tile;
     // every matrix has fewer than 2^30 cells, so a byte offset inside one fits in 32 bits
     if ((int64_t)(n + 2) * (int64_t)(m + 1) >= ((int64_t)1 << 30)) return false;
+    // a row index (at most n + 1) and a row length are 24-bit factors of a cell index
+    if (n + 2 >= (1 << 24)) return false;
     int64_t off = 0;
     L.off_hdr = off;
     off += 4 * kHeaderWords;
