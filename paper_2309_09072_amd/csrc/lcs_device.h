@@ -213,13 +213,12 @@ template <int B = kBatch>
 __device__ __forceinline__ bool batch_reduce(int32_t j, int32_t k0, int32_t step, int32_t hi,
                                              int32_t xb, int32_t vlo, int32_t n,
                                              const int32_t (&xs)[B], const int32_t (&vs)[B],
-                                             int32_t &best, int32_t &bk, int32_t &bx) {
+                                             int32_t &best, int32_t &bk) {
 #pragma unroll
     for (int t = 0; t < B; ++t) {
         const bool upd = vs[t] < best;
         best = upd ? vs[t] : best;
         bk = upd ? k0 + t * step : bk;
-        bx = upd ? xs[t] : bx;
     }
     const int32_t klast = k0 + (B - 1) * step;
     const int32_t xl = xs[B - 1];
@@ -228,15 +227,15 @@ __device__ __forceinline__ bool batch_reduce(int32_t j, int32_t k0, int32_t step
 __device__ __forceinline__ bool scan_batch(const int32_t *__restrict__ U, uint32_t urow,
                                            const int32_t *__restrict__ L, int32_t ldL, int32_t j,
                                            int32_t k0, int32_t step, int32_t hi, int32_t xb,
-                                           int32_t vlo, int32_t n, int32_t &best, int32_t &bk,
-                                           int32_t &bx) {
+                                           int32_t vlo, int32_t n, int32_t &best,
+                                           int32_t &bk) {
     int32_t xs[kBatch], vs[kBatch];
     batch_load_u(U, urow, k0, step, hi, n, xs);
     if (step == 1)
         batch_load_l<true>(L, ldL, j, k0, step, hi, xs, vs);
     else
         batch_load_l<false>(L, ldL, j, k0, step, hi, xs, vs);
-    return batch_reduce(j, k0, step, hi, xb, vlo, n, xs, vs, best, bk, bx);
+    return batch_reduce(j, k0, step, hi, xb, vlo, n, xs, vs, best, bk);
 }
 
 // Whole scan over [lo, hi] with stride step (loop of batches).
@@ -244,17 +243,15 @@ __device__ __forceinline__ void scan_candidates(const int32_t *__restrict__ U, u
                                                 const int32_t *__restrict__ L, int32_t ldL,
                                                 int32_t j, int32_t lo, int32_t hi, int32_t step,
                                                 int32_t xb, int32_t vlo, int32_t n, int32_t &best,
-                                                int32_t &bk, int32_t &bx) {
+                                                int32_t &bk) {
     best = n + 2;
     bk = -1;
-    bx = n + 1;
     if (lo <= hi)
         for (int32_t k0 = lo;; k0 += kBatch * step)
-            if (scan_batch(U, urow, L, ldL, j, k0, step, hi, xb, vlo, n, best, bk, bx)) break;
+            if (scan_batch(U, urow, L, ldL, j, k0, step, hi, xb, vlo, n, best, bk)) break;
     if (best > n) {
         best = n + 1;
         bk = -1;
-        bx = n + 1;
     }
 }
 
@@ -317,8 +314,8 @@ __device__ void anchor_block(const int32_t *__restrict__ U, int32_t hU,
                 if (!dead) {
                     const int32_t lo = imax(kl, imax(c - hL, 0));
                     const int32_t hi = imin(kr, imin(c, hU));
-                    int32_t best, bk, bx;
-                    scan_candidates(U, urow, L, ldL, c, lo + gl, hi, g, n, -1, n, best, bk, bx);
+                    int32_t best, bk;
+                    scan_candidates(U, urow, L, ldL, c, lo + gl, hi, g, n, -1, n, best, bk);
                     if (best <= n) key = ((unsigned long long)(uint32_t)best << 32) | (uint32_t)bk;
                 }
             }
@@ -382,7 +379,6 @@ __device__ void anchor_block(const int32_t *__restrict__ U, int32_t hU,
 constexpr int kUWin = 64;
 struct BracketSmem {
     int32_t k[(kMaxTile + 1) * kJChunk];
-    int32_t x[(kMaxTile + 1) * kJChunk];
     int32_t v[(kMaxTile + 1) * kJChunk];
     int32_t u[(kMaxTile + 1) * kUWin];    // D_U parallelogram (row v starts at k*(i0, j0) - v)
     int32_t q[(kMaxTile / 2) * kJChunk];  // queued outputs of one level (slot * kJChunk + jj)
@@ -394,7 +390,24 @@ struct BracketWindow {
     bool dead;
 };
 
-__device__ __forceinline__ BracketWindow bracket_window(const BracketSmem &sm, int32_t v,
+// D_U(i0 + v, k) of a tile vertex: from the LDS parallelogram (kLds; the
+// index is clamped into the row, so any k reads inside it) or from global
+// memory.
+template <bool kLds>
+__device__ __forceinline__ int32_t bracket_u(const BracketSmem &sm, const int32_t *__restrict__ U,
+                                             int32_t ldU, int32_t hU, int32_t i0, int32_t ubase,
+                                             int32_t v, int32_t k, int32_t n) {
+    if (kLds) return sm.u[v * kUWin + imin(imax(k - ubase + v, 0), kUWin - 1)];
+    return umin(ld_cell(U, (uint32_t)(i0 + v) * (uint32_t)ldU + (uint32_t)imin(imax(k, 0), hU)),
+                n + 1);
+}
+
+// Search window of output (v, j) from the solved vertices va < v < vb; the
+// crossing bound x*(vb, j) = D_U(i0 + vb, k*(vb, j)) is looked up from k*.
+template <bool kLds>
+__device__ __forceinline__ BracketWindow bracket_window(const BracketSmem &sm,
+                                                        const int32_t *__restrict__ U, int32_t ldU,
+                                                        int32_t i0, int32_t ubase, int32_t v,
                                                         int32_t va, int32_t vb, int32_t jj,
                                                         int32_t j, int32_t hU, int32_t hL,
                                                         int32_t n) {
@@ -407,7 +420,7 @@ __device__ __forceinline__ BracketWindow bracket_window(const BracketSmem &sm, i
     w.xb = n;
     if (kb >= 0) {
         w.hi = imin(kb + (vb - v), w.hi);
-        w.xb = sm.x[vb * S + jj];
+        w.xb = bracket_u<kLds>(sm, U, ldU, hU, i0, ubase, vb, kb, n);
     }
     w.lo = imax(ka - (v - va), imax(j - hL, 0));
     w.vlo = sm.v[va * S + jj];
@@ -416,32 +429,24 @@ __device__ __forceinline__ BracketWindow bracket_window(const BracketSmem &sm, i
 
 // Final result of one output: LDS state for the finer levels and D_G.
 __device__ __forceinline__ void bracket_store(BracketSmem &sm, int32_t id, int32_t *__restrict__ g,
-                                              int32_t n, int32_t best, int32_t bk, int32_t bx) {
+                                              int32_t n, int32_t best, int32_t bk) {
     if (best > n) {
         best = n + 1;
         bk = -1;
-        bx = n + 1;
     }
     sm.k[id] = bk;
-    sm.x[id] = bx;
     sm.v[id] = best;
     *g = best;
 }
 
-// D_U loads of one batch of tile vertex v: from the LDS parallelogram (kLds,
-// k0 >= ubase - v and hi < ubase - v + kUWin) or from global memory.
+// D_U loads of one batch of tile vertex v (LDS parallelogram or global).
 template <int B, bool kLds>
 __device__ __forceinline__ void bracket_load_u(const BracketSmem &sm, const int32_t *__restrict__ U,
-                                               int32_t ldU, int32_t i0, int32_t ubase, int32_t v,
-                                               int32_t k0, int32_t hi, int32_t n,
+                                               int32_t ldU, int32_t hU, int32_t i0, int32_t ubase,
+                                               int32_t v, int32_t k0, int32_t hi, int32_t n,
                                                int32_t (&xs)[B]) {
-    if (kLds) {
-        const int32_t off = v * kUWin - ubase + v;
 #pragma unroll
-        for (int t = 0; t < B; ++t) xs[t] = sm.u[off + imin(k0 + t, hi)];
-    } else {
-        batch_load_u<B>(U, (uint32_t)(i0 + v) * (uint32_t)ldU, k0, 1, hi, n, xs);
-    }
+    for (int t = 0; t < B; ++t) xs[t] = bracket_u<kLds>(sm, U, ldU, hU, i0, ubase, v, imin(k0 + t, hi), n);
 }
 
 // Pass 1 of one bisection level with R outputs per thread: every output runs
@@ -479,9 +484,10 @@ __device__ __forceinline__ void bracket_pass1(BracketSmem &sm, const int32_t *__
         act[r] = false;
         if ((e < nitems) && (jj < js)) {
             const int32_t j = j0 + jj;
-            const BracketWindow w = bracket_window(sm, v, v - half, imin(v + half, len), jj, j, hU, hL, n);
+            const BracketWindow w = bracket_window<kLds>(sm, U, ldU, i0, ubase, v, v - half,
+                                                         imin(v + half, len), jj, j, hU, hL, n);
             if (w.dead || w.lo > w.hi) {
-                bracket_store(sm, id[r], G + (size_t)(i0 + v) * H + j, n, INF, -1, INF);
+                bracket_store(sm, id[r], G + (size_t)(i0 + v) * H + j, n, INF, -1);
             } else {
                 act[r] = true;
                 vr[r] = v;
@@ -496,7 +502,7 @@ __device__ __forceinline__ void bracket_pass1(BracketSmem &sm, const int32_t *__
     int32_t xs[R][B], vs[R][B];
 #pragma unroll
     for (int r = 0; r < R; ++r)
-        bracket_load_u<B, kLds>(sm, U, ldU, i0, ubase, vr[r], lo[r], hi[r], n, xs[r]);
+        bracket_load_u<B, kLds>(sm, U, ldU, hU, i0, ubase, vr[r], lo[r], hi[r], n, xs[r]);
 #pragma unroll
     for (int r = 0; r < R; ++r)
         batch_load_l<true, B>(L, ldL, jv[r], lo[r], 1, hi[r], xs[r], vs[r]);
@@ -509,16 +515,15 @@ __device__ __forceinline__ void bracket_pass1(BracketSmem &sm, const int32_t *__
         for (int t = 0; t < B; ++t) asm volatile("" : "+v"(vs[r][t]), "+v"(xs[r][t]));
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        int32_t best = n + 2, bk = -1, bx = INF;
+        int32_t best = n + 2, bk = -1;
         const bool done =
-            batch_reduce<B>(jv[r], lo[r], 1, hi[r], xb[r], vlo[r], n, xs[r], vs[r], best, bk, bx);
+            batch_reduce<B>(jv[r], lo[r], 1, hi[r], xb[r], vlo[r], n, xs[r], vs[r], best, bk);
         bool queued = false;
         if (act[r]) {
             if (done) {
-                bracket_store(sm, id[r], G + (size_t)(i0 + vr[r]) * H + jv[r], n, best, bk, bx);
+                bracket_store(sm, id[r], G + (size_t)(i0 + vr[r]) * H + jv[r], n, best, bk);
             } else {  // provisional state; pass 2 resumes at lo + B
                 sm.k[id[r]] = bk;
-                sm.x[id[r]] = bx;
                 sm.v[id[r]] = best;
                 queued = true;
             }
@@ -579,17 +584,17 @@ __device__ __forceinline__ void bracket_levels(BracketSmem &sm, const int32_t *_
                 const int32_t idq = sm.q[e];
                 const int32_t v = idq / S, jj = idq - v * S;
                 const int32_t j = j0 + jj;
-                const BracketWindow wq =
-                    bracket_window(sm, v, v - half, imin(v + half, len), jj, j, hU, hL, n);
-                int32_t best = sm.v[idq], bk = sm.k[idq], bx = sm.x[idq];
+                const BracketWindow wq = bracket_window<kLds>(sm, U, ldU, i0, ubase, v, v - half,
+                                                              imin(v + half, len), jj, j, hU, hL, n);
+                int32_t best = sm.v[idq], bk = sm.k[idq];
                 for (int32_t k0 = wq.lo + b1;; k0 += kBatch) {
                     int32_t xs[kBatch], vs[kBatch];
-                    bracket_load_u<kBatch, kLds>(sm, U, ldU, i0, ubase, v, k0, wq.hi, n, xs);
+                    bracket_load_u<kBatch, kLds>(sm, U, ldU, hU, i0, ubase, v, k0, wq.hi, n, xs);
                     batch_load_l<true>(L, ldL, j, k0, 1, wq.hi, xs, vs);
-                    if (batch_reduce(j, k0, 1, wq.hi, wq.xb, wq.vlo, n, xs, vs, best, bk, bx))
+                    if (batch_reduce(j, k0, 1, wq.hi, wq.xb, wq.vlo, n, xs, vs, best, bk))
                         break;
                 }
-                bracket_store(sm, idq, G + (size_t)(i0 + v) * H + j, n, best, bk, bx);
+                bracket_store(sm, idq, G + (size_t)(i0 + v) * H + j, n, best, bk);
             }
             __syncthreads();
         }
@@ -625,7 +630,6 @@ __device__ void bracket_block(const int32_t *__restrict__ U, int32_t hU,
         const int32_t vert = i0 + slot;
         sm.k[slot * S + jj0] = kend;
         sm.v[slot * S + jj0] = G[(size_t)vert * H + j0 + jj0];
-        sm.x[slot * S + jj0] = (kend >= 0) ? umin(U[(size_t)vert * ldU + umin(kend, hU)], INF) : INF;
     }
     if (threadIdx.x < 2) sm.qn[threadIdx.x] = 0;
     if (jn > S) {  // weight j0 + S = hU + hL: one candidate, k = hU
