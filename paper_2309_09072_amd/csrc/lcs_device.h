@@ -224,37 +224,6 @@ __device__ __forceinline__ bool batch_reduce(int32_t j, int32_t k0, int32_t step
     const int32_t xl = xs[B - 1];
     return (klast >= hi) | (xl > xb) | (best == vlo) | ((best <= n) & (xl - klast >= best - j));
 }
-__device__ __forceinline__ bool scan_batch(const int32_t *__restrict__ U, uint32_t urow,
-                                           const int32_t *__restrict__ L, int32_t ldL, int32_t j,
-                                           int32_t k0, int32_t step, int32_t hi, int32_t xb,
-                                           int32_t vlo, int32_t n, int32_t &best,
-                                           int32_t &bk) {
-    int32_t xs[kBatch], vs[kBatch];
-    batch_load_u(U, urow, k0, step, hi, n, xs);
-    if (step == 1)
-        batch_load_l<true>(L, ldL, j, k0, step, hi, xs, vs);
-    else
-        batch_load_l<false>(L, ldL, j, k0, step, hi, xs, vs);
-    return batch_reduce(j, k0, step, hi, xb, vlo, n, xs, vs, best, bk);
-}
-
-// Whole scan over [lo, hi] with stride step (loop of batches).
-__device__ __forceinline__ void scan_candidates(const int32_t *__restrict__ U, uint32_t urow,
-                                                const int32_t *__restrict__ L, int32_t ldL,
-                                                int32_t j, int32_t lo, int32_t hi, int32_t step,
-                                                int32_t xb, int32_t vlo, int32_t n, int32_t &best,
-                                                int32_t &bk) {
-    best = n + 2;
-    bk = -1;
-    if (lo <= hi)
-        for (int32_t k0 = lo;; k0 += kBatch * step)
-            if (scan_batch(U, urow, L, ldL, j, k0, step, hi, xb, vlo, n, best, bk)) break;
-    if (best > n) {
-        best = n + 1;
-        bk = -1;
-    }
-}
-
 // ---------------------------------------------------------------------------
 // Combine, anchor vertex (Alg. 1 with Alg. 2's tie rule).  For the vertex
 // `vtx` of parent G = U (+) L, every column j of D_G(vtx, .) is
@@ -275,23 +244,64 @@ __device__ __forceinline__ void scan_candidates(const int32_t *__restrict__ U, u
 // increasing k stops early once D_U(vtx, k) - k >= best - j: since
 // D_L(x, w) >= x + w, no later k can reach `best`.
 // Krow (global, H entries) receives k*(j) or -1; D_G row vtx receives values.
-// lds: kBlock uint64.
-__device__ void anchor_block(const int32_t *__restrict__ U, int32_t hU,
-                             const int32_t *__restrict__ L, int32_t hL, int32_t *__restrict__ G,
-                             int32_t n, int32_t vtx, int32_t *__restrict__ Krow,
-                             unsigned long long *lds) {
+// NT threads.  kLds: the D_U row and the k* row live in LDS (us: hU + 1
+// entries, ks: H entries; Krow is written once at the end), so that a
+// candidate costs one global load (the D_L gather); otherwise both are read
+// from global memory.  red: NT uint64 for the per-column minima.
+template <bool kLds>
+__device__ __forceinline__ int32_t anchor_u(const int32_t *__restrict__ U, uint32_t urow,
+                                            const int32_t *us, int32_t k, int32_t n) {
+    if (kLds) return us[k];
+    return umin(ld_cell(U, urow + (uint32_t)k), n + 1);
+}
+
+template <bool kLds>
+__device__ __forceinline__ void anchor_scan(const int32_t *__restrict__ U, uint32_t urow,
+                                            const int32_t *us, const int32_t *__restrict__ L,
+                                            int32_t ldL, int32_t j, int32_t lo, int32_t hi,
+                                            int32_t step, int32_t n, int32_t &best, int32_t &bk) {
+    best = n + 2;
+    bk = -1;
+    if (lo <= hi)
+        for (int32_t k0 = lo;; k0 += kBatch * step) {
+            int32_t xs[kBatch], vs[kBatch];
+#pragma unroll
+            for (int t = 0; t < kBatch; ++t)
+                xs[t] = anchor_u<kLds>(U, urow, us, imin(k0 + t * step, hi), n);
+            if (step == 1)
+                batch_load_l<true>(L, ldL, j, k0, step, hi, xs, vs);
+            else
+                batch_load_l<false>(L, ldL, j, k0, step, hi, xs, vs);
+            if (batch_reduce(j, k0, step, hi, n, -1, n, xs, vs, best, bk)) break;
+        }
+    if (best > n) {
+        best = n + 1;
+        bk = -1;
+    }
+}
+
+template <bool kLds, int NT>
+__device__ void anchor_block_t(const int32_t *__restrict__ U, int32_t hU,
+                               const int32_t *__restrict__ L, int32_t hL, int32_t *__restrict__ G,
+                               int32_t n, int32_t vtx, int32_t *__restrict__ Krow,
+                               unsigned long long *red, int32_t *us, int32_t *ks) {
     const int32_t INF = n + 1;
     const int32_t H = hU + hL + 1;
     int32_t P = 1;
     while (P < H + 1) P <<= 1;
     const uint32_t urow = (uint32_t)vtx * (uint32_t)(hU + 1);
     int32_t *__restrict__ grow = G + (size_t)vtx * (size_t)H;
+    int32_t *krow = kLds ? ks : Krow;
     const int32_t ldL = hL + 1;
+    if (kLds) {
+        for (int32_t k = threadIdx.x; k <= hU; k += NT) us[k] = umin(ld_cell(U, urow + (uint32_t)k), INF);
+        __syncthreads();
+    }
     for (int32_t s = P >> 1; s >= 1; s >>= 1) {
         const int32_t ncols = (H - s) >= 0 ? imin((H - s) / (2 * s) + 1, P / (2 * s)) : 0;
         int32_t g = 1;  // threads per column (power of two), all columns in one pass
-        while (2 * g <= kBlock && 2 * g * ncols <= kBlock) g <<= 1;
-        const int32_t cpp = kBlock / g;  // columns per pass
+        while (2 * g <= NT && 2 * g * ncols <= NT) g <<= 1;
+        const int32_t cpp = NT / g;  // columns per pass
         const int32_t gl = (int32_t)threadIdx.x & (g - 1);
         const int32_t slot = (int32_t)threadIdx.x / g;
         for (int32_t base = 0; base < ncols; base += cpp) {
@@ -304,41 +314,53 @@ __device__ void anchor_block(const int32_t *__restrict__ U, int32_t hU,
                 const int32_t cl = c - s, cr = c + s;
                 int32_t kl = 0, kr = hU;
                 if (cl >= 0) {
-                    kl = Krow[cl];
+                    kl = krow[cl];
                     if (kl < 0) dead = true;
                 }
                 if (cr < H) {
-                    const int32_t t2 = Krow[cr];
+                    const int32_t t2 = krow[cr];
                     if (t2 >= 0) kr = t2;
                 }
                 if (!dead) {
                     const int32_t lo = imax(kl, imax(c - hL, 0));
                     const int32_t hi = imin(kr, imin(c, hU));
                     int32_t best, bk;
-                    scan_candidates(U, urow, L, ldL, c, lo + gl, hi, g, n, -1, n, best, bk);
+                    anchor_scan<kLds>(U, urow, us, L, ldL, c, lo + gl, hi, g, n, best, bk);
                     if (best <= n) key = ((unsigned long long)(uint32_t)best << 32) | (uint32_t)bk;
                 }
             }
             if (g > 1) {
-                if (gl == 0) lds[slot] = ~0ull;
+                if (gl == 0) red[slot] = ~0ull;
                 __syncthreads();
-                if (act && !dead && key != ~0ull) atomicMin(&lds[slot], key);
+                if (act && !dead && key != ~0ull) atomicMin(&red[slot], key);
                 __syncthreads();
-                if (act && gl == 0) key = dead ? ~0ull : lds[slot];
+                if (act && gl == 0) key = dead ? ~0ull : red[slot];
                 __syncthreads();
             }
             if (act && gl == 0) {
                 if (key == ~0ull) {
-                    Krow[c] = -1;
+                    krow[c] = -1;
                     grow[c] = INF;
                 } else {
-                    Krow[c] = (int32_t)(uint32_t)(key & 0xffffffffull);
+                    krow[c] = (int32_t)(uint32_t)(key & 0xffffffffull);
                     grow[c] = (int32_t)(key >> 32);
                 }
             }
         }
         __syncthreads();
     }
+    if (kLds) {
+        for (int32_t c = threadIdx.x; c < H; c += NT) Krow[c] = ks[c];
+        __syncthreads();
+    }
+}
+
+// Global-memory form (the batch kernels: fixed LDS budget).  lds: kBlock uint64.
+__device__ __forceinline__ void anchor_block(const int32_t *__restrict__ U, int32_t hU,
+                                             const int32_t *__restrict__ L, int32_t hL,
+                                             int32_t *__restrict__ G, int32_t n, int32_t vtx,
+                                             int32_t *__restrict__ Krow, unsigned long long *lds) {
+    anchor_block_t<false, kBlock>(U, hU, L, hL, G, n, vtx, Krow, lds, nullptr, nullptr);
 }
 
 // ---------------------------------------------------------------------------

@@ -29,6 +29,26 @@ __global__ void __launch_bounds__(kBlock) k_base(const uint8_t *a, int32_t n, in
                          lds);
 }
 
+// Anchor search with the D_U row and the k* row of the vertex in LDS
+// (dynamic: NT uint64 reduction slots, hc + 1 and 2 hc + 1 int32).
+template <int NT>
+__global__ void __launch_bounds__(NT) k_anchor_lds(CombineArgs c) {
+    extern __shared__ unsigned long long dyn[];
+    const int32_t p = blockIdx.y, a = blockIdx.x;
+    const StripRef U = child_strip(c, 2 * p), L = child_strip(c, 2 * p + 1);
+    int32_t *G = parent_strip(c, p);
+    const int32_t vtx = anchor_vertex(a, c.tile, c.n);
+    int32_t *Krow = c.anch + ((size_t)p * c.nanch + a) * (size_t)c.hs;
+    int32_t *us = reinterpret_cast<int32_t *>(dyn + NT);
+    int32_t *ks = us + (c.hc + 1);
+    anchor_block_t<true, NT>(U.d, U.h, L.d, L.h, G, c.n, vtx, Krow, dyn, us, ks);
+    if (a == c.nanch - 1) {  // sentinel row n + 1
+        const int32_t H = U.h + L.h + 1;
+        int32_t *srow = G + (size_t)(c.n + 1) * H;
+        for (int32_t j = threadIdx.x; j < H; j += NT) srow[j] = c.n + 1;
+    }
+}
+
 __global__ void __launch_bounds__(kBlock) k_anchor(CombineArgs c) {
     __shared__ unsigned long long lds[kBlock];
     const int32_t p = blockIdx.y, a = blockIdx.x;
@@ -135,8 +155,39 @@ hipError_t launch_base(int32_t h0, const uint8_t *a, int32_t n, int32_t sigma, c
     return hipGetLastError();
 }
 
+// LDS available to one work-group on gfx950
+constexpr size_t kMaxGroupLds = 160 * 1024;
+
 hipError_t launch_anchor(const CombineArgs &c, int32_t npairs, hipStream_t s) {
-    hipLaunchKernelGGL(k_anchor, dim3(c.nanch, npairs), dim3(kBlock), 0, s, c);
+    // few anchors (the top levels): 1024 threads each, so that the wide
+    // columns of the first depths and the many narrow ones of the last take
+    // fewer passes
+    const int64_t blocks = (int64_t)c.nanch * npairs;
+    const int32_t nt = (blocks <= 1024) ? 1024 : kBlock;
+    const size_t bytes = (size_t)nt * 8 + 4 * ((size_t)c.hc + 1 + (size_t)c.hs);
+    if (bytes <= kMaxGroupLds) {
+        // opt in to more than 64 KB of dynamic LDS, once per device
+        static bool opted[2][64] = {};
+        int dev = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e != hipSuccess) return e;
+        const int w = (nt == 1024) ? 1 : 0;
+        if (dev >= 0 && dev < 64 && !opted[w][dev]) {
+            const void *fn = (nt == 1024) ? (const void *)k_anchor_lds<1024>
+                                          : (const void *)k_anchor_lds<kBlock>;
+            e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)kMaxGroupLds);
+            if (e != hipSuccess) return e;
+            opted[w][dev] = true;
+        }
+        if (nt == 1024)
+            hipLaunchKernelGGL(k_anchor_lds<1024>, dim3(c.nanch, npairs), dim3(1024), bytes, s, c);
+        else
+            hipLaunchKernelGGL(k_anchor_lds<kBlock>, dim3(c.nanch, npairs), dim3(kBlock), bytes, s,
+                               c);
+    } else {
+        hipLaunchKernelGGL(k_anchor, dim3(c.nanch, npairs), dim3(kBlock), 0, s, c);
+    }
     return hipGetLastError();
 }
 
