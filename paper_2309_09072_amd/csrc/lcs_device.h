@@ -399,16 +399,18 @@ __device__ __forceinline__ void anchor_block(const int32_t *__restrict__ U, int3
 // block that holds it (jn = kJChunk + 1) evaluates it directly, so the
 // bisection works on at most kJChunk weights.
 constexpr int kUWin = 64;
+constexpr int kCoarseItems = kBlock / 2;  // a level with at most this many outputs is coarse
 struct BracketSmem {
     int32_t k[(kMaxTile + 1) * kJChunk];
     int32_t v[(kMaxTile + 1) * kJChunk];
     int32_t u[(kMaxTile + 1) * kUWin];    // D_U parallelogram (row v starts at k*(i0, j0) - v)
     int32_t q[(kMaxTile / 2) * kJChunk];  // queued outputs of one level (slot * kJChunk + jj)
+    unsigned long long key[kCoarseItems];  // slice minima (value, k) of a coarse level
     int32_t qn[2];                        // queue lengths, alternating between levels
 };
 
 struct BracketWindow {
-    int32_t lo, hi, xb, vlo;
+    int32_t lo, hi, xb, vlo, vhi;
     bool dead;
 };
 
@@ -446,6 +448,7 @@ __device__ __forceinline__ BracketWindow bracket_window(const BracketSmem &sm,
     }
     w.lo = imax(ka - (v - va), imax(j - hL, 0));
     w.vlo = sm.v[va * S + jj];
+    w.vhi = sm.v[vb * S + jj];
     return w;
 }
 
@@ -489,6 +492,8 @@ __device__ __forceinline__ void bracket_pass1(BracketSmem &sm, const int32_t *__
     const int32_t H = hU + hL + 1;
     const int32_t ldU = hU + 1, ldL = hL + 1;
     const int32_t lane = __lane_id();
+    // at the finest level only values are needed (no vertex brackets another)
+    const bool finest = (st == 2);
     int32_t id[R], vr[R], jv[R], lo[R], hi[R], xb[R], vlo[R];
     bool act[R];
 #pragma unroll
@@ -510,6 +515,9 @@ __device__ __forceinline__ void bracket_pass1(BracketSmem &sm, const int32_t *__
                                                          imin(v + half, len), jj, j, hU, hL, n);
             if (w.dead || w.lo > w.hi) {
                 bracket_store(sm, id[r], G + (size_t)(i0 + v) * H + j, n, INF, -1);
+            } else if (finest && w.vlo == w.vhi) {
+                // D_G(ia, j) <= D_G(i, j) <= D_G(ib, j): the value is fixed
+                bracket_store(sm, id[r], G + (size_t)(i0 + v) * H + j, n, w.vlo, 0);
             } else {
                 act[r] = true;
                 vr[r] = v;
@@ -565,6 +573,92 @@ __device__ __forceinline__ void bracket_pass1(BracketSmem &sm, const int32_t *__
     }
 }
 
+// Coarse bisection level (at most kCoarseItems outputs, wide windows): g
+// threads per output scan consecutive slices of kBatch candidates of its
+// window in the same round, so the output sees g * kBatch candidates for one
+// round trip.  Slice minima meet through a 64-bit LDS atomic min of
+// (value, k), which keeps the smallest minimising k.  The stop tests then run
+// on the whole range; an unfinished output resumes in pass 2 after it.
+template <bool kLds>
+__device__ __forceinline__ void bracket_coarse(BracketSmem &sm, const int32_t *__restrict__ U,
+                                               int32_t hU, const int32_t *__restrict__ L,
+                                               int32_t hL, int32_t *__restrict__ G, int32_t n,
+                                               int32_t i0, int32_t len, int32_t j0, int32_t js,
+                                               int32_t half, int32_t st, int32_t nitems,
+                                               int32_t par, int32_t ubase, int32_t g) {
+    constexpr int32_t S = kJChunk;
+    const int32_t INF = n + 1;
+    const int32_t H = hU + hL + 1;
+    const int32_t ldU = hU + 1, ldL = hL + 1;
+    const int32_t lane = __lane_id();
+    {  // slices
+        const int32_t e = (int32_t)threadIdx.x / g, sub = (int32_t)threadIdx.x - e * g;
+        const int32_t t = e / S, jj = e - t * S;
+        if (e < nitems && jj < js) {
+            const int32_t v = half + t * st, j = j0 + jj;
+            const BracketWindow w = bracket_window<kLds>(sm, U, ldU, i0, ubase, v, v - half,
+                                                         imin(v + half, len), jj, j, hU, hL, n);
+            const int32_t k0 = w.lo + sub * kBatch;
+            if (!w.dead && k0 <= w.hi) {
+                int32_t xs[kBatch], vs[kBatch];
+                bracket_load_u<kBatch, kLds>(sm, U, ldU, hU, i0, ubase, v, k0, w.hi, n, xs);
+                batch_load_l<false>(L, ldL, j, k0, 1, w.hi, xs, vs);
+                int32_t best = n + 2, bk = -1;
+                batch_reduce(j, k0, 1, w.hi, w.xb, w.vlo, n, xs, vs, best, bk);
+                if (best <= n)
+                    atomicMin(&sm.key[e], ((unsigned long long)(uint32_t)best << 32) | (uint32_t)bk);
+            }
+        }
+    }
+    __syncthreads();
+    // one thread per output: stop tests on the whole range, store or queue
+    bool queued = false;
+    int32_t qid = 0;
+    const int32_t e = (int32_t)threadIdx.x;
+    const int32_t t = e / S, jj = e - t * S;
+    if (e < nitems && jj < js) {
+        const int32_t v = half + t * st, j = j0 + jj;
+        const int32_t id = v * S + jj;
+        const BracketWindow w = bracket_window<kLds>(sm, U, ldU, i0, ubase, v, v - half,
+                                                     imin(v + half, len), jj, j, hU, hL, n);
+        const unsigned long long key = sm.key[e];
+        sm.key[e] = ~0ull;  // ready for the next coarse level
+        int32_t *g_out = G + (size_t)(i0 + v) * H + j;
+        if (w.dead || w.lo > w.hi) {
+            bracket_store(sm, id, g_out, n, INF, -1);
+        } else {
+            int32_t best = n + 2, bk = -1;
+            if (key != ~0ull) {
+                best = (int32_t)(key >> 32);
+                bk = (int32_t)(uint32_t)(key & 0xffffffffull);
+            }
+            const int32_t kend = w.lo + g * kBatch - 1;
+            const int32_t xl = bracket_u<kLds>(sm, U, ldU, hU, i0, ubase, v, imin(kend, w.hi), n);
+            const bool done = (kend >= w.hi) | (xl > w.xb) | (best == w.vlo) |
+                              ((best <= n) & (xl - kend >= best - j));
+            if (done) {
+                bracket_store(sm, id, g_out, n, best, bk);
+            } else {  // provisional state; pass 2 resumes at lo + g * kBatch
+                sm.k[id] = bk;
+                sm.v[id] = best;
+                queued = true;
+                qid = id;
+            }
+        }
+    }
+    const unsigned long long mask = __ballot(queued);
+    if (mask) {
+        const int32_t leader = __ffsll((long long)mask) - 1;
+        int32_t qbase = 0;
+        if (lane == leader) qbase = atomicAdd(&sm.qn[par], __popcll(mask));
+        qbase = __shfl(qbase, leader, kWave);
+        if (queued) {
+            const unsigned long long below = mask & ((1ull << lane) - 1ull);
+            sm.q[qbase + __popcll(below)] = qid;
+        }
+    }
+}
+
 template <bool kLds>
 __device__ __forceinline__ void bracket_levels(BracketSmem &sm, const int32_t *__restrict__ U,
                                                int32_t hU, const int32_t *__restrict__ L,
@@ -582,13 +676,15 @@ __device__ __forceinline__ void bracket_levels(BracketSmem &sm, const int32_t *_
         const int32_t nv = (len > half) ? (len - half + st - 1) / st : 0;
         const int32_t nitems = nv * S;
         if (threadIdx.x == 0) sm.qn[par ^ 1] = 0;  // next level's queue (read after a barrier)
-        // batch of the first pass: 8 candidates where the windows are wide
-        // (the coarse levels), 4 at the fine levels that hold most outputs
+        // first pass: coarse levels spread each window over g threads; the
+        // fine levels (most outputs, narrow windows) take batches of 4
         int32_t b1;
-        if (st >= 8) {
-            b1 = 8;
-            bracket_pass1<1, 8, kLds>(sm, U, hU, L, hL, G, n, i0, len, j0, js, half, st, nitems,
-                                      par, ubase);
+        if (nitems <= kCoarseItems) {
+            int32_t g = 2;
+            while (2 * g * nitems <= kBlock) g <<= 1;
+            b1 = g * kBatch;
+            bracket_coarse<kLds>(sm, U, hU, L, hL, G, n, i0, len, j0, js, half, st, nitems, par,
+                                 ubase, g);
         } else if (nitems > kBlock) {
             b1 = 4;
             bracket_pass1<kBracketItems, 4, kLds>(sm, U, hU, L, hL, G, n, i0, len, j0, js, half,
@@ -654,6 +750,7 @@ __device__ void bracket_block(const int32_t *__restrict__ U, int32_t hU,
         sm.v[slot * S + jj0] = G[(size_t)vert * H + j0 + jj0];
     }
     if (threadIdx.x < 2) sm.qn[threadIdx.x] = 0;
+    if (threadIdx.x < kCoarseItems) sm.key[threadIdx.x] = ~0ull;
     if (jn > S) {  // weight j0 + S = hU + hL: one candidate, k = hU
         const int32_t j = j0 + S;
         for (int32_t v = 1 + (int32_t)threadIdx.x; v < len; v += kBlock) {
