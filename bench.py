@@ -206,7 +206,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(WORKLOADS))
     ap.add_argument("--base-rows", type=int, default=64)
-    ap.add_argument("--tile", type=int, default=32)
+    ap.add_argument("--tile", type=int, default=0,
+                    help="vertices between anchor searches; 0: chosen by the autotuner")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
@@ -234,6 +235,13 @@ def main():
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
     ad, bd = lcs.device_bytes(pair.a), lcs.device_bytes(pair.b)
+    tuning = None
+    if args.tile == 0:  # the autotuner picks the tile for this base-strip height
+        from paper_2309_09072_amd import tune
+        tr = tune.tune_pair(ad, bd, pair.sigma, base_rows=args.base_rows, use_cache=False)
+        args.tile = tr.best[1]
+        tuning = tr.as_json()
+        log("autotuner: tile %d (%s)" % (args.tile, tuning["ms"]))
     plan = lcs.Plan(m, n, pair.sigma, args.base_rows, args.tile)
     pplan = lcs.Plan(m, n, pair.sigma, args.base_rows, args.tile, profile=True)
     ws = lcs.alloc_workspace(plan.workspace_for(m, n))
@@ -315,7 +323,7 @@ def main():
 
     cells = m * n
     out = {
-        "metric": "LCS cells/s (m*n/s) + HBM GB/s; exact match",
+        "metric": "LCS cells/s (m\u00b7n/s) + HBM GB/s; batched vs one-pair-per-launch, exact match",
         "value": cells / (ms_per_step * 1e-3) if exact else None,
         "unit": "cells/s",
         "n_gpus": 1,
@@ -330,6 +338,7 @@ def main():
         "config": {"workload": args.workload, "m": m, "n": n, "alphabet": pair.sigma,
                    "seed": pair.seed, "base_rows": args.base_rows, "tile": args.tile,
                    "parallelism": "single-gpu"},
+        "autotune": tuning,
         "exact_match": bool(exact),
         "lcs_length": Lg,
         "alg_GBps_whole_build": round(total_alg / (ms_per_step * 1e-3) / 1e9, 1),

@@ -309,8 +309,79 @@ __global__ void __launch_bounds__(kBlock) k_stage(BatchArgs A, StageArgs S) {
     exec_task<H0>(A, s_pu[0], KIND, S.level, s_pu[1], sm);
 }
 
+// Staged anchor search with the vertex's D_U row and k* row in dynamic LDS
+// (kBlock uint64, hc + 1 and 2 hc + 1 int32; hc = child strip height, the
+// same for every pair at one level).
+template <int H0>
+__global__ void __launch_bounds__(kBlock) k_stage_anchor_lds(BatchArgs A, StageArgs S, int32_t hc) {
+    extern __shared__ unsigned long long dyn[];
+    __shared__ int32_t s_pu[2];
+    const int64_t t = blockIdx.x;
+    if (threadIdx.x == 0) {
+        int32_t lo = 0, hi = S.npairs - 1;
+        while (lo < hi) {
+            const int32_t mid = (lo + hi + 1) >> 1;
+            if (S.first[mid] <= t)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        s_pu[0] = S.pair[lo];
+        s_pu[1] = (int32_t)(t - S.first[lo]);
+    }
+    __syncthreads();
+    const int32_t p = s_pu[0], u = s_pu[1];
+    const PairRec &P = A.pairs[p];
+    uint8_t *ws = A.ws + P.ws_off;
+    const CombineArgs c = pair_combine_args(P, ws, S.level, A.tile);
+    const int32_t q = u / P.nanch, an = u - q * P.nanch;
+    const StripRef U = child_strip(c, 2 * q), L = child_strip(c, 2 * q + 1);
+    int32_t *G = parent_strip(c, q);
+    int32_t *us = reinterpret_cast<int32_t *>(dyn + kBlock);
+    int32_t *ks = us + (hc + 1);
+    anchor_block_t<true, kBlock>(U.d, U.h, L.d, L.h, G, P.n, anchor_vertex(an, A.tile, P.n),
+                                 c.anch + ((size_t)q * c.nanch + an) * (size_t)c.hs, dyn, us, ks);
+    if (an == c.nanch - 1) {
+        const int32_t H = U.h + L.h + 1;
+        int32_t *srow = G + (size_t)(P.n + 1) * H;
+        for (int32_t j = threadIdx.x; j < H; j += kBlock) srow[j] = P.n + 1;
+    }
+}
+
+// dynamic LDS a staged anchor search may take: what one work-group of gfx950
+// can hold (160 KB) minus room for the kernel's static LDS
+constexpr size_t kStageMaxLds = 159 * 1024;
+
+// Opt the staged anchor kernels in to more than 64 KB of dynamic LDS, once per
+// device (also called at plan time, outside any graph capture).
+static hipError_t opt_in_stage_lds() {
+    static bool opted[64] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= 64 || opted[dev]) return hipSuccess;
+    const void *fns[3] = {(const void *)k_stage_anchor_lds<16>, (const void *)k_stage_anchor_lds<32>,
+                          (const void *)k_stage_anchor_lds<64>};
+    for (const void *f : fns) {
+        e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kStageMaxLds);
+        if (e != hipSuccess) return e;
+    }
+    opted[dev] = true;
+    return hipSuccess;
+}
+
 template <int H0>
 static hipError_t launch_stage(const BatchArgs &A, const StageArgs &S, dim3 grid, hipStream_t st) {
+    if (S.kind == ST_ANCHOR && S.level >= 1 && S.level < kMaxLev) {
+        const int32_t hc = H0 << (S.level - 1);
+        const size_t bytes = (size_t)kBlock * 8 + 4 * ((size_t)hc + 1 + 2 * (size_t)hc + 1);
+        if (bytes <= kStageMaxLds) {
+            const hipError_t e = opt_in_stage_lds();
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL((k_stage_anchor_lds<H0>), grid, dim3(kBlock), bytes, st, A, S, hc);
+            return hipGetLastError();
+        }
+    }
     switch (S.kind) {
         case ST_EMPTY: hipLaunchKernelGGL((k_stage<H0, ST_EMPTY>), grid, dim3(kBlock), 0, st, A, S); break;
         case ST_NM_SYM: hipLaunchKernelGGL((k_stage<H0, ST_NM_SYM>), grid, dim3(kBlock), 0, st, A, S); break;
@@ -433,12 +504,22 @@ extern "C" int32_t lcs_batch_plan(const lcs_batch_desc *desc, lcs_batch_t *out, 
         default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_persistent<64>, kBlock, 0); break;
     }
     if (e != hipSuccess || per < 1 || ncu < 1) {
+        hipHostFree(b->host_stage);
         hipHostFree(b->host_pairs);
         delete b;
         return LCS_E_HIP;
     }
     b->resident = per * ncu;
     if (hipEventCreateWithFlags(&b->copied, hipEventDisableTiming) != hipSuccess) {
+        hipHostFree(b->host_stage);
+        hipHostFree(b->host_pairs);
+        delete b;
+        return LCS_E_HIP;
+    }
+    if (opt_in_stage_lds() != hipSuccess) {  // done here, outside any graph capture
+        (void)hipGetLastError();
+        hipEventDestroy(b->copied);
+        hipHostFree(b->host_stage);
         hipHostFree(b->host_pairs);
         delete b;
         return LCS_E_HIP;
