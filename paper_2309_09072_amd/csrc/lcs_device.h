@@ -719,7 +719,7 @@ __device__ __forceinline__ void bracket_levels(BracketSmem &sm, const int32_t *_
     }
 }
 
-__device__ void bracket_block(const int32_t *__restrict__ U, int32_t hU,
+__device__ __forceinline__ void bracket_block(const int32_t *__restrict__ U, int32_t hU,
                               const int32_t *__restrict__ L, int32_t hL, int32_t *__restrict__ G,
                               int32_t n, int32_t i0, int32_t len, int32_t j0, int32_t jn,
                               const int32_t *__restrict__ Ka, const int32_t *__restrict__ Kb,
