@@ -45,6 +45,23 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9  # CUs x SIMDs x lanes x clock: 39.3 T lane-ops/s
+
+
+def read_valu(workload: str, kernel: str):
+    """VALU wave-instructions per launch from the committed counter summary, if it
+    was taken on the current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", "valu_%s_%s.md" % (kernel, workload))
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    src = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", txt)
+    val = re.search(r"valu_insts_per_launch:\s*([0-9.eE+]+)", txt)
+    if not src or not val or src.group(1) != kernel_source_hash():
+        return None
+    return float(val.group(1))
+
+
 def read_traffic(workload: str, kernel: str):
     """HBM bytes per launch from the committed counter summary, if it was taken
     on the current kernel sources (else None)."""
@@ -180,7 +197,7 @@ def bench_serving(count: int, budget_gb: float, slots: int):
     out = {"workload": "serving-poisson-128..8192", "requests": count, "slots": slots,
            "budget_GB": budget_gb, "saturation_req_per_s": round(r_sat, 1),
            "saturation_cells_per_s": cells / wall}
-    for frac in (0.7,):
+    for frac in (0.5, 0.7, 0.9):
         reqs, res, bufs, wall, lat, cells, peak = run(frac * r_sat)
         items = []
         for r in reqs:
@@ -309,6 +326,12 @@ def main():
     achieved = per_launch_bytes / per_launch_s / 1e9
     kernel_name = {"base": "k_base", "anchor": "k_anchor", "bracket": "k_bracket"}[dom]
     traffic = read_traffic(args.workload, kernel_name)
+    valu_insts = read_valu(args.workload, kernel_name)
+    valu = None
+    if valu_insts is not None:  # wave instructions x 64 lanes per launch / launch time
+        lane_ops = valu_insts * 64 / per_launch_s
+        valu = {"lane_ops_per_s": lane_ops, "peak": VALU_PEAK_LANE_OPS,
+                "frac": round(lane_ops / VALU_PEAK_LANE_OPS, 4), "insts_per_launch": valu_insts}
     total_alg = sum(v["bytes"] for k, v in by.items() if k in ("nextmatch", "base", "anchor", "bracket", "length")) / args.steps
     log("breakdown: " + json.dumps(breakdown))
 
@@ -352,6 +375,7 @@ def main():
             "traffic": traffic,
             "alg_bytes_per_launch": int(per_launch_bytes),
             "avg_launch_ms": round(per_launch_s * 1e3, 4),
+            "valu": valu,
         },
         "breakdown": breakdown,
     }
