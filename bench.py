@@ -126,17 +126,18 @@ def bench_batched(reps: int):
     out = {"workload": batch.name, "pairs": batch.count, "cells": batch.cells, "seed": batch.seed,
            "slots": 512, "workspace_GB": round(ws.numel() / 1e9, 2)}
     for name, mode in (("staged_graph", lcs.BATCH_STAGED | lcs.BATCH_GRAPH),
+                       ("pair_queue_graph", lcs.BATCH_PAIR_QUEUE | lcs.BATCH_GRAPH),
                        ("persistent_graph", lcs.BATCH_PERSISTENT | lcs.BATCH_GRAPH),
                        ("one_pair_per_launch", lcs.BATCH_PER_PAIR)):
         plan.submit(sym, batch.a_off, batch.b_off, batch.m, batch.n, ws, lengths, ai, bi, mode)
         torch.cuda.synchronize()
-        n = reps if mode & lcs.BATCH_STAGED else 1
+        n = reps if mode & (lcs.BATCH_STAGED | lcs.BATCH_PAIR_QUEUE) else 1
         t0 = time.perf_counter()
         for _ in range(n):
             plan.submit(sym, batch.a_off, batch.b_off, batch.m, batch.n, ws, lengths, ai, bi, mode)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / n
-        if not (mode & (lcs.BATCH_PER_PAIR | lcs.BATCH_STAGED)):
+        if not (mode & (lcs.BATCH_PER_PAIR | lcs.BATCH_STAGED | lcs.BATCH_PAIR_QUEUE)):
             plan.status(ws)
         L = lengths.cpu().numpy()
         A, B = ai.cpu().numpy(), bi.cpu().numpy()
@@ -147,6 +148,8 @@ def bench_batched(reps: int):
         log("batched %s: %.3f s per batch, %.3g cells/s, exact=%s" % (name, dt, batch.cells / dt, exact))
     out["speedup_staged_vs_per_pair"] = round(
         out["one_pair_per_launch"]["s_per_batch"] / out["staged_graph"]["s_per_batch"], 2)
+    out["speedup_pair_queue_vs_per_pair"] = round(
+        out["one_pair_per_launch"]["s_per_batch"] / out["pair_queue_graph"]["s_per_batch"], 2)
     out["speedup_persistent_vs_per_pair"] = round(
         out["one_pair_per_launch"]["s_per_batch"] / out["persistent_graph"]["s_per_batch"], 2)
     del ws

@@ -212,6 +212,11 @@ typedef struct lcs_pair_desc {
 #define LCS_BATCH_STAGED 4u     /* one launch per step of the method across all pairs
                                    (work-groups over every pair's items); pairs are
                                    packed into the slot area in waves */
+#define LCS_BATCH_PAIR_QUEUE 8u /* one persistent launch whose work-groups take whole
+                                   pairs from a device queue (largest first) and run
+                                   every step of a pair in order, separated by
+                                   work-group barriers, in the work-group's own slot:
+                                   no waits between work-groups */
 
 typedef struct lcs_batch_desc {
     int32_t max_pairs; /* most pairs per submit */
@@ -242,8 +247,9 @@ int32_t lcs_batch_destroy(lcs_batch_t batch);
  *              wit_off[p] = sum over q < p of min(m_q, n_q); witness_capacity
  *              must be >= that sum over all pairs.  May be NULL (lengths only)
  *              when witness_capacity is 0.
- *   mode       LCS_BATCH_PERSISTENT, LCS_BATCH_STAGED or LCS_BATCH_PER_PAIR,
- *              optionally OR LCS_BATCH_GRAPH (not with PER_PAIR).
+ *   mode       LCS_BATCH_PERSISTENT, LCS_BATCH_PAIR_QUEUE, LCS_BATCH_STAGED or
+ *              LCS_BATCH_PER_PAIR, optionally OR LCS_BATCH_GRAPH (not with
+ *              PER_PAIR).
  * Asynchronous on `stream`.  Submits of one batch handle must not overlap:
  * the call waits until the previous submit has consumed its staged pair
  * records.  Errors: LCS_E_INVAL, LCS_E_TOO_BIG,

@@ -131,10 +131,9 @@ __device__ __forceinline__ int32_t level_chunks(const PairRec &P, int32_t l) {
 
 // One task of pair p (all threads of the work-group).
 template <int H0>
-__device__ __forceinline__ void exec_task(const BatchArgs &A, int32_t p, int32_t kind, int32_t l, int32_t u,
-                          PersistentSmem &sm) {
+__device__ __forceinline__ void exec_task(const BatchArgs &A, uint8_t *ws, int32_t p, int32_t kind,
+                                          int32_t l, int32_t u, PersistentSmem &sm) {
     const PairRec &P = A.pairs[p];
-    uint8_t *ws = A.ws + P.ws_off;
     int32_t *hdr = reinterpret_cast<int32_t *>(ws + P.off_hdr);
     int32_t *nm = reinterpret_cast<int32_t *>(ws + P.off_nm);
     const uint8_t *a = A.symbols + P.a_off;
@@ -269,11 +268,43 @@ __global__ void __launch_bounds__(kBlock) k_persistent(BatchArgs A) {
         __syncthreads();
         const int32_t kind = s_task.kind;
         if (kind < 0) break;
-        if (s_ok) exec_task<H0>(A, s_task.pair, kind, s_task.level, s_task.u, sm);
+        if (s_ok)
+            exec_task<H0>(A, A.ws + A.pairs[s_task.pair].ws_off, s_task.pair, kind, s_task.level,
+                          s_task.u, sm);
         __syncthreads();
         if (threadIdx.x == 0)
             for (int32_t i = 0; i < s_task.nsig; ++i) signal(A.ctr + s_task.sig_idx[i]);
         __syncthreads();
+    }
+}
+
+// Pair queue: a work-group takes whole pairs from the queue A.next (in the
+// host's order, largest first, for balance) and runs the stages of each in
+// order, every task of a stage and every stage separated by a work-group
+// barrier; all of a pair's matrices live in the work-group's own slot.
+// Nothing waits on another work-group.
+template <int H0>
+__global__ void __launch_bounds__(kBlock) k_pair_queue(BatchArgs A, const int32_t *order,
+                                                        int64_t off_slots, int64_t slot_bytes) {
+    __shared__ PersistentSmem sm;
+    __shared__ int32_t s_q;
+    uint8_t *ws = A.ws + off_slots + (int64_t)blockIdx.x * slot_bytes;
+    for (;;) {
+        if (threadIdx.x == 0) s_q = (int32_t)atomicAdd(A.next, 1ull);
+        __syncthreads();
+        const int32_t q = s_q;
+        __syncthreads();
+        if (q >= A.npairs) break;
+        const int32_t p = order[q];
+        const PairRec &P = A.pairs[p];
+        for (int32_t st = 0; st < P.nstages; ++st) {
+            const int32_t kind = P.stage_kind[st], l = P.stage_level[st];
+            const int32_t nu = P.stage_start[st + 1] - P.stage_start[st];
+            for (int32_t u = 0; u < nu; ++u) {
+                exec_task<H0>(A, ws, p, kind, l, u, sm);
+                __syncthreads();
+            }
+        }
     }
 }
 
@@ -306,7 +337,7 @@ __global__ void __launch_bounds__(kBlock) k_stage(BatchArgs A, StageArgs S) {
         s_pu[1] = (int32_t)(t - S.first[lo]);
     }
     __syncthreads();
-    exec_task<H0>(A, s_pu[0], KIND, S.level, s_pu[1], sm);
+    exec_task<H0>(A, A.ws + A.pairs[s_pu[0]].ws_off, s_pu[0], KIND, S.level, s_pu[1], sm);
 }
 
 // Staged anchor search with the vertex's D_U row and k* row in dynamic LDS
@@ -417,6 +448,7 @@ struct lcs_batch_s {
     int64_t off_ctl = 0, off_pairs = 0, off_ctr = 0, off_slots = 0, total = 0;
     PairRec *host_pairs = nullptr;  // pinned staging of the pair records
     int32_t resident = 0;           // work-groups of the persistent kernel that fit at once
+    int32_t resident_pq = 0;        // the same for the pair-queue kernel
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
     uint64_t gkey = 0;
@@ -510,6 +542,19 @@ extern "C" int32_t lcs_batch_plan(const lcs_batch_desc *desc, lcs_batch_t *out, 
         return LCS_E_HIP;
     }
     b->resident = per * ncu;
+    int per_pq = 0;
+    switch (b->d.base_rows) {
+        case 16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_pq, k_pair_queue<16>, kBlock, 0); break;
+        case 32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_pq, k_pair_queue<32>, kBlock, 0); break;
+        default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_pq, k_pair_queue<64>, kBlock, 0); break;
+    }
+    if (e != hipSuccess || per_pq < 1) {
+        hipHostFree(b->host_stage);
+        hipHostFree(b->host_pairs);
+        delete b;
+        return LCS_E_HIP;
+    }
+    b->resident_pq = per_pq * ncu;
     if (hipEventCreateWithFlags(&b->copied, hipEventDisableTiming) != hipSuccess) {
         hipHostFree(b->host_stage);
         hipHostFree(b->host_pairs);
@@ -608,9 +653,13 @@ extern "C" int32_t lcs_batch_submit(lcs_batch_t B, const lcs_pair_desc *pairs, i
                                     void *stream) {
     if (!B || (count > 0 && (!pairs || !lengths)) || count < 0 || !workspace) return LCS_E_INVAL;
     if (count > B->d.max_pairs) return LCS_E_TOO_BIG;
-    if ((mode & ~(uint32_t)(LCS_BATCH_PER_PAIR | LCS_BATCH_GRAPH | LCS_BATCH_STAGED)) != 0 ||
-        ((mode & LCS_BATCH_PER_PAIR) && (mode & LCS_BATCH_STAGED)))
-        return LCS_E_INVAL;
+    {
+        const uint32_t kinds = mode & (LCS_BATCH_PER_PAIR | LCS_BATCH_STAGED | LCS_BATCH_PAIR_QUEUE);
+        if ((mode & ~(uint32_t)(LCS_BATCH_PER_PAIR | LCS_BATCH_GRAPH | LCS_BATCH_STAGED |
+                                LCS_BATCH_PAIR_QUEUE)) != 0 ||
+            (kinds & (kinds - 1)) != 0)  // at most one of them
+            return LCS_E_INVAL;
+    }
     if ((size_t)B->total > workspace_bytes) return LCS_E_WORKSPACE;
     if (reinterpret_cast<uintptr_t>(workspace) & 255) return LCS_E_INVAL;
     int64_t wit = 0;
@@ -736,6 +785,14 @@ extern "C" int32_t lcs_batch_submit(lcs_batch_t B, const lcs_pair_desc *pairs, i
         }
         if (soff > B->stage_bytes) return LCS_E_TOO_BIG;
     }
+    if (mode & LCS_BATCH_PAIR_QUEUE) {  // queue order: largest pair first
+        if (4 * (int64_t)count > B->stage_bytes) return LCS_E_TOO_BIG;
+        int32_t *order = reinterpret_cast<int32_t *>(B->host_stage);
+        for (int32_t p = 0; p < count; ++p) order[p] = p;
+        std::stable_sort(order, order + count, [&](int32_t x, int32_t y) {
+            return (int64_t)pairs[x].m * pairs[x].n > (int64_t)pairs[y].m * pairs[y].n;
+        });
+    }
     BatchArgs A;
     A.pairs = reinterpret_cast<const PairRec *>(ws + B->off_pairs);
     A.npairs = count;
@@ -783,6 +840,23 @@ extern "C" int32_t lcs_batch_submit(lcs_batch_t B, const lcs_pair_desc *pairs, i
                 if (e != hipSuccess) return LCS_E_HIP;
             }
             return LCS_OK;
+        }
+        if (mode & LCS_BATCH_PAIR_QUEUE) {
+            if (hipMemcpyAsync(ws + B->off_stage, B->host_stage, 4 * (size_t)count,
+                               hipMemcpyHostToDevice, st) != hipSuccess)
+                return LCS_E_HIP;
+            if (hipEventRecord(B->copied, st) != hipSuccess) return LCS_E_HIP;
+            hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, st,
+                               reinterpret_cast<int32_t *>(ws + B->off_ctl), (int64_t)16, 0);
+            // one slot per work-group: at most `slots` of them
+            const int32_t g = std::max(1, std::min(std::min(B->resident_pq, B->d.slots), count));
+            const int32_t *order = reinterpret_cast<const int32_t *>(ws + B->off_stage);
+            switch (B->d.base_rows) {
+                case 16: hipLaunchKernelGGL(k_pair_queue<16>, dim3(g), dim3(kBlock), 0, st, A, order, B->off_slots, B->slot_bytes); break;
+                case 32: hipLaunchKernelGGL(k_pair_queue<32>, dim3(g), dim3(kBlock), 0, st, A, order, B->off_slots, B->slot_bytes); break;
+                default: hipLaunchKernelGGL(k_pair_queue<64>, dim3(g), dim3(kBlock), 0, st, A, order, B->off_slots, B->slot_bytes); break;
+            }
+            return hipGetLastError() == hipSuccess ? LCS_OK : LCS_E_HIP;
         }
         if (hipEventRecord(B->copied, st) != hipSuccess) return LCS_E_HIP;
         hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, st, reinterpret_cast<int32_t *>(ws + B->off_ctl),

@@ -22,7 +22,7 @@ STATUS = {
     -5: "LCS_E_SYMBOL", -6: "LCS_E_CAPACITY", -7: "LCS_E_STATE", -8: "LCS_E_NOMEM",
     -9: "LCS_E_BUDGET", -10: "LCS_E_AGAIN",
 }
-BATCH_PERSISTENT, BATCH_PER_PAIR, BATCH_GRAPH, BATCH_STAGED = 0, 1, 2, 4
+BATCH_PERSISTENT, BATCH_PER_PAIR, BATCH_GRAPH, BATCH_STAGED, BATCH_PAIR_QUEUE = 0, 1, 2, 4, 8
 
 
 class LcsError(RuntimeError):
@@ -372,7 +372,7 @@ def run_batch(batch, mode: int = BATCH_PERSISTENT, base_rows: int = 0, tile: int
     bi = torch.full((max(int(off[-1]), 1),), -1, dtype=torch.int32, device=device)
     b.submit(sym, batch.a_off, batch.b_off, batch.m, batch.n, ws, lengths, ai, bi, mode)
     torch.cuda.synchronize()
-    if not (mode & (BATCH_PER_PAIR | BATCH_STAGED)):
+    if not (mode & (BATCH_PER_PAIR | BATCH_STAGED | BATCH_PAIR_QUEUE)):
         b.status(ws)
     return lengths.cpu().numpy(), ai.cpu().numpy(), bi.cpu().numpy(), off
 

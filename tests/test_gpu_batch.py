@@ -60,6 +60,28 @@ def test_staged_matches_oracle(base_rows, tile, slots):
     check(batch, *res)
 
 
+@pytest.mark.parametrize("base_rows,tile,slots", [(16, 8, 3), (32, 32, 0), (64, 16, 1)])
+def test_pair_queue_matches_oracle(base_rows, tile, slots):
+    """Pair queue: one work-group per pair; fewer slots than pairs means a
+    work-group runs many pairs in its slot."""
+    batch = mixed_small(60, 60 + base_rows)
+    say("pair queue", base_rows, tile, slots)
+    res = L.run_batch(batch, L.BATCH_PAIR_QUEUE, base_rows, tile, slots)
+    check(batch, *res)
+
+
+def test_pair_queue_graph_replays():
+    batch = mixed_small(40, 79)
+    plan = L.Batch(batch.count, 300, 4, 32, 16, 6)
+    ws = L.alloc_workspace(plan.workspace_bytes)
+    r1 = L.run_batch(batch, L.BATCH_PER_PAIR, planned=plan, ws=ws)
+    check(batch, *r1)
+    for rep in range(3):
+        r2 = L.run_batch(batch, L.BATCH_PAIR_QUEUE | L.BATCH_GRAPH, planned=plan, ws=ws)
+        for x, y in zip(r1, r2):
+            assert np.array_equal(x, y), "replay %d differs" % rep
+
+
 def test_staged_graph_replays():
     batch = mixed_small(40, 78)
     plan = L.Batch(batch.count, 300, 4, 32, 16, 4)
@@ -93,15 +115,16 @@ def test_bad_symbol_only_fails_its_pair():
              for _ in range(6)]
     pairs[3] = (np.array([0, 1, 7, 2], np.uint8), np.array([0, 1, 2], np.uint8))
     batch = synth.batch_from_pairs(pairs, 4)
-    lengths, ai, bi, off = L.run_batch(batch, L.BATCH_PERSISTENT, 16, 8, 2)
-    assert lengths[3] == -5
-    check(batch, lengths, ai, bi, off, skip=(3,))
+    for mode in (L.BATCH_PERSISTENT, L.BATCH_PAIR_QUEUE):
+        lengths, ai, bi, off = L.run_batch(batch, mode, 16, 8, 2)
+        assert lengths[3] == -5
+        check(batch, lengths, ai, bi, off, skip=(3,))
 
 
 def test_mixed_workload_sample():
     """512 pairs of the 64..2048 mixed workload (half unrelated, half mutated copies)."""
     batch = synth.batch_mixed(count=512, seed=synth.SEED_BASE + 40)
     say("mixed 512 pairs, cells", batch.cells)
-    for mode in (L.BATCH_STAGED, L.BATCH_PERSISTENT):
+    for mode in (L.BATCH_STAGED, L.BATCH_PERSISTENT, L.BATCH_PAIR_QUEUE):
         res = L.run_batch(batch, mode, 64, 32, 0)
         check(batch, *res)
