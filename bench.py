@@ -219,6 +219,70 @@ def bench_serving(count: int, budget_gb: float, slots: int):
     return out
 
 
+# Table I of the paper: seconds per LCS of its Chapel implementation on Xeon
+# Gold 6330 cores, for string lengths (s1, s2); {s1: (32-core row, 8-core row)}.
+PAPER_TABLE_I = {
+    1024: ((0.119569, 0.62156, 1.63747, 3.2784), (0.370135, 1.5887, 2.30283, 4.75351)),
+    2048: ((0.890801, 2.4456, 4.51969, 12.2226), (1.37578, 6.31841, 8.03229, 19.2526)),
+    4096: ((6.64456, 11.1501, 16.5999, 51.9423), (5.35454, 21.2137, 33.1638, 72.9992)),
+    8192: ((29.5529, 53.5266, 67.5972, 190.575), (28.722, 88.2542, 145.517, 417.969)),
+}
+PAPER_S2 = (2, 4, 8, 16)
+
+
+def paper_sweep(steps: int, warmup: int):
+    """The paper's Table I shapes on one GPU (both orientations: the long string
+    on the rows, then on the columns), exact-checked, beside the paper's seconds."""
+    import numpy as np
+    import torch
+    import oracle
+    import paper_2309_09072_amd.synth as synth
+    from paper_2309_09072_amd import lcs
+    g = np.random.default_rng(synth.SEED_BASE + 90)
+    rows = []
+    for s1, (t32, t8) in sorted(PAPER_TABLE_I.items()):
+        for c, s2 in enumerate(PAPER_S2):
+            x, y = synth.uniform(g, s1, 4), synth.uniform(g, s2, 4)
+            want = oracle.lcs_witness(x, y)
+            entry = {"s1": s1, "s2": s2, "paper_s_32_cores": t32[c], "paper_s_8_cores": t8[c]}
+            for name, (a, b) in (("long_rows", (x, y)), ("long_cols", (y, x))):
+                m, n = a.size, b.size
+                ad, bd = lcs.device_bytes(a), lcs.device_bytes(b)
+                plan = lcs.Plan(m, n, 4, 64, 32)
+                ws = lcs.alloc_workspace(plan.workspace_for(m, n))
+                cap = max(1, min(m, n))
+                ai = torch.empty(cap, dtype=torch.int32, device="cuda")
+                bi = torch.empty(cap, dtype=torch.int32, device="cuda")
+                ld = torch.zeros(1, dtype=torch.int32, device="cuda")
+
+                def step():
+                    plan.build(ad, bd, ws)
+                    plan.trace_device(ai, bi, ld)
+
+                for _ in range(warmup):
+                    step()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                torch.cuda.synchronize()
+                e0.record()
+                for _ in range(steps):
+                    step()
+                e1.record()
+                torch.cuda.synchronize()
+                us = e0.elapsed_time(e1) * 1e3 / steps
+                L = int(ld.item())
+                ref = oracle.lcs_witness(a, b)
+                exact = (L == ref[0] and np.array_equal(ai[:L].cpu().numpy(), ref[1])
+                         and np.array_equal(bi[:L].cpu().numpy(), ref[2]))
+                assert L == want[0]
+                entry[name] = {"us_per_lcs": round(us, 2), "exact_match": bool(exact),
+                               "speedup_vs_paper_32_cores": round(t32[c] / (us * 1e-6), 1)}
+                plan.close()
+            rows.append(entry)
+            log("paper shape %dx%d: %s us (long rows), %s us (long cols); paper 32 cores %.3g s" % (
+                s1, s2, entry["long_rows"]["us_per_lcs"], entry["long_cols"]["us_per_lcs"], t32[c]))
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -236,6 +300,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=400)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also launch one plain device copy of this many MiB (counter calibration)")
+    ap.add_argument("--paper-sweep", action="store_true",
+                    help="instead: the paper's Table I shapes (one JSON line of its own)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -248,6 +314,14 @@ def main():
 
     import paper_2309_09072_amd.synth as synth
     from paper_2309_09072_amd import lcs
+
+    if args.paper_sweep:
+        torch.cuda.set_device(0)
+        rows = paper_sweep(max(args.steps, 5), max(args.warmup, 1))
+        print(json.dumps({"metric": "microseconds per LCS, paper Table I shapes", "unit": "us",
+                          "higher_is_better": False, "n_gpus": 1, "dtype": "int32",
+                          "data": "synthetic", "rows": rows}))
+        return
 
     pair = getattr(synth, WORKLOADS[args.workload])()
     m, n = int(pair.a.size), int(pair.b.size)

@@ -153,6 +153,20 @@ int32_t lcs_trace_device(lcs_plan_t plan, int32_t *a_idx, int32_t *b_idx, int32_
                          int32_t *length_dev, void *stream);
 
 /*
+ * Semi-local LCS queries on the last build: out[q] = LCS(a, b[i_q : k_q]) for
+ * count queries with 0 <= i_q <= k_q <= n, read from the top breakout matrix
+ * (Section II-B-1: D(i, j) is the smallest end column c with
+ * LCS(a, b[i:c]) >= j, so the answer is the largest j with D(i, j) <= k;
+ * one binary search over row i).  qi, qk: device int32[count] (column
+ * indices, 0-based, half-open substring); out: device int32[count]; a query
+ * outside 0 <= i <= k <= n gets -1.  Asynchronous on `stream`, graph-safe.
+ * Errors: LCS_E_INVAL (null pointer with count > 0, count < 0),
+ * LCS_E_STATE (no build), LCS_E_HIP.
+ */
+int32_t lcs_semilocal(lcs_plan_t plan, const int32_t *qi, const int32_t *qk, int32_t count,
+                      int32_t *out, void *stream);
+
+/*
  * Per-kernel timing of a plan made with LCS_PLAN_PROFILE: one record per
  * launch of every build and trace since the records were last read, in launch
  * order, measured with HIP events recorded on the caller's stream right

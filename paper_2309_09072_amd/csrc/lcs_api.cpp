@@ -290,6 +290,22 @@ extern "C" int32_t lcs_length_device(lcs_plan_t p, int32_t *length_dev, void *st
                : LCS_E_HIP;
 }
 
+extern "C" int32_t lcs_semilocal(lcs_plan_t p, const int32_t *qi, const int32_t *qk, int32_t count,
+                                 int32_t *out, void *stream) {
+    if (!p || count < 0 || (count > 0 && (!qi || !qk || !out))) return LCS_E_INVAL;
+    if (!p->built) return LCS_E_STATE;
+    const int32_t *top = nullptr;
+    int32_t m = 0;
+    if (!p->empty) {
+        top = reinterpret_cast<const int32_t *>(p->ws + p->lay.lev.back().last_off);
+        m = p->lay.m;
+    }
+    return launch_semilocal(top, m, p->lay.n, qi, qk, count, out, static_cast<hipStream_t>(stream)) ==
+                   hipSuccess
+               ? LCS_OK
+               : LCS_E_HIP;
+}
+
 extern "C" int32_t lcs_trace(lcs_plan_t p, int32_t *a_idx, int32_t *b_idx, int32_t capacity,
                              int32_t *length_host, void *stream) {
     if (!p || !length_host) return LCS_E_INVAL;

@@ -807,6 +807,26 @@ __device__ void length_block(const int32_t *__restrict__ top, int32_t m, int32_t
 }
 
 // ---------------------------------------------------------------------------
+// Semi-local query: LCS(a, b[i:k]) = the largest j with D_top(i, j) <= k
+// (D_top(i, .) is strictly increasing on its finite prefix and
+// D_top(i, 0) = i).  top: (n+2) x (m+1); m = 0 (no matrix) answers 0.
+__device__ __forceinline__ int32_t semilocal_query(const int32_t *__restrict__ top, int32_t m,
+                                                   int32_t n, int32_t i, int32_t k) {
+    if (i < 0 || k < i || k > n) return -1;
+    if (m == 0) return 0;
+    const int32_t *__restrict__ row = top + (size_t)i * (size_t)(m + 1);
+    int32_t lo = 0, hi = m;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (row[mid] <= k)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// ---------------------------------------------------------------------------
 // Midpoint trace, one split (Section II-D).  Node (source s, weight w, end e)
 // of G = U (+) L, with e = D_G(s, w).  The cross vertex on the boundary row is
 // x = D_U(s, k*) for the SMALLEST k with D_L(D_U(s, k), w - k) == e (Alg. 2's

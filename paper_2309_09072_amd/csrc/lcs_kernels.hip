@@ -115,6 +115,12 @@ __global__ void __launch_bounds__(kBlock) k_trace_leaf(const uint8_t *a, int32_t
                          err, lds);
 }
 
+__global__ void __launch_bounds__(kBlock) k_semilocal(const int32_t *top, int32_t m, int32_t n,
+                                                      const int32_t *qi, const int32_t *qk,
+                                                      int32_t count, int32_t *out) {
+    for (int32_t q = blockIdx.x * kBlock + threadIdx.x; q < count; q += gridDim.x * kBlock)
+        out[q] = semilocal_query(top, m, n, qi[q], qk[q]);
+}
 __global__ void k_copy_len(const int32_t *hdr, int32_t *dst) {
     if (threadIdx.x == 0) *dst = hdr[1];
 }
@@ -235,6 +241,15 @@ hipError_t launch_trace_leaf(int32_t h0, const uint8_t *a, int32_t n, int32_t si
 
 hipError_t launch_copy_len(const int32_t *hdr, int32_t *dst, hipStream_t s) {
     hipLaunchKernelGGL(k_copy_len, dim3(1), dim3(64), 0, s, hdr, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_semilocal(const int32_t *top, int32_t m, int32_t n, const int32_t *qi,
+                            const int32_t *qk, int32_t count, int32_t *out, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    const int32_t blocks = (count + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_semilocal, dim3(blocks < 4096 ? blocks : 4096), dim3(kBlock), 0, s, top, m,
+                       n, qi, qk, count, out);
     return hipGetLastError();
 }
 

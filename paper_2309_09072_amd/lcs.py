@@ -91,6 +91,7 @@ PROTOTYPES = {
     "lcs_trace": (_I32, [_P, _P, _P, _I32, _PI32, _P]),
     "lcs_trace_device": (_I32, [_P, _P, _P, _I32, _P, _P]),
     "lcs_plan_profile": (_I32, [_P, _P, _I32, _PI32]),
+    "lcs_semilocal": (_I32, [_P, _P, _P, _I32, _P, _P]),
     "lcs_plan_levels": (_I32, [_P, _PI32, _PI32]),
     "lcs_dist_view": (_I32, [_P, _I32, _I32, ctypes.POINTER(_P), _PI32, _PI32, _PI32]),
     "lcs_batch_plan": (_I32, [ctypes.POINTER(BatchDesc), ctypes.POINTER(_P), _PSZ]),
@@ -210,6 +211,16 @@ class Plan:
         out = ctypes.c_int32()
         check(load().lcs_length(self._h, ctypes.byref(out), stream_handle(stream)), "lcs_length")
         return int(out.value)
+
+    def semilocal(self, qi, qk, out=None, stream=None):
+        """LCS(a, b[i:k]) for device int32 query tensors qi, qk (lcs_semilocal);
+        -1 for a query outside 0 <= i <= k <= n."""
+        torch = _torch()
+        if out is None:
+            out = torch.empty(int(qi.numel()), dtype=torch.int32, device=qi.device)
+        check(load().lcs_semilocal(self._h, _dptr(qi), _dptr(qk), int(qi.numel()), _dptr(out),
+                                   stream_handle(stream)), "lcs_semilocal")
+        return out
 
     def length_device(self, out, stream=None) -> None:
         check(load().lcs_length_device(self._h, _dptr(out), stream_handle(stream)), "lcs_length_device")
