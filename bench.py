@@ -245,10 +245,11 @@ def paper_sweep(steps: int, warmup: int):
             x, y = synth.uniform(g, s1, 4), synth.uniform(g, s2, 4)
             want = oracle.lcs_witness(x, y)
             entry = {"s1": s1, "s2": s2, "paper_s_32_cores": t32[c], "paper_s_8_cores": t8[c]}
-            for name, (a, b) in (("long_rows", (x, y)), ("long_cols", (y, x))):
+            for name, (a, b), orient in (("long_rows", (x, y), False), ("long_cols", (y, x), False),
+                                         ("long_rows_oriented", (x, y), True)):
                 m, n = a.size, b.size
                 ad, bd = lcs.device_bytes(a), lcs.device_bytes(b)
-                plan = lcs.Plan(m, n, 4, 64, 32)
+                plan = lcs.Plan(m, n, 4, 64, 32, orient=orient)
                 ws = lcs.alloc_workspace(plan.workspace_for(m, n))
                 cap = max(1, min(m, n))
                 ai = torch.empty(cap, dtype=torch.int32, device="cuda")
@@ -278,8 +279,10 @@ def paper_sweep(steps: int, warmup: int):
                                "speedup_vs_paper_32_cores": round(t32[c] / (us * 1e-6), 1)}
                 plan.close()
             rows.append(entry)
-            log("paper shape %dx%d: %s us (long rows), %s us (long cols); paper 32 cores %.3g s" % (
-                s1, s2, entry["long_rows"]["us_per_lcs"], entry["long_cols"]["us_per_lcs"], t32[c]))
+            log("paper shape %dx%d: %s us (long rows), %s us (long cols), %s us (long rows, oriented);"
+                " paper 32 cores %.3g s" % (s1, s2, entry["long_rows"]["us_per_lcs"],
+                                             entry["long_cols"]["us_per_lcs"],
+                                             entry["long_rows_oriented"]["us_per_lcs"], t32[c]))
     return rows
 
 

@@ -73,10 +73,19 @@ typedef struct lcs_plan_desc {
                           base_rows rows): 16, 32 or 64; 0 selects 64 */
     int32_t tile;      /* vertices per search tile of the combine: power of two
                           in 4..32; 0 selects the default (32) */
-    uint32_t flags;    /* 0 or LCS_PLAN_PROFILE */
+    uint32_t flags;    /* 0 or an OR of LCS_PLAN_PROFILE, LCS_PLAN_ORIENT */
 } lcs_plan_desc;
 
 #define LCS_PLAN_PROFILE 1u /* record HIP events around every kernel of a build/trace */
+#define LCS_PLAN_ORIENT 2u  /* when m > n, build the problem of reversed b (rows) against
+                               reversed a (columns): the recursion depth follows the
+                               shorter string (Section II-C: depth grows with log m).
+                               The length is the same, and the witness is mapped back
+                               to a's and b's indices: the canonical witness of the
+                               reversed, transposed problem is the canonical witness of
+                               (a, b) read backwards.  lcs_semilocal is then not
+                               available (LCS_E_STATE) and lcs_dist_view shows the
+                               matrices of the problem that was built. */
 
 /*
  * Plan the breakout-matrix recursion for strings up to max_m x max_n.

@@ -68,10 +68,26 @@ struct lcs_plan_s {
     Layout lay;
     bool built = false;
     bool empty = false;
+    bool transposed = false;  // an oriented build of (rev b, rev a)
+    int32_t m = 0, n = 0;     // sizes of the caller's a and b
     uint8_t *ws = nullptr;
     const uint8_t *a = nullptr;
     const uint8_t *b = nullptr;
 };
+
+// Layout of one build.  With LCS_PLAN_ORIENT and m > n the problem built is
+// (rev b, rev a): layout (n, m) plus room for the two reversed strings.
+static bool plan_layout(const lcs_plan_desc &d, int32_t m, int32_t n, Layout &L, bool *transposed) {
+    *transposed = false;
+    if ((d.flags & LCS_PLAN_ORIENT) && m > n &&
+        make_layout(n, m, d.alphabet, d.base_rows, d.tile, L)) {
+        L.off_rev = L.total;
+        L.total = align256(L.total + align256(n) + m);
+        *transposed = true;
+        return true;
+    }
+    return make_layout(m, n, d.alphabet, d.base_rows, d.tile, L);
+}
 
 extern "C" const char *lcs_status_string(int32_t s) {
     switch (s) {
@@ -202,17 +218,27 @@ extern "C" int32_t lcs_plan(const lcs_plan_desc *desc, lcs_plan_t *out, size_t *
     d.base_rows = resolve(d.base_rows, kDefaultBaseRows);
     d.tile = resolve(d.tile, kDefaultTile);
     if (d.max_m < 0 || d.max_n < 0 || d.alphabet < 1 || d.alphabet > 256 ||
-        (d.flags & ~LCS_PLAN_PROFILE) != 0)
+        (d.flags & ~(LCS_PLAN_PROFILE | LCS_PLAN_ORIENT)) != 0)
         return LCS_E_INVAL;
     if (!valid_shape(d.base_rows, d.tile)) return LCS_E_INVAL;
     if (d.max_n > 0x7ffffff0 || d.max_m > 0x7ffffff0) return LCS_E_TOO_BIG;
     Layout L;
     if (!make_layout(d.max_m, d.max_n, d.alphabet, d.base_rows, d.tile, L)) return LCS_E_TOO_BIG;
+    int64_t total = L.total;
+    if (d.flags & LCS_PLAN_ORIENT) {
+        // an oriented build of (m, n) uses layout (n, m) (at most layout
+        // (max_n, max_m): layouts grow with both sizes) plus the reversed strings
+        Layout T;
+        if (make_layout(d.max_n, d.max_m, d.alphabet, d.base_rows, d.tile, T)) {
+            const int64_t t = align256(T.total + align256(d.max_n) + d.max_m);
+            if (t > total) total = t;
+        }
+    }
     lcs_plan_s *p = new (std::nothrow) lcs_plan_s();
     if (!p) return LCS_E_NOMEM;
     p->d = d;
     p->rec.on = (d.flags & LCS_PLAN_PROFILE) != 0;
-    *workspace_bytes = (size_t)L.total;
+    *workspace_bytes = (size_t)total;
     *out = p;
     return LCS_OK;
 }
@@ -221,7 +247,8 @@ extern "C" int32_t lcs_plan_workspace(lcs_plan_t p, int32_t m, int32_t n, size_t
     if (!p || !bytes || m < 0 || n < 0) return LCS_E_INVAL;
     if (m > p->d.max_m || n > p->d.max_n) return LCS_E_TOO_BIG;
     Layout L;
-    if (!make_layout(m, n, p->d.alphabet, p->d.base_rows, p->d.tile, L)) return LCS_E_TOO_BIG;
+    bool tr = false;
+    if (!plan_layout(p->d, m, n, L, &tr)) return LCS_E_TOO_BIG;
     *bytes = (size_t)L.total;
     return LCS_OK;
 }
@@ -241,15 +268,28 @@ extern "C" int32_t lcs_dist_build(lcs_plan_t p, const uint8_t *a, int32_t m, con
     if (m > p->d.max_m || n > p->d.max_n) return LCS_E_TOO_BIG;
     if (reinterpret_cast<uintptr_t>(workspace) & 255) return LCS_E_INVAL;
     Layout L;
-    if (!make_layout(m, n, p->d.alphabet, p->d.base_rows, p->d.tile, L)) return LCS_E_TOO_BIG;
+    bool tr = false;
+    if (!plan_layout(p->d, m, n, L, &tr)) return LCS_E_TOO_BIG;
     if ((size_t)L.total > workspace_bytes) return LCS_E_WORKSPACE;
     p->lay = L;
     p->ws = static_cast<uint8_t *>(workspace);
     p->a = a;
     p->b = b;
+    p->m = m;
+    p->n = n;
+    p->transposed = tr;
     p->empty = (m == 0 || n == 0);
     p->rec.s = static_cast<hipStream_t>(stream);
-    const int32_t rc = enqueue_build(L, p->ws, a, b, static_cast<hipStream_t>(stream), &p->rec);
+    if (tr) {  // rows: reversed b; columns: reversed a
+        uint8_t *rb = p->ws + L.off_rev;
+        uint8_t *ra = rb + align256(n);
+        if (launch_reverse(b, n, rb, p->rec.s) != hipSuccess ||
+            launch_reverse(a, m, ra, p->rec.s) != hipSuccess)
+            return LCS_E_HIP;
+        p->a = rb;
+        p->b = ra;
+    }
+    const int32_t rc = enqueue_build(L, p->ws, p->a, p->b, static_cast<hipStream_t>(stream), &p->rec);
     if (rc != LCS_OK) return rc;
     p->built = true;
     return LCS_OK;
@@ -293,7 +333,7 @@ extern "C" int32_t lcs_length_device(lcs_plan_t p, int32_t *length_dev, void *st
 extern "C" int32_t lcs_semilocal(lcs_plan_t p, const int32_t *qi, const int32_t *qk, int32_t count,
                                  int32_t *out, void *stream) {
     if (!p || count < 0 || (count > 0 && (!qi || !qk || !out))) return LCS_E_INVAL;
-    if (!p->built) return LCS_E_STATE;
+    if (!p->built || p->transposed) return LCS_E_STATE;
     const int32_t *top = nullptr;
     int32_t m = 0;
     if (!p->empty) {
@@ -321,6 +361,10 @@ extern "C" int32_t lcs_trace(lcs_plan_t p, int32_t *a_idx, int32_t *b_idx, int32
     p->rec.s = s;
     const int32_t rc = enqueue_trace(p->lay, p->ws, p->a, a_idx, b_idx, s, &p->rec);
     if (rc != LCS_OK) return rc;
+    if (p->transposed &&
+        launch_unflip(reinterpret_cast<const int32_t *>(p->ws + p->lay.off_hdr), a_idx, b_idx,
+                      capacity, p->m, p->n, s) != hipSuccess)
+        return LCS_E_HIP;
     int32_t h[3];
     const int32_t rc2 = read_header(p, s, h);
     if (rc2 != LCS_OK) return rc2;
@@ -365,6 +409,10 @@ extern "C" int32_t lcs_trace_device(lcs_plan_t p, int32_t *a_idx, int32_t *b_idx
         p->rec.s = s;
         const int32_t rc = enqueue_trace(p->lay, p->ws, p->a, a_idx, b_idx, s, &p->rec);
         if (rc != LCS_OK) return rc;
+        if (p->transposed &&
+            launch_unflip(reinterpret_cast<const int32_t *>(p->ws + p->lay.off_hdr), a_idx, b_idx,
+                          capacity, p->m, p->n, s) != hipSuccess)
+            return LCS_E_HIP;
     }
     return launch_copy_len(reinterpret_cast<const int32_t *>(p->ws + p->lay.off_hdr), length_dev, s) ==
                    hipSuccess

@@ -121,6 +121,25 @@ __global__ void __launch_bounds__(kBlock) k_semilocal(const int32_t *top, int32_
     for (int32_t q = blockIdx.x * kBlock + threadIdx.x; q < count; q += gridDim.x * kBlock)
         out[q] = semilocal_query(top, m, n, qi[q], qk[q]);
 }
+__global__ void __launch_bounds__(kBlock) k_reverse(const uint8_t *src, int32_t len, uint8_t *dst) {
+    for (int32_t t = blockIdx.x * kBlock + threadIdx.x; t < len; t += gridDim.x * kBlock)
+        dst[t] = src[len - 1 - t];
+}
+// Witness of the built problem (rows: reversed b, columns: reversed a), read
+// backwards and mapped to indices of a and b.  Thread t swaps entries t and
+// L - 1 - t.  L comes from the header (device), clamped to the capacity.
+__global__ void __launch_bounds__(kBlock) k_unflip(const int32_t *hdr, int32_t *a_idx, int32_t *b_idx,
+                                                   int32_t capacity, int32_t m, int32_t n) {
+    const int32_t L = imin(imax(hdr[1], 0), capacity);
+    for (int32_t t = blockIdx.x * kBlock + threadIdx.x; 2 * t < L; t += gridDim.x * kBlock) {
+        const int32_t u = L - 1 - t;
+        const int32_t rt = a_idx[t], ct = b_idx[t], ru = a_idx[u], cu = b_idx[u];
+        a_idx[t] = m - 1 - cu;
+        b_idx[t] = n - 1 - ru;
+        a_idx[u] = m - 1 - ct;
+        b_idx[u] = n - 1 - rt;
+    }
+}
 __global__ void k_copy_len(const int32_t *hdr, int32_t *dst) {
     if (threadIdx.x == 0) *dst = hdr[1];
 }
@@ -250,6 +269,23 @@ hipError_t launch_semilocal(const int32_t *top, int32_t m, int32_t n, const int3
     const int32_t blocks = (count + kBlock - 1) / kBlock;
     hipLaunchKernelGGL(k_semilocal, dim3(blocks < 4096 ? blocks : 4096), dim3(kBlock), 0, s, top, m,
                        n, qi, qk, count, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_reverse(const uint8_t *src, int32_t len, uint8_t *dst, hipStream_t s) {
+    if (len <= 0) return hipSuccess;
+    const int32_t blocks = (len + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_reverse, dim3(blocks < 4096 ? blocks : 4096), dim3(kBlock), 0, s, src, len,
+                       dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_unflip(const int32_t *hdr, int32_t *a_idx, int32_t *b_idx, int32_t capacity,
+                         int32_t m, int32_t n, hipStream_t s) {
+    const int32_t half = (imin(m, n) + 1) / 2;
+    const int32_t blocks = imax(1, (half + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(k_unflip, dim3(blocks < 4096 ? blocks : 4096), dim3(kBlock), 0, s, hdr, a_idx,
+                       b_idx, capacity, m, n);
     return hipGetLastError();
 }
 

@@ -21,6 +21,7 @@ struct Layout {
     std::vector<int64_t> node_off;   // per level: trace nodes (int4 per strip)
     std::vector<int64_t> anch_off;   // per level: anchor argmin rows of its combines
     int64_t off_hdr = 0, off_nm = 0, total = 0;
+    int64_t off_rev = -1;  // reversed strings of an oriented build (rows, then columns)
     int32_t nanch = 0;
 };
 

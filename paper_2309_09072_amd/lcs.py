@@ -62,6 +62,7 @@ class PhaseTime(ctypes.Structure):
 PHASES = {0: "nextmatch", 1: "base", 2: "anchor", 3: "bracket", 4: "length", 5: "trace_split",
           6: "trace_leaf"}
 PLAN_PROFILE = 1
+PLAN_ORIENT = 2
 
 
 class Result(ctypes.Structure):
@@ -184,10 +185,10 @@ class Plan:
     """One planned strip recursion (lcs_plan); reusable for any m <= max_m, n <= max_n."""
 
     def __init__(self, max_m: int, max_n: int, alphabet: int, base_rows: int = 0, tile: int = 0,
-                 profile: bool = False):
+                 profile: bool = False, orient: bool = False):
         lib = load()
         self.desc = PlanDesc(int(max_m), int(max_n), int(alphabet), int(base_rows), int(tile),
-                             PLAN_PROFILE if profile else 0)
+                             (PLAN_PROFILE if profile else 0) | (PLAN_ORIENT if orient else 0))
         h = ctypes.c_void_p()
         ws = ctypes.c_size_t()
         check(lib.lcs_plan(ctypes.byref(self.desc), ctypes.byref(h), ctypes.byref(ws)), "lcs_plan")
@@ -281,12 +282,12 @@ class Plan:
 
 
 def lcs(a, b, alphabet: int, base_rows: int = 0, tile: int = 0, witness: bool = True,
-        device="cuda", stream=None):
+        device="cuda", stream=None, orient: bool = False):
     """LCS of two symbol strings on the GPU: (L, a_idx, b_idx) as numpy arrays."""
     torch = _torch()
     ad, bd = device_bytes(a, device), device_bytes(b, device)
     m, n = int(ad.numel()), int(bd.numel())
-    plan = Plan(m, n, alphabet, base_rows, tile)
+    plan = Plan(m, n, alphabet, base_rows, tile, orient=orient)
     try:
         ws = alloc_workspace(plan.workspace_for(m, n), device)
         plan.build(ad, bd, ws, stream)

@@ -87,3 +87,20 @@ def test_calls_validate_before_device_work():
     # null plan / null outputs
     assert lib.lcs_length(null, ctypes.byref(out), null) == -1
     assert lib.lcs_plan_workspace(null, 1, 1, None) == -1
+
+
+def test_orient_flag_and_workspace_bound():
+    from paper_2309_09072_amd import lcs
+    p = lcs.Plan(1000, 300, 4, 16, 8, orient=True)
+    for m, n in [(1000, 300), (1000, 1), (301, 300), (300, 300), (5, 300), (0, 0), (1000, 0)]:
+        assert p.workspace_for(m, n) <= p.workspace_bytes, (m, n)
+    # oriented: layout of the transposed problem (fewer levels when m > n)
+    q = lcs.Plan(1000, 300, 4, 16, 8)
+    assert p.workspace_for(1000, 300) < q.workspace_for(1000, 300)
+    assert p.workspace_for(200, 300) == q.workspace_for(200, 300)
+    p.close()
+    q.close()
+    desc = lcs.PlanDesc(10, 10, 4, 16, 8, 4)   # unknown flag bit
+    import ctypes
+    h, ws = ctypes.c_void_p(), ctypes.c_size_t()
+    assert lcs.load().lcs_plan(ctypes.byref(desc), ctypes.byref(h), ctypes.byref(ws)) == -1
