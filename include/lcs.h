@@ -176,6 +176,23 @@ int32_t lcs_semilocal(lcs_plan_t plan, const int32_t *qi, const int32_t *qk, int
                       int32_t *out, void *stream);
 
 /*
+ * Every vertex of the canonical path, row by row (Section II-E, the vertices
+ * between two cross-vertices of a row): the path enters grid row r (the row
+ * between the first r and r+1 symbols of a, r = 0..m) at column col_in[r] and
+ * leaves it at col_out[r] >= col_in[r]; it then goes down (col_out[r] ==
+ * col_in[r + 1]) or along the match a[r] = b[col_out[r]] (col_in[r + 1] =
+ * col_out[r] + 1).  The path is the leftmost one, whose matches are the
+ * canonical witness: it comes down as early as it can and runs right along the
+ * row of its next match (col_out[m] = n).
+ *   a_idx, b_idx, length_dev: the device witness of lcs_trace_device for the
+ *   last build (pairs sorted, *length_dev of them); col_in, col_out: device
+ *   int32[m + 1] each.  Asynchronous, graph-safe.
+ * Errors: LCS_E_INVAL (null pointer), LCS_E_STATE (no build), LCS_E_HIP.
+ */
+int32_t lcs_path(lcs_plan_t plan, const int32_t *a_idx, const int32_t *b_idx,
+                 const int32_t *length_dev, int32_t *col_in, int32_t *col_out, void *stream);
+
+/*
  * Per-kernel timing of a plan made with LCS_PLAN_PROFILE: one record per
  * launch of every build and trace since the records were last read, in launch
  * order, measured with HIP events recorded on the caller's stream right

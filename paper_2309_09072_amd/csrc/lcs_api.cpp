@@ -346,6 +346,19 @@ extern "C" int32_t lcs_semilocal(lcs_plan_t p, const int32_t *qi, const int32_t 
                : LCS_E_HIP;
 }
 
+extern "C" int32_t lcs_path(lcs_plan_t p, const int32_t *a_idx, const int32_t *b_idx,
+                            const int32_t *length_dev, int32_t *col_in, int32_t *col_out,
+                            void *stream) {
+    if (!p || !length_dev || !col_in || !col_out) return LCS_E_INVAL;
+    if (!p->built) return LCS_E_STATE;
+    const int32_t cap = p->m < p->n ? p->m : p->n;
+    if (cap > 0 && (!a_idx || !b_idx)) return LCS_E_INVAL;
+    return launch_path(a_idx, b_idx, length_dev, cap, p->m, p->n, col_in, col_out,
+                       static_cast<hipStream_t>(stream)) == hipSuccess
+               ? LCS_OK
+               : LCS_E_HIP;
+}
+
 extern "C" int32_t lcs_trace(lcs_plan_t p, int32_t *a_idx, int32_t *b_idx, int32_t capacity,
                              int32_t *length_host, void *stream) {
     if (!p || !length_host) return LCS_E_INVAL;

@@ -827,6 +827,30 @@ __device__ __forceinline__ int32_t semilocal_query(const int32_t *__restrict__ t
 }
 
 // ---------------------------------------------------------------------------
+// Path listing of grid row r from the canonical witness (a_idx sorted, L
+// pairs): t = matches above row r (binary search); the path enters at the
+// column after the previous match and leaves at the column of row r's own
+// match, or where it entered (a vertical step), or at n on the last row.
+__device__ __forceinline__ void path_row(const int32_t *__restrict__ a_idx,
+                                         const int32_t *__restrict__ b_idx, int32_t L, int32_t m,
+                                         int32_t n, int32_t r, int32_t *cin, int32_t *cout) {
+    int32_t lo = 0, hi = L;  // first t with a_idx[t] >= r
+    while (lo < hi) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (a_idx[mid] < r)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    const int32_t c0 = lo > 0 ? imin(imax(b_idx[lo - 1] + 1, 0), n) : 0;
+    int32_t c1 = c0;
+    if (lo < L && a_idx[lo] == r) c1 = imin(imax(b_idx[lo], c0), n);
+    if (r == m) c1 = n;
+    *cin = c0;
+    *cout = c1;
+}
+
+// ---------------------------------------------------------------------------
 // Midpoint trace, one split (Section II-D).  Node (source s, weight w, end e)
 // of G = U (+) L, with e = D_G(s, w).  The cross vertex on the boundary row is
 // x = D_U(s, k*) for the SMALLEST k with D_L(D_U(s, k), w - k) == e (Alg. 2's

@@ -140,6 +140,13 @@ __global__ void __launch_bounds__(kBlock) k_unflip(const int32_t *hdr, int32_t *
         b_idx[u] = n - 1 - rt;
     }
 }
+__global__ void __launch_bounds__(kBlock) k_path(const int32_t *a_idx, const int32_t *b_idx,
+                                                 const int32_t *length, int32_t cap, int32_t m,
+                                                 int32_t n, int32_t *col_in, int32_t *col_out) {
+    const int32_t L = imin(imax(*length, 0), cap);
+    for (int32_t r = blockIdx.x * kBlock + threadIdx.x; r <= m; r += gridDim.x * kBlock)
+        path_row(a_idx, b_idx, L, m, n, r, col_in + r, col_out + r);
+}
 __global__ void k_copy_len(const int32_t *hdr, int32_t *dst) {
     if (threadIdx.x == 0) *dst = hdr[1];
 }
@@ -286,6 +293,15 @@ hipError_t launch_unflip(const int32_t *hdr, int32_t *a_idx, int32_t *b_idx, int
     const int32_t blocks = imax(1, (half + kBlock - 1) / kBlock);
     hipLaunchKernelGGL(k_unflip, dim3(blocks < 4096 ? blocks : 4096), dim3(kBlock), 0, s, hdr, a_idx,
                        b_idx, capacity, m, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_path(const int32_t *a_idx, const int32_t *b_idx, const int32_t *length,
+                       int32_t cap, int32_t m, int32_t n, int32_t *col_in, int32_t *col_out,
+                       hipStream_t s) {
+    const int32_t blocks = (m + 1 + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_path, dim3(blocks < 4096 ? blocks : 4096), dim3(kBlock), 0, s, a_idx, b_idx,
+                       length, cap, m, n, col_in, col_out);
     return hipGetLastError();
 }
 

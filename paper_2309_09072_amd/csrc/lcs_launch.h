@@ -23,6 +23,9 @@ hipError_t launch_trace_leaf(int32_t h0, const uint8_t *a, int32_t n, int32_t si
                              int32_t *a_idx, int32_t *b_idx, int32_t wcap, int32_t *err,
                              hipStream_t s);
 hipError_t launch_copy_len(const int32_t *hdr, int32_t *dst, hipStream_t s);
+hipError_t launch_path(const int32_t *a_idx, const int32_t *b_idx, const int32_t *length,
+                       int32_t cap, int32_t m, int32_t n, int32_t *col_in, int32_t *col_out,
+                       hipStream_t s);
 hipError_t launch_reverse(const uint8_t *src, int32_t len, uint8_t *dst, hipStream_t s);
 hipError_t launch_unflip(const int32_t *hdr, int32_t *a_idx, int32_t *b_idx, int32_t capacity,
                          int32_t m, int32_t n, hipStream_t s);

@@ -93,6 +93,7 @@ PROTOTYPES = {
     "lcs_trace_device": (_I32, [_P, _P, _P, _I32, _P, _P]),
     "lcs_plan_profile": (_I32, [_P, _P, _I32, _PI32]),
     "lcs_semilocal": (_I32, [_P, _P, _P, _I32, _P, _P]),
+    "lcs_path": (_I32, [_P, _P, _P, _P, _P, _P, _P]),
     "lcs_plan_levels": (_I32, [_P, _PI32, _PI32]),
     "lcs_dist_view": (_I32, [_P, _I32, _I32, ctypes.POINTER(_P), _PI32, _PI32, _PI32]),
     "lcs_batch_plan": (_I32, [ctypes.POINTER(BatchDesc), ctypes.POINTER(_P), _PSZ]),
@@ -212,6 +213,17 @@ class Plan:
         out = ctypes.c_int32()
         check(load().lcs_length(self._h, ctypes.byref(out), stream_handle(stream)), "lcs_length")
         return int(out.value)
+
+    def path(self, a_idx, b_idx, length_dev, m: int, stream=None):
+        """(col_in, col_out) device int32[m + 1]: the canonical path row by row
+        (lcs_path) from a device witness of trace_device."""
+        torch = _torch()
+        dev = length_dev.device
+        cin = torch.empty(m + 1, dtype=torch.int32, device=dev)
+        cout = torch.empty(m + 1, dtype=torch.int32, device=dev)
+        check(load().lcs_path(self._h, _dptr(a_idx), _dptr(b_idx), _dptr(length_dev), _dptr(cin),
+                              _dptr(cout), stream_handle(stream)), "lcs_path")
+        return cin, cout
 
     def semilocal(self, qi, qk, out=None, stream=None):
         """LCS(a, b[i:k]) for device int32 query tensors qi, qk (lcs_semilocal);
