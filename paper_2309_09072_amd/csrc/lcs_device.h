@@ -20,7 +20,6 @@ constexpr int kWaves = kBlock / kWave;
 constexpr int kJChunk = 32;  // weights per bracket block (a block may take kJChunk + 1)
 constexpr int kBatch = 8;    // candidates whose loads are issued together
 constexpr int kMaxTile = 32;
-constexpr int kBracketItems = 2;  // outputs per thread and bisection level, loads interleaved
 
 __host__ __device__ __forceinline__ int32_t imin(int32_t a, int32_t b) { return a < b ? a : b; }
 __host__ __device__ __forceinline__ int32_t imax(int32_t a, int32_t b) { return a > b ? a : b; }
@@ -384,30 +383,61 @@ __device__ __forceinline__ void anchor_block(const int32_t *__restrict__ U, int3
 // D_U in LDS: by the window above (applied level by level, and with k*
 // non-decreasing in j) every candidate of vertex i0 + v lies in
 // [k*(i0, j0) - v, k*(i1, jl) + (len - v)], jl the last weight that is
-// reachable from i0.  When that parallelogram is at most kUWin wide and
+// reachable from i0.  When that parallelogram is at most kUW wide and
 // k*(i1, jl) exists, the block first copies it from D_U into LDS and the
 // bisection reads D_U only from there: one HBM round trip per level (the D_L
 // gathers) instead of two.  Otherwise D_U is read from global memory.
 // A block none of whose weights is reachable from i0 writes unreachable
 // everywhere (reachability is monotone in the vertex).
-// Latency: within a bisection level each thread owns up to kBracketItems
+// Latency: within a bisection level each thread owns up to 2
 // outputs and issues the loads of all of them before it waits, and every
 // output first runs exactly one batch of candidates; the few that are not
 // finished are queued in LDS and completed by all threads together, so a wave
 // never waits for its slowest lane during the common case.
 // The last weight of a strip, j = hU + hL, has the single candidate k = hU; a
-// block that holds it (jn = kJChunk + 1) evaluates it directly, so the
-// bisection works on at most kJChunk weights.
-constexpr int kUWin = 64;
+// block that holds it (jn = kJ + 1) evaluates it directly, so the
+// bisection works on at most kJ weights.
 constexpr int kCoarseItems = kBlock / 2;  // a level with at most this many outputs is coarse
-struct BracketSmem {
-    int32_t k[(kMaxTile + 1) * kJChunk];
-    int32_t v[(kMaxTile + 1) * kJChunk];
-    int32_t u[(kMaxTile + 1) * kUWin];    // D_U parallelogram (row v starts at k*(i0, j0) - v)
-    int32_t q[(kMaxTile / 2) * kJChunk];  // queued outputs of one level (slot * kJChunk + jj)
-    unsigned long long key[kCoarseItems];  // slice minima (value, k) of a coarse level
-    int32_t qn[2];                        // queue lengths, alternating between levels
+// Shape of a bracket work-group: LDS state type, weights per block, width of
+// the D_U parallelogram.  32-bit state: any size.  16-bit state (values and
+// indices stored in 16 bits, k* stored as k* + 1 so that -1 is 0): needs
+// n + 1 <= 65535 and strip heights <= 65534, and holds twice the weights in
+// about the same LDS, which halves the per-work-group overhead per output.
+template <typename T, int J, int UW>
+struct BracketCfg {
+    using St = T;
+    static constexpr int kJ = J;
+    static constexpr int kUW = UW;
 };
+using BracketCfg32 = BracketCfg<int32_t, 32, 64>;
+using BracketCfg16 = BracketCfg<uint16_t, 64, 96>;
+
+template <class C>
+struct BracketSmemT {
+    using St = typename C::St;
+    St k[(kMaxTile + 1) * C::kJ];
+    St v[(kMaxTile + 1) * C::kJ];
+    St u[(kMaxTile + 1) * C::kUW];  // D_U parallelogram (row v starts at k*(i0, j0) - v)
+    St q[(kMaxTile / 2) * C::kJ];   // queued outputs of one level (slot * kJ + jj)
+    unsigned long long key[kCoarseItems];  // slice minima (value, k) of a coarse level
+    int32_t qn[2];                         // queue lengths, alternating between levels
+};
+using BracketSmem = BracketSmemT<BracketCfg32>;
+
+template <class C>
+__device__ __forceinline__ int32_t ldk(const BracketSmemT<C> &sm, int32_t i) {
+    if constexpr (sizeof(typename C::St) == 2)
+        return (int32_t)sm.k[i] - 1;
+    else
+        return sm.k[i];
+}
+template <class C>
+__device__ __forceinline__ void stk(BracketSmemT<C> &sm, int32_t i, int32_t k) {
+    if constexpr (sizeof(typename C::St) == 2)
+        sm.k[i] = (uint16_t)(k + 1);
+    else
+        sm.k[i] = k;
+}
 
 struct BracketWindow {
     int32_t lo, hi, xb, vlo, vhi;
@@ -417,77 +447,80 @@ struct BracketWindow {
 // D_U(i0 + v, k) of a tile vertex: from the LDS parallelogram (kLds; the
 // index is clamped into the row, so any k reads inside it) or from global
 // memory.
-template <bool kLds>
-__device__ __forceinline__ int32_t bracket_u(const BracketSmem &sm, const int32_t *__restrict__ U,
+template <class C, bool kLds>
+__device__ __forceinline__ int32_t bracket_u(const BracketSmemT<C> &sm, const int32_t *__restrict__ U,
                                              int32_t ldU, int32_t hU, int32_t i0, int32_t ubase,
                                              int32_t v, int32_t k, int32_t n) {
-    if (kLds) return sm.u[v * kUWin + imin(imax(k - ubase + v, 0), kUWin - 1)];
+    if (kLds) return (int32_t)sm.u[v * C::kUW + imin(imax(k - ubase + v, 0), C::kUW - 1)];
     return umin(ld_cell(U, (uint32_t)(i0 + v) * (uint32_t)ldU + (uint32_t)imin(imax(k, 0), hU)),
                 n + 1);
 }
 
 // Search window of output (v, j) from the solved vertices va < v < vb; the
 // crossing bound x*(vb, j) = D_U(i0 + vb, k*(vb, j)) is looked up from k*.
-template <bool kLds>
-__device__ __forceinline__ BracketWindow bracket_window(const BracketSmem &sm,
+template <class C, bool kLds>
+__device__ __forceinline__ BracketWindow bracket_window(const BracketSmemT<C> &sm,
                                                         const int32_t *__restrict__ U, int32_t ldU,
                                                         int32_t i0, int32_t ubase, int32_t v,
                                                         int32_t va, int32_t vb, int32_t jj,
                                                         int32_t j, int32_t hU, int32_t hL,
                                                         int32_t n) {
-    constexpr int32_t S = kJChunk;
+    constexpr int32_t S = C::kJ;
     BracketWindow w;
-    const int32_t ka = sm.k[va * S + jj];
-    const int32_t kb = sm.k[vb * S + jj];
+    const int32_t ka = ldk(sm, va * S + jj);
+    const int32_t kb = ldk(sm, vb * S + jj);
     w.dead = ka < 0;
     w.hi = imin(j, hU);
     w.xb = n;
     if (kb >= 0) {
         w.hi = imin(kb + (vb - v), w.hi);
-        w.xb = bracket_u<kLds>(sm, U, ldU, hU, i0, ubase, vb, kb, n);
+        w.xb = bracket_u<C, kLds>(sm, U, ldU, hU, i0, ubase, vb, kb, n);
     }
     w.lo = imax(ka - (v - va), imax(j - hL, 0));
-    w.vlo = sm.v[va * S + jj];
-    w.vhi = sm.v[vb * S + jj];
+    w.vlo = (int32_t)sm.v[va * S + jj];
+    w.vhi = (int32_t)sm.v[vb * S + jj];
     return w;
 }
 
 // Final result of one output: LDS state for the finer levels and D_G.
-__device__ __forceinline__ void bracket_store(BracketSmem &sm, int32_t id, int32_t *__restrict__ g,
-                                              int32_t n, int32_t best, int32_t bk) {
+template <class C>
+__device__ __forceinline__ void bracket_store(BracketSmemT<C> &sm, int32_t id,
+                                              int32_t *__restrict__ g, int32_t n, int32_t best,
+                                              int32_t bk) {
     if (best > n) {
         best = n + 1;
         bk = -1;
     }
-    sm.k[id] = bk;
-    sm.v[id] = best;
+    stk(sm, id, bk);
+    sm.v[id] = (typename C::St)best;
     *g = best;
 }
 
 // D_U loads of one batch of tile vertex v (LDS parallelogram or global).
-template <int B, bool kLds>
-__device__ __forceinline__ void bracket_load_u(const BracketSmem &sm, const int32_t *__restrict__ U,
+template <class C, int B, bool kLds>
+__device__ __forceinline__ void bracket_load_u(const BracketSmemT<C> &sm, const int32_t *__restrict__ U,
                                                int32_t ldU, int32_t hU, int32_t i0, int32_t ubase,
                                                int32_t v, int32_t k0, int32_t hi, int32_t n,
                                                int32_t (&xs)[B]) {
 #pragma unroll
-    for (int t = 0; t < B; ++t) xs[t] = bracket_u<kLds>(sm, U, ldU, hU, i0, ubase, v, imin(k0 + t, hi), n);
+    for (int t = 0; t < B; ++t)
+        xs[t] = bracket_u<C, kLds>(sm, U, ldU, hU, i0, ubase, v, imin(k0 + t, hi), n);
 }
 
 // Pass 1 of one bisection level with R outputs per thread: every output runs
 // one batch of candidates.  The loads carry no branches (an idle output reads
 // vertex i0, weight 0, which is in bounds) so that the loads of all R outputs
 // are in flight together.  Unfinished outputs are queued for pass 2.
-template <int R, int B, bool kLds>
-__device__ __forceinline__ void bracket_pass1(BracketSmem &sm, const int32_t *__restrict__ U,
+template <class C, int R, int B, bool kLds>
+__device__ __forceinline__ void bracket_pass1(BracketSmemT<C> &sm, const int32_t *__restrict__ U,
                                               int32_t hU, const int32_t *__restrict__ L,
                                               int32_t hL, int32_t *__restrict__ G, int32_t n,
                                               int32_t i0, int32_t len, int32_t j0, int32_t js,
                                               int32_t half, int32_t st, int32_t nitems,
-                                              int32_t par, int32_t ubase) {
-    constexpr int32_t S = kJChunk;
+                                              int32_t par, int32_t ubase, int32_t ebase) {
+    constexpr int32_t S = C::kJ;
     // a wave without outputs at this level skips it (no barrier inside)
-    if ((int32_t)(threadIdx.x & ~(kWave - 1)) >= nitems) return;
+    if (ebase + (int32_t)(threadIdx.x & ~(kWave - 1)) >= nitems) return;
     const int32_t INF = n + 1;
     const int32_t H = hU + hL + 1;
     const int32_t ldU = hU + 1, ldL = hL + 1;
@@ -498,7 +531,7 @@ __device__ __forceinline__ void bracket_pass1(BracketSmem &sm, const int32_t *__
     bool act[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        const int32_t e = (int32_t)threadIdx.x + r * kBlock;
+        const int32_t e = ebase + (int32_t)threadIdx.x + r * kBlock;
         const int32_t t = e / S, jj = e - t * S;
         const int32_t v = half + t * st;
         id[r] = v * S + jj;
@@ -511,7 +544,7 @@ __device__ __forceinline__ void bracket_pass1(BracketSmem &sm, const int32_t *__
         act[r] = false;
         if ((e < nitems) && (jj < js)) {
             const int32_t j = j0 + jj;
-            const BracketWindow w = bracket_window<kLds>(sm, U, ldU, i0, ubase, v, v - half,
+            const BracketWindow w = bracket_window<C, kLds>(sm, U, ldU, i0, ubase, v, v - half,
                                                          imin(v + half, len), jj, j, hU, hL, n);
             if (w.dead || w.lo > w.hi) {
                 bracket_store(sm, id[r], G + (size_t)(i0 + v) * H + j, n, INF, -1);
@@ -532,7 +565,7 @@ __device__ __forceinline__ void bracket_pass1(BracketSmem &sm, const int32_t *__
     int32_t xs[R][B], vs[R][B];
 #pragma unroll
     for (int r = 0; r < R; ++r)
-        bracket_load_u<B, kLds>(sm, U, ldU, hU, i0, ubase, vr[r], lo[r], hi[r], n, xs[r]);
+        bracket_load_u<C, B, kLds>(sm, U, ldU, hU, i0, ubase, vr[r], lo[r], hi[r], n, xs[r]);
 #pragma unroll
     for (int r = 0; r < R; ++r)
         batch_load_l<true, B>(L, ldL, jv[r], lo[r], 1, hi[r], xs[r], vs[r]);
@@ -553,8 +586,8 @@ __device__ __forceinline__ void bracket_pass1(BracketSmem &sm, const int32_t *__
             if (done) {
                 bracket_store(sm, id[r], G + (size_t)(i0 + vr[r]) * H + jv[r], n, best, bk);
             } else {  // provisional state; pass 2 resumes at lo + B
-                sm.k[id[r]] = bk;
-                sm.v[id[r]] = best;
+                stk(sm, id[r], bk);
+                sm.v[id[r]] = (typename C::St)imin(best, n + 1);
                 queued = true;
             }
         }
@@ -567,7 +600,7 @@ __device__ __forceinline__ void bracket_pass1(BracketSmem &sm, const int32_t *__
             qbase = __shfl(qbase, leader, kWave);
             if (queued) {
                 const unsigned long long below = mask & ((1ull << lane) - 1ull);
-                sm.q[qbase + __popcll(below)] = id[r];
+                sm.q[qbase + __popcll(below)] = (typename C::St)id[r];
             }
         }
     }
@@ -579,14 +612,14 @@ __device__ __forceinline__ void bracket_pass1(BracketSmem &sm, const int32_t *__
 // round trip.  Slice minima meet through a 64-bit LDS atomic min of
 // (value, k), which keeps the smallest minimising k.  The stop tests then run
 // on the whole range; an unfinished output resumes in pass 2 after it.
-template <bool kLds>
-__device__ __forceinline__ void bracket_coarse(BracketSmem &sm, const int32_t *__restrict__ U,
+template <class C, bool kLds>
+__device__ __forceinline__ void bracket_coarse(BracketSmemT<C> &sm, const int32_t *__restrict__ U,
                                                int32_t hU, const int32_t *__restrict__ L,
                                                int32_t hL, int32_t *__restrict__ G, int32_t n,
                                                int32_t i0, int32_t len, int32_t j0, int32_t js,
                                                int32_t half, int32_t st, int32_t nitems,
                                                int32_t par, int32_t ubase, int32_t g) {
-    constexpr int32_t S = kJChunk;
+    constexpr int32_t S = C::kJ;
     const int32_t INF = n + 1;
     const int32_t H = hU + hL + 1;
     const int32_t ldU = hU + 1, ldL = hL + 1;
@@ -596,12 +629,12 @@ __device__ __forceinline__ void bracket_coarse(BracketSmem &sm, const int32_t *_
         const int32_t t = e / S, jj = e - t * S;
         if (e < nitems && jj < js) {
             const int32_t v = half + t * st, j = j0 + jj;
-            const BracketWindow w = bracket_window<kLds>(sm, U, ldU, i0, ubase, v, v - half,
+            const BracketWindow w = bracket_window<C, kLds>(sm, U, ldU, i0, ubase, v, v - half,
                                                          imin(v + half, len), jj, j, hU, hL, n);
             const int32_t k0 = w.lo + sub * kBatch;
             if (!w.dead && k0 <= w.hi) {
                 int32_t xs[kBatch], vs[kBatch];
-                bracket_load_u<kBatch, kLds>(sm, U, ldU, hU, i0, ubase, v, k0, w.hi, n, xs);
+                bracket_load_u<C, kBatch, kLds>(sm, U, ldU, hU, i0, ubase, v, k0, w.hi, n, xs);
                 batch_load_l<false>(L, ldL, j, k0, 1, w.hi, xs, vs);
                 int32_t best = n + 2, bk = -1;
                 batch_reduce(j, k0, 1, w.hi, w.xb, w.vlo, n, xs, vs, best, bk);
@@ -619,7 +652,7 @@ __device__ __forceinline__ void bracket_coarse(BracketSmem &sm, const int32_t *_
     if (e < nitems && jj < js) {
         const int32_t v = half + t * st, j = j0 + jj;
         const int32_t id = v * S + jj;
-        const BracketWindow w = bracket_window<kLds>(sm, U, ldU, i0, ubase, v, v - half,
+        const BracketWindow w = bracket_window<C, kLds>(sm, U, ldU, i0, ubase, v, v - half,
                                                      imin(v + half, len), jj, j, hU, hL, n);
         const unsigned long long key = sm.key[e];
         sm.key[e] = ~0ull;  // ready for the next coarse level
@@ -633,14 +666,14 @@ __device__ __forceinline__ void bracket_coarse(BracketSmem &sm, const int32_t *_
                 bk = (int32_t)(uint32_t)(key & 0xffffffffull);
             }
             const int32_t kend = w.lo + g * kBatch - 1;
-            const int32_t xl = bracket_u<kLds>(sm, U, ldU, hU, i0, ubase, v, imin(kend, w.hi), n);
+            const int32_t xl = bracket_u<C, kLds>(sm, U, ldU, hU, i0, ubase, v, imin(kend, w.hi), n);
             const bool done = (kend >= w.hi) | (xl > w.xb) | (best == w.vlo) |
                               ((best <= n) & (xl - kend >= best - j));
             if (done) {
                 bracket_store(sm, id, g_out, n, best, bk);
             } else {  // provisional state; pass 2 resumes at lo + g * kBatch
-                sm.k[id] = bk;
-                sm.v[id] = best;
+                stk(sm, id, bk);
+                sm.v[id] = (typename C::St)imin(best, n + 1);
                 queued = true;
                 qid = id;
             }
@@ -654,18 +687,18 @@ __device__ __forceinline__ void bracket_coarse(BracketSmem &sm, const int32_t *_
         qbase = __shfl(qbase, leader, kWave);
         if (queued) {
             const unsigned long long below = mask & ((1ull << lane) - 1ull);
-            sm.q[qbase + __popcll(below)] = qid;
+            sm.q[qbase + __popcll(below)] = (typename C::St)qid;
         }
     }
 }
 
-template <bool kLds>
-__device__ __forceinline__ void bracket_levels(BracketSmem &sm, const int32_t *__restrict__ U,
+template <class C, bool kLds>
+__device__ __forceinline__ void bracket_levels(BracketSmemT<C> &sm, const int32_t *__restrict__ U,
                                                int32_t hU, const int32_t *__restrict__ L,
                                                int32_t hL, int32_t *__restrict__ G, int32_t n,
                                                int32_t i0, int32_t len, int32_t j0, int32_t js,
                                                int32_t ubase) {
-    constexpr int32_t S = kJChunk;
+    constexpr int32_t S = C::kJ;
     const int32_t H = hU + hL + 1;
     const int32_t ldU = hU + 1, ldL = hL + 1;
     int32_t P2 = 1;
@@ -683,31 +716,34 @@ __device__ __forceinline__ void bracket_levels(BracketSmem &sm, const int32_t *_
             int32_t g = 2;
             while (2 * g * nitems <= kBlock) g <<= 1;
             b1 = g * kBatch;
-            bracket_coarse<kLds>(sm, U, hU, L, hL, G, n, i0, len, j0, js, half, st, nitems, par,
-                                 ubase, g);
+            bracket_coarse<C, kLds>(sm, U, hU, L, hL, G, n, i0, len, j0, js, half, st, nitems,
+                                    par, ubase, g);
         } else if (nitems > kBlock) {
+            // two outputs per thread in flight together; a level of more than
+            // 2 * kBlock outputs takes two such rounds
             b1 = 4;
-            bracket_pass1<kBracketItems, 4, kLds>(sm, U, hU, L, hL, G, n, i0, len, j0, js, half,
-                                                  st, nitems, par, ubase);
+            for (int32_t eb = 0; eb < nitems; eb += 2 * kBlock)
+                bracket_pass1<C, 2, 4, kLds>(sm, U, hU, L, hL, G, n, i0, len, j0, js, half, st,
+                                             nitems, par, ubase, eb);
         } else {
             b1 = 4;
-            bracket_pass1<1, 4, kLds>(sm, U, hU, L, hL, G, n, i0, len, j0, js, half, st, nitems,
-                                      par, ubase);
+            bracket_pass1<C, 1, 4, kLds>(sm, U, hU, L, hL, G, n, i0, len, j0, js, half, st, nitems,
+                                         par, ubase, 0);
         }
         __syncthreads();
         // pass 2: the queued outputs, one per thread
         const int32_t qn = sm.qn[par];
         if (qn > 0) {
             for (int32_t e = threadIdx.x; e < qn; e += kBlock) {
-                const int32_t idq = sm.q[e];
+                const int32_t idq = (int32_t)sm.q[e];
                 const int32_t v = idq / S, jj = idq - v * S;
                 const int32_t j = j0 + jj;
-                const BracketWindow wq = bracket_window<kLds>(sm, U, ldU, i0, ubase, v, v - half,
+                const BracketWindow wq = bracket_window<C, kLds>(sm, U, ldU, i0, ubase, v, v - half,
                                                               imin(v + half, len), jj, j, hU, hL, n);
-                int32_t best = sm.v[idq], bk = sm.k[idq];
+                int32_t best = (int32_t)sm.v[idq], bk = ldk(sm, idq);
                 for (int32_t k0 = wq.lo + b1;; k0 += kBatch) {
                     int32_t xs[kBatch], vs[kBatch];
-                    bracket_load_u<kBatch, kLds>(sm, U, ldU, hU, i0, ubase, v, k0, wq.hi, n, xs);
+                    bracket_load_u<C, kBatch, kLds>(sm, U, ldU, hU, i0, ubase, v, k0, wq.hi, n, xs);
                     batch_load_l<true>(L, ldL, j, k0, 1, wq.hi, xs, vs);
                     if (batch_reduce(j, k0, 1, wq.hi, wq.xb, wq.vlo, n, xs, vs, best, bk))
                         break;
@@ -719,35 +755,36 @@ __device__ __forceinline__ void bracket_levels(BracketSmem &sm, const int32_t *_
     }
 }
 
+template <class C>
 __device__ __forceinline__ void bracket_block(const int32_t *__restrict__ U, int32_t hU,
-                              const int32_t *__restrict__ L, int32_t hL, int32_t *__restrict__ G,
-                              int32_t n, int32_t i0, int32_t len, int32_t j0, int32_t jn,
-                              const int32_t *__restrict__ Ka, const int32_t *__restrict__ Kb,
-                              BracketSmem &sm) {
+                                              const int32_t *__restrict__ L, int32_t hL,
+                                              int32_t *__restrict__ G, int32_t n, int32_t i0,
+                                              int32_t len, int32_t j0, int32_t jn,
+                                              const int32_t *__restrict__ Ka,
+                                              const int32_t *__restrict__ Kb, BracketSmemT<C> &sm) {
     if (len < 2 || jn <= 0) return;
-    constexpr int32_t S = kJChunk;  // LDS row stride; item slots per vertex
-    static_assert((kMaxTile / 2) * kJChunk <= kBracketItems * kBlock,
-                  "a bisection level exceeds kBracketItems outputs per thread");
-    static_assert(kJChunk <= kWave / 2, "tile ends are read by half a wave each");
+    constexpr int32_t S = C::kJ;  // LDS row stride; item slots per vertex
+    static_assert((kMaxTile / 2) * S <= 4 * kBlock, "a bisection level exceeds 4 outputs per thread");
+    static_assert(S <= kWave, "tile ends are read by one wave");
     const int32_t INF = n + 1;
     const int32_t H = hU + hL + 1;
     const int32_t ldU = hU + 1, ldL = hL + 1;
     const int32_t js = imin(jn, S);  // weights solved by bisection
     const int32_t lane = __lane_id();
-    // Tile ends: in every wave, lanes 0..31 hold k*(i0, j0 + lane) and lanes
-    // 32..63 k*(i1, j0 + lane - 32); wave 0 also stores them in LDS.
-    const int32_t side = lane >> 5, jj0 = lane & 31;
-    const bool lend = jj0 < js;
-    const int32_t kend = lend ? (side ? Kb : Ka)[j0 + jj0] : -1;
-    const unsigned long long live = __ballot(side == 0 && kend >= 0);
-    const int32_t ka0 = __shfl(kend, 0, kWave);  // k*(i0, j0)
+    // Tile ends, in every wave: lane l holds k*(i0, j0 + l) and k*(i1, j0 + l);
+    // wave 0 also stores them (and the ends' values) in LDS.
+    const bool lend = lane < js;
+    const int32_t kA = lend ? Ka[j0 + lane] : -1;
+    const int32_t kB = lend ? Kb[j0 + lane] : -1;
+    const unsigned long long live = __ballot(kA >= 0);
+    const int32_t ka0 = __shfl(kA, 0, kWave);                     // k*(i0, j0)
     const int32_t jl = live ? 63 - __clzll((long long)live) : 0;  // last weight reachable from i0
-    const int32_t kbl = __shfl(kend, 32 + jl, kWave);                // k*(i1, jl)
+    const int32_t kbl = __shfl(kB, jl, kWave);                    // k*(i1, jl)
     if (threadIdx.x < kWave && lend) {
-        const int32_t slot = side ? len : 0;
-        const int32_t vert = i0 + slot;
-        sm.k[slot * S + jj0] = kend;
-        sm.v[slot * S + jj0] = G[(size_t)vert * H + j0 + jj0];
+        stk(sm, lane, kA);
+        stk(sm, len * S + lane, kB);
+        sm.v[lane] = (typename C::St)umin(G[(size_t)i0 * H + j0 + lane], INF);
+        sm.v[len * S + lane] = (typename C::St)umin(G[(size_t)(i0 + len) * H + j0 + lane], INF);
     }
     if (threadIdx.x < 2) sm.qn[threadIdx.x] = 0;
     if (threadIdx.x < kCoarseItems) sm.key[threadIdx.x] = ~0ull;
@@ -767,19 +804,20 @@ __device__ __forceinline__ void bracket_block(const int32_t *__restrict__ U, int
         __syncthreads();
         return;
     }
-    const bool lds_u = (kbl >= 0) && (kbl - ka0 + len + 1 <= kUWin);
+    constexpr int32_t UW = C::kUW;
+    const bool lds_u = (kbl >= 0) && (kbl - ka0 + len + 1 <= UW);
     if (lds_u) {  // copy the D_U parallelogram (all rows: an idle output reads row 0)
-        for (int32_t e = threadIdx.x; e < (len + 1) * kUWin; e += kBlock) {
-            const int32_t v = e / kUWin, c = e - v * kUWin;
+        for (int32_t e = threadIdx.x; e < (len + 1) * UW; e += kBlock) {
+            const int32_t v = e / UW, c = e - v * UW;
             const int32_t k = imin(imax(ka0 - v + c, 0), hU);
-            sm.u[v * kUWin + c] = umin(U[(size_t)(i0 + v) * ldU + k], INF);
+            sm.u[v * UW + c] = (typename C::St)umin(U[(size_t)(i0 + v) * ldU + k], INF);
         }
     }
     __syncthreads();
     if (lds_u)
-        bracket_levels<true>(sm, U, hU, L, hL, G, n, i0, len, j0, js, ka0);
+        bracket_levels<C, true>(sm, U, hU, L, hL, G, n, i0, len, j0, js, ka0);
     else
-        bracket_levels<false>(sm, U, hU, L, hL, G, n, i0, len, j0, js, ka0);
+        bracket_levels<C, false>(sm, U, hU, L, hL, G, n, i0, len, j0, js, ka0);
     __syncthreads();
 }
 

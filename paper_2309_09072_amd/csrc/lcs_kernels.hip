@@ -64,8 +64,9 @@ __global__ void __launch_bounds__(kBlock) k_anchor(CombineArgs c) {
     }
 }
 
+template <class C>
 __global__ void __launch_bounds__(kBlock) k_bracket(CombineArgs c) {
-    __shared__ BracketSmem sm;
+    __shared__ BracketSmemT<C> sm;
     const int32_t p = blockIdx.y;
     const int32_t tile = blockIdx.x / c.nchunks, chunk = blockIdx.x - tile * c.nchunks;
     const StripRef U = child_strip(c, 2 * p), L = child_strip(c, 2 * p + 1);
@@ -79,7 +80,7 @@ __global__ void __launch_bounds__(kBlock) k_bracket(CombineArgs c) {
     int32_t *G = parent_strip(c, p);
     const int32_t *Ka = c.anch + ((size_t)p * c.nanch + tile) * (size_t)c.hs;
     const int32_t *Kb = c.anch + ((size_t)p * c.nanch + tile + 1) * (size_t)c.hs;
-    bracket_block(U.d, U.h, L.d, L.h, G, c.n, i0, len, j0, jn, Ka, Kb, sm);
+    bracket_block<C>(U.d, U.h, L.d, L.h, G, c.n, i0, len, j0, jn, Ka, Kb, sm);
 }
 
 __global__ void __launch_bounds__(kBlock) k_length(const int32_t *top, int32_t m, int32_t n,
@@ -223,10 +224,20 @@ hipError_t launch_anchor(const CombineArgs &c, int32_t npairs, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_bracket(const CombineArgs &c, int32_t npairs, hipStream_t s) {
-    const int32_t ntiles = (c.n + c.tile - 1) / c.tile;
+hipError_t launch_bracket(const CombineArgs &c0, int32_t npairs, hipStream_t s) {
+    const int32_t ntiles = (c0.n + c0.tile - 1) / c0.tile;
     if (ntiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_bracket, dim3(ntiles * c.nchunks, npairs), dim3(kBlock), 0, s, c);
+    // 16-bit state (64 weights per work-group) when every value fits
+    const bool narrow = (c0.n + 1 <= 65535) && (c0.hc <= 65534);
+    CombineArgs c = c0;
+    c.jchunk = narrow ? BracketCfg16::kJ : BracketCfg32::kJ;
+    c.nchunks = imax(1, (c.hs - 1 + c.jchunk - 1) / c.jchunk);  // hs = 2 hc + 1 weights
+    if (narrow)
+        hipLaunchKernelGGL(k_bracket<BracketCfg16>, dim3(ntiles * c.nchunks, npairs), dim3(kBlock),
+                           0, s, c);
+    else
+        hipLaunchKernelGGL(k_bracket<BracketCfg32>, dim3(ntiles * c.nchunks, npairs), dim3(kBlock),
+                           0, s, c);
     return hipGetLastError();
 }
 
