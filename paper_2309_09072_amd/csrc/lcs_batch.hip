@@ -111,7 +111,7 @@ __device__ __forceinline__ CombineArgs pair_combine_args(const PairRec &P, uint8
 union PersistentSmem {
     int32_t nm[kWaves];
     int32_t base[kWave * 65];
-    unsigned long long anchor[kBlock];
+    AnchorSmemBlock anchor;
     BracketSmem bracket;
     int32_t len[1];
     int32_t split[1];
@@ -341,7 +341,7 @@ __global__ void __launch_bounds__(kBlock) k_stage(BatchArgs A, StageArgs S) {
 }
 
 // Staged anchor search with the vertex's D_U row and k* row in dynamic LDS
-// (kBlock uint64, hc + 1 and 2 hc + 1 int32; hc = child strip height, the
+// (the search's AnchorSmem, hc + 1 and 2 hc + 1 int32; hc = child strip height, the
 // same for every pair at one level).
 template <int H0>
 __global__ void __launch_bounds__(kBlock) k_stage_anchor_lds(BatchArgs A, StageArgs S, int32_t hc) {
@@ -368,10 +368,11 @@ __global__ void __launch_bounds__(kBlock) k_stage_anchor_lds(BatchArgs A, StageA
     const int32_t q = u / P.nanch, an = u - q * P.nanch;
     const StripRef U = child_strip(c, 2 * q), L = child_strip(c, 2 * q + 1);
     int32_t *G = parent_strip(c, q);
-    int32_t *us = reinterpret_cast<int32_t *>(dyn + kBlock);
+    AnchorSmemBlock &sm = *reinterpret_cast<AnchorSmemBlock *>(dyn);
+    int32_t *us = reinterpret_cast<int32_t *>(dyn + sizeof(AnchorSmemBlock) / 8);
     int32_t *ks = us + (hc + 1);
-    anchor_block_t<true, kBlock>(U.d, U.h, L.d, L.h, G, P.n, anchor_vertex(an, A.tile, P.n),
-                                 c.anch + ((size_t)q * c.nanch + an) * (size_t)c.hs, dyn, us, ks);
+    anchor_block_t<true, kBlock, 4>(U.d, U.h, L.d, L.h, G, P.n, anchor_vertex(an, A.tile, P.n),
+                                    c.anch + ((size_t)q * c.nanch + an) * (size_t)c.hs, sm, us, ks);
     if (an == c.nanch - 1) {
         const int32_t H = U.h + L.h + 1;
         int32_t *srow = G + (size_t)(P.n + 1) * H;
@@ -405,7 +406,7 @@ template <int H0>
 static hipError_t launch_stage(const BatchArgs &A, const StageArgs &S, dim3 grid, hipStream_t st) {
     if (S.kind == ST_ANCHOR && S.level >= 1 && S.level < kMaxLev) {
         const int32_t hc = H0 << (S.level - 1);
-        const size_t bytes = (size_t)kBlock * 8 + 4 * ((size_t)hc + 1 + 2 * (size_t)hc + 1);
+        const size_t bytes = sizeof(AnchorSmemBlock) + 4 * ((size_t)hc + 1 + 2 * (size_t)hc + 1);
         if (bytes <= kStageMaxLds) {
             const hipError_t e = opt_in_stage_lds();
             if (e != hipSuccess) return e;

@@ -19,6 +19,7 @@ constexpr int kWave = 64;
 constexpr int kWaves = kBlock / kWave;
 constexpr int kJChunk = 32;  // weights per bracket block (a block may take kJChunk + 1)
 constexpr int kBatch = 8;    // candidates whose loads are issued together
+constexpr int kAnchorEval = 8;  // anchor search: candidates per thread per depth
 constexpr int kMaxTile = 32;
 
 __host__ __device__ __forceinline__ int32_t imin(int32_t a, int32_t b) { return a < b ? a : b; }
@@ -235,18 +236,70 @@ __device__ __forceinline__ bool batch_reduce(int32_t j, int32_t k0, int32_t step
 // minimum is unreachable makes every column to its right unreachable.
 //
 // GPU form: the recursion tree is walked level-synchronously over positions
-// 0..P-2 (P a power of two > H): at stride s the columns s-1+2st are solved,
-// bounded by columns c-s and c+s (position -1 and positions >= H are the open
-// bounds 0 and hU).  Few wide columns get many threads each (strided scan +
-// LDS 64-bit atomic min of (value, k), i.e. Alg. 2's minimum with the smaller
-// index on ties); many narrow columns get one thread each.  A scan in
-// increasing k stops early once D_U(vtx, k) - k >= best - j: since
-// D_L(x, w) >= x + w, no later k can reach `best`.
+// 0..P-2 (P a power of two > H), with a fan-out f per depth instead of
+// Alg. 1's halving: when the columns c with (c + 1) % S == 0 are solved, the
+// next depth solves every column with (c + 1) % (S / f) == 0 in between, each
+// bounded by the two solved columns around it (position -1 and positions >= H
+// are the open bounds 0 and hU).  Monotonicity bounds a column by ANY solved
+// column on either side, so the result is the same for every f; f = 2 is
+// Alg. 1's order.  f is the largest power of two that keeps a depth's
+// candidates near kAnchorEval per thread, so a top-level row of 4097 columns
+// takes 5-7 depths instead of 13.
+// Within a depth the candidates of all new columns form one flat list (an
+// exclusive prefix sum over the columns' window sizes) cut into equal
+// consecutive runs, one per thread: the cost of a depth is its total number
+// of candidates over the thread count, whatever the shape of the windows.
+// A column-per-thread scan would instead wait for its longest window, and on
+// rows with many unreachable columns (right of the vertex's LCS) the
+// windows beside the reachable boundary are hundreds of candidates long.
+// Each thread folds its run's (value, k) keys per column and merges them into
+// the column's LDS 64-bit minimum, i.e. Alg. 2's minimum with the smaller
+// index on ties.  Windows stop at KU, the largest k with D_U(vtx, k) <= n:
+// beyond it D_U is the unreachable sentinel and so is every candidate.
 // Krow (global, H entries) receives k*(j) or -1; D_G row vtx receives values.
-// NT threads.  kLds: the D_U row and the k* row live in LDS (us: hU + 1
-// entries, ks: H entries; Krow is written once at the end), so that a
-// candidate costs one global load (the D_L gather); otherwise both are read
-// from global memory.  red: NT uint64 for the per-column minima.
+// NT threads; a depth's new columns are processed NT * CPT at a time.  kLds:
+// the D_U row and the k* row live in LDS (us: hU + 1 entries, ks: H entries;
+// Krow is written once at the end), so that a candidate costs one global load
+// (the D_L gather); otherwise both are read from global memory.
+template <int NT, int CPT>
+struct AnchorSmem {
+    static constexpr int32_t kCols = NT * CPT;  // columns per segment
+    unsigned long long key[kCols];              // per-column (value, k) minimum
+    int32_t cps[kCols + 1];                     // exclusive prefix of window sizes
+    int32_t clo[kCols];                         // first k of each window
+    int32_t wsum[NT / kWave];
+    int32_t ku;
+};
+
+// Inclusive prefix sum over a wave: lane l receives v[0] + ... + v[l].
+__device__ __forceinline__ int32_t wave_prefix_sum(int32_t v) {
+    const int lane = __lane_id();
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const int32_t t = __shfl_up(v, d, kWave);
+        if (lane >= d) v += t;
+    }
+    return v;
+}
+// Exclusive prefix sum over the NT threads of a block; total receives the sum
+// of all.  wsum: NT / kWave int32 of LDS, reusable after the next barrier.
+template <int NT>
+__device__ __forceinline__ int32_t block_exclusive_sum(int32_t v, int32_t *wsum, int32_t &total) {
+    const int32_t incl = wave_prefix_sum(v);
+    const int w = (int)threadIdx.x / kWave;
+    if (__lane_id() == kWave - 1) wsum[w] = incl;
+    __syncthreads();
+    int32_t before = 0;
+    total = 0;
+#pragma unroll
+    for (int w2 = 0; w2 < NT / kWave; ++w2) {
+        const int32_t t = wsum[w2];
+        before += (w2 < w) ? t : 0;
+        total += t;
+    }
+    return before + incl - v;
+}
+
 template <bool kLds>
 __device__ __forceinline__ int32_t anchor_u(const int32_t *__restrict__ U, uint32_t urow,
                                             const int32_t *us, int32_t k, int32_t n) {
@@ -254,36 +307,12 @@ __device__ __forceinline__ int32_t anchor_u(const int32_t *__restrict__ U, uint3
     return umin(ld_cell(U, urow + (uint32_t)k), n + 1);
 }
 
-template <bool kLds>
-__device__ __forceinline__ void anchor_scan(const int32_t *__restrict__ U, uint32_t urow,
-                                            const int32_t *us, const int32_t *__restrict__ L,
-                                            int32_t ldL, int32_t j, int32_t lo, int32_t hi,
-                                            int32_t step, int32_t n, int32_t &best, int32_t &bk) {
-    best = n + 2;
-    bk = -1;
-    if (lo <= hi)
-        for (int32_t k0 = lo;; k0 += kBatch * step) {
-            int32_t xs[kBatch], vs[kBatch];
-#pragma unroll
-            for (int t = 0; t < kBatch; ++t)
-                xs[t] = anchor_u<kLds>(U, urow, us, imin(k0 + t * step, hi), n);
-            if (step == 1)
-                batch_load_l<true>(L, ldL, j, k0, step, hi, xs, vs);
-            else
-                batch_load_l<false>(L, ldL, j, k0, step, hi, xs, vs);
-            if (batch_reduce(j, k0, step, hi, n, -1, n, xs, vs, best, bk)) break;
-        }
-    if (best > n) {
-        best = n + 1;
-        bk = -1;
-    }
-}
-
-template <bool kLds, int NT>
+template <bool kLds, int NT, int CPT>
 __device__ void anchor_block_t(const int32_t *__restrict__ U, int32_t hU,
                                const int32_t *__restrict__ L, int32_t hL, int32_t *__restrict__ G,
                                int32_t n, int32_t vtx, int32_t *__restrict__ Krow,
-                               unsigned long long *red, int32_t *us, int32_t *ks) {
+                               AnchorSmem<NT, CPT> &sm, int32_t *us, int32_t *ks) {
+    constexpr int32_t CM = AnchorSmem<NT, CPT>::kCols;
     const int32_t INF = n + 1;
     const int32_t H = hU + hL + 1;
     int32_t P = 1;
@@ -292,61 +321,147 @@ __device__ void anchor_block_t(const int32_t *__restrict__ U, int32_t hU,
     int32_t *__restrict__ grow = G + (size_t)vtx * (size_t)H;
     int32_t *krow = kLds ? ks : Krow;
     const int32_t ldL = hL + 1;
-    if (kLds) {
-        for (int32_t k = threadIdx.x; k <= hU; k += NT) us[k] = umin(ld_cell(U, urow + (uint32_t)k), INF);
-        __syncthreads();
+    if (threadIdx.x == 0) sm.ku = -1;
+    __syncthreads();
+    // D_U row (non-decreasing in k) and KU
+    for (int32_t k = threadIdx.x; k <= hU; k += NT) {
+        const int32_t x = umin(ld_cell(U, urow + (uint32_t)k), INF);
+        const int32_t xn = (k < hU) ? umin(ld_cell(U, urow + (uint32_t)k + 1u), INF) : INF;
+        if (kLds) us[k] = x;
+        if (x <= n && xn > n) sm.ku = k;
     }
-    for (int32_t s = P >> 1; s >= 1; s >>= 1) {
-        const int32_t ncols = (H - s) >= 0 ? imin((H - s) / (2 * s) + 1, P / (2 * s)) : 0;
-        int32_t g = 1;  // threads per column (power of two), all columns in one pass
-        while (2 * g <= NT && 2 * g * ncols <= NT) g <<= 1;
-        const int32_t cpp = NT / g;  // columns per pass
-        const int32_t gl = (int32_t)threadIdx.x & (g - 1);
-        const int32_t slot = (int32_t)threadIdx.x / g;
-        for (int32_t base = 0; base < ncols; base += cpp) {
-            const int32_t t = base + slot;
-            const bool act = t < ncols;
-            const int32_t c = s - 1 + t * 2 * s;
-            unsigned long long key = ~0ull;
-            bool dead = false;
-            if (act) {
-                const int32_t cl = c - s, cr = c + s;
-                int32_t kl = 0, kr = hU;
-                if (cl >= 0) {
-                    kl = krow[cl];
-                    if (kl < 0) dead = true;
+    __syncthreads();
+    const int32_t KU = sm.ku;
+    for (int32_t S = P; S > 1;) {
+        // fan-out: the f - 1 new columns of each interval scan about
+        // (f - 1) * (hU + 1 + intervals) candidates in all
+        const int32_t rng = hU + 1 + (H + S - 1) / S;
+        int32_t f = 2;
+        while (f < S && (2 * f - 1) * rng <= NT * kAnchorEval) f <<= 1;
+        const int32_t S2 = S / f;
+        const int32_t ncols = H / S2;  // positions (t + 1) * S2 - 1 < H
+        for (int32_t seg = 0; seg < ncols; seg += CM) {
+            // windows of the segment's new columns (already solved positions
+            // and dead columns get none)
+            int32_t r[CPT];
+            int32_t tsum = 0;
+#pragma unroll
+            for (int u = 0; u < CPT; ++u) {
+                const int32_t idx = (int32_t)threadIdx.x * CPT + u;
+                const int32_t t = seg + idx;
+                int32_t lo = 0;
+                r[u] = 0;
+                if (t < ncols && ((t + 1) & (f - 1)) != 0) {
+                    const int32_t c = (t + 1) * S2 - 1;
+                    const int32_t cl = ((t + 1) & ~(f - 1)) * S2 - 1, cr = cl + S;
+                    int32_t kl = 0, kr = hU;
+                    bool dead = false;
+                    if (cl >= 0) {
+                        kl = krow[cl];
+                        dead = kl < 0;
+                    }
+                    if (cr < H) {
+                        const int32_t t2 = krow[cr];
+                        if (t2 >= 0) kr = t2;
+                    }
+                    lo = imax(kl, imax(c - hL, 0));
+                    const int32_t hi = imin(imin(kr, KU), imin(c, hU));
+                    if (!dead && lo <= hi) {
+                        r[u] = hi - lo + 1;
+                    } else {
+                        krow[c] = -1;
+                        grow[c] = INF;
+                    }
                 }
-                if (cr < H) {
-                    const int32_t t2 = krow[cr];
-                    if (t2 >= 0) kr = t2;
+                sm.key[idx] = ~0ull;
+                sm.clo[idx] = lo;
+                tsum += r[u];
+            }
+            int32_t W;
+            int32_t ex = block_exclusive_sum<NT>(tsum, sm.wsum, W);
+#pragma unroll
+            for (int u = 0; u < CPT; ++u) {
+                sm.cps[threadIdx.x * CPT + u] = ex;
+                ex += r[u];
+            }
+            if (threadIdx.x == 0) sm.cps[CM] = W;
+            __syncthreads();
+            // candidates e0 .. e1-1 of the flat list
+            const int32_t C = (W + NT - 1) / NT;
+            const int32_t e0 = (int32_t)threadIdx.x * C;
+            const int32_t e1 = imin(e0 + C, W);
+            if (e0 < e1) {
+                // the column holding e0: the last index with cps <= e0 (a
+                // non-empty window, since cps[CM] = W > e0)
+                int32_t col = 0;
+                for (int32_t hi2 = CM - 1; col < hi2;) {
+                    const int32_t mid = (col + hi2 + 1) >> 1;
+                    if (sm.cps[mid] <= e0)
+                        col = mid;
+                    else
+                        hi2 = mid - 1;
                 }
-                if (!dead) {
-                    const int32_t lo = imax(kl, imax(c - hL, 0));
-                    const int32_t hi = imin(kr, imin(c, hU));
-                    int32_t best, bk;
-                    anchor_scan<kLds>(U, urow, us, L, ldL, c, lo + gl, hi, g, n, best, bk);
-                    if (best <= n) key = ((unsigned long long)(uint32_t)best << 32) | (uint32_t)bk;
+                int32_t cbeg = sm.cps[col], cend = sm.cps[col + 1], clo = sm.clo[col];
+                int32_t rcol = col;
+                unsigned long long run = ~0ull;
+                for (int32_t e = e0; e < e1; e += kBatch) {
+                    int32_t cix[kBatch], kk[kBatch], xs[kBatch], vs[kBatch];
+#pragma unroll
+                    for (int t = 0; t < kBatch; ++t) {
+                        const int32_t ee = imin(e + t, e1 - 1);
+                        while (ee >= cend) {
+                            ++col;
+                            cbeg = cend;
+                            cend = sm.cps[col + 1];
+                            clo = sm.clo[col];
+                        }
+                        cix[t] = col;
+                        kk[t] = clo + (ee - cbeg);
+                    }
+#pragma unroll
+                    for (int t = 0; t < kBatch; ++t) xs[t] = anchor_u<kLds>(U, urow, us, kk[t], n);
+#pragma unroll
+                    for (int t = 0; t < kBatch; ++t) {
+                        const int32_t c = (seg + cix[t] + 1) * S2 - 1;
+                        vs[t] = ld_cell(L, __umul24((uint32_t)xs[t], (uint32_t)ldL) + (uint32_t)(c - kk[t]));
+                    }
+#pragma unroll
+                    for (int t = 0; t < kBatch; ++t) {
+                        if (e + t < e1) {
+                            const unsigned long long key =
+                                ((unsigned long long)(uint32_t)vs[t] << 32) | (uint32_t)kk[t];
+                            if (cix[t] != rcol) {
+                                atomicMin(&sm.key[rcol], run);
+                                rcol = cix[t];
+                                run = key;
+                            } else {
+                                run = key < run ? key : run;
+                            }
+                        }
+                    }
+                }
+                atomicMin(&sm.key[rcol], run);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < CPT; ++u) {
+                if (r[u] > 0) {
+                    const int32_t idx = (int32_t)threadIdx.x * CPT + u;
+                    const int32_t c = (seg + idx + 1) * S2 - 1;
+                    const unsigned long long key = sm.key[idx];
+                    const uint32_t v = (uint32_t)(key >> 32);
+                    if (v <= (uint32_t)n) {
+                        krow[c] = (int32_t)(uint32_t)(key & 0xffffffffull);
+                        grow[c] = (int32_t)v;
+                    } else {
+                        krow[c] = -1;
+                        grow[c] = INF;
+                    }
                 }
             }
-            if (g > 1) {
-                if (gl == 0) red[slot] = ~0ull;
-                __syncthreads();
-                if (act && !dead && key != ~0ull) atomicMin(&red[slot], key);
-                __syncthreads();
-                if (act && gl == 0) key = dead ? ~0ull : red[slot];
-                __syncthreads();
-            }
-            if (act && gl == 0) {
-                if (key == ~0ull) {
-                    krow[c] = -1;
-                    grow[c] = INF;
-                } else {
-                    krow[c] = (int32_t)(uint32_t)(key & 0xffffffffull);
-                    grow[c] = (int32_t)(key >> 32);
-                }
-            }
+            __syncthreads();
         }
-        __syncthreads();
+        S = S2;
     }
     if (kLds) {
         for (int32_t c = threadIdx.x; c < H; c += NT) Krow[c] = ks[c];
@@ -354,12 +469,13 @@ __device__ void anchor_block_t(const int32_t *__restrict__ U, int32_t hU,
     }
 }
 
-// Global-memory form (the batch kernels: fixed LDS budget).  lds: kBlock uint64.
+// Global-memory form (the batch kernels: fixed LDS budget).
+using AnchorSmemBlock = AnchorSmem<kBlock, 4>;
 __device__ __forceinline__ void anchor_block(const int32_t *__restrict__ U, int32_t hU,
                                              const int32_t *__restrict__ L, int32_t hL,
                                              int32_t *__restrict__ G, int32_t n, int32_t vtx,
-                                             int32_t *__restrict__ Krow, unsigned long long *lds) {
-    anchor_block_t<false, kBlock>(U, hU, L, hL, G, n, vtx, Krow, lds, nullptr, nullptr);
+                                             int32_t *__restrict__ Krow, AnchorSmemBlock &sm) {
+    anchor_block_t<false, kBlock, 4>(U, hU, L, hL, G, n, vtx, Krow, sm, nullptr, nullptr);
 }
 
 // ---------------------------------------------------------------------------

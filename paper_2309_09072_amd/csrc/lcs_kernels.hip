@@ -30,8 +30,8 @@ __global__ void __launch_bounds__(kBlock) k_base(const uint8_t *a, int32_t n, in
 }
 
 // Anchor search with the D_U row and the k* row of the vertex in LDS
-// (dynamic: NT uint64 reduction slots, hc + 1 and 2 hc + 1 int32).
-template <int NT>
+// (dynamic: the search's AnchorSmem, then hc + 1 and 2 hc + 1 int32).
+template <int NT, int CPT>
 __global__ void __launch_bounds__(NT) k_anchor_lds(CombineArgs c) {
     extern __shared__ unsigned long long dyn[];
     const int32_t p = blockIdx.y, a = blockIdx.x;
@@ -39,9 +39,10 @@ __global__ void __launch_bounds__(NT) k_anchor_lds(CombineArgs c) {
     int32_t *G = parent_strip(c, p);
     const int32_t vtx = anchor_vertex(a, c.tile, c.n);
     int32_t *Krow = c.anch + ((size_t)p * c.nanch + a) * (size_t)c.hs;
-    int32_t *us = reinterpret_cast<int32_t *>(dyn + NT);
+    AnchorSmem<NT, CPT> &sm = *reinterpret_cast<AnchorSmem<NT, CPT> *>(dyn);
+    int32_t *us = reinterpret_cast<int32_t *>(dyn + sizeof(AnchorSmem<NT, CPT>) / 8);
     int32_t *ks = us + (c.hc + 1);
-    anchor_block_t<true, NT>(U.d, U.h, L.d, L.h, G, c.n, vtx, Krow, dyn, us, ks);
+    anchor_block_t<true, NT, CPT>(U.d, U.h, L.d, L.h, G, c.n, vtx, Krow, sm, us, ks);
     if (a == c.nanch - 1) {  // sentinel row n + 1
         const int32_t H = U.h + L.h + 1;
         int32_t *srow = G + (size_t)(c.n + 1) * H;
@@ -49,18 +50,20 @@ __global__ void __launch_bounds__(NT) k_anchor_lds(CombineArgs c) {
     }
 }
 
-__global__ void __launch_bounds__(kBlock) k_anchor(CombineArgs c) {
-    __shared__ unsigned long long lds[kBlock];
+// Anchor search with both rows in global memory (rows too long for LDS).
+template <int NT, int CPT>
+__global__ void __launch_bounds__(NT) k_anchor(CombineArgs c) {
+    __shared__ AnchorSmem<NT, CPT> sm;
     const int32_t p = blockIdx.y, a = blockIdx.x;
     const StripRef U = child_strip(c, 2 * p), L = child_strip(c, 2 * p + 1);
     int32_t *G = parent_strip(c, p);
     const int32_t vtx = anchor_vertex(a, c.tile, c.n);
     int32_t *Krow = c.anch + ((size_t)p * c.nanch + a) * (size_t)c.hs;
-    anchor_block(U.d, U.h, L.d, L.h, G, c.n, vtx, Krow, lds);
+    anchor_block_t<false, NT, CPT>(U.d, U.h, L.d, L.h, G, c.n, vtx, Krow, sm, nullptr, nullptr);
     if (a == c.nanch - 1) {  // sentinel row n + 1
         const int32_t H = U.h + L.h + 1;
         int32_t *srow = G + (size_t)(c.n + 1) * H;
-        for (int32_t j = threadIdx.x; j < H; j += kBlock) srow[j] = c.n + 1;
+        for (int32_t j = threadIdx.x; j < H; j += NT) srow[j] = c.n + 1;
     }
 }
 
@@ -191,36 +194,68 @@ hipError_t launch_base(int32_t h0, const uint8_t *a, int32_t n, int32_t sigma, c
 // LDS available to one work-group on gfx950
 constexpr size_t kMaxGroupLds = 160 * 1024;
 
-hipError_t launch_anchor(const CombineArgs &c, int32_t npairs, hipStream_t s) {
-    // few anchors (the top levels): 1024 threads each, so that the wide
-    // columns of the first depths and the many narrow ones of the last take
-    // fewer passes
-    const int64_t blocks = (int64_t)c.nanch * npairs;
-    const int32_t nt = (blocks <= 1024) ? 1024 : kBlock;
-    const size_t bytes = (size_t)nt * 8 + 4 * ((size_t)c.hc + 1 + (size_t)c.hs);
-    if (bytes <= kMaxGroupLds) {
-        // opt in to more than 64 KB of dynamic LDS, once per device
-        static bool opted[2][64] = {};
-        int dev = 0;
-        hipError_t e = hipGetDevice(&dev);
-        if (e != hipSuccess) return e;
-        const int w = (nt == 1024) ? 1 : 0;
-        if (dev >= 0 && dev < 64 && !opted[w][dev]) {
-            const void *fn = (nt == 1024) ? (const void *)k_anchor_lds<1024>
-                                          : (const void *)k_anchor_lds<kBlock>;
-            e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)kMaxGroupLds);
-            if (e != hipSuccess) return e;
-            opted[w][dev] = true;
-        }
-        if (nt == 1024)
-            hipLaunchKernelGGL(k_anchor_lds<1024>, dim3(c.nanch, npairs), dim3(1024), bytes, s, c);
-        else
-            hipLaunchKernelGGL(k_anchor_lds<kBlock>, dim3(c.nanch, npairs), dim3(kBlock), bytes, s,
-                               c);
-    } else {
-        hipLaunchKernelGGL(k_anchor, dim3(c.nanch, npairs), dim3(kBlock), 0, s, c);
+// Compute units of the current device (cached per device; 256 if unknown).
+static int64_t device_cus() {
+    static int cus[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (cus[dev] <= 0) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0)
+            v = 256;
+        cus[dev] = v;
     }
+    return cus[dev];
+}
+
+// Opt a kernel in to more than 64 KB of dynamic LDS, once per device.
+template <int NT, int CPT>
+static hipError_t opt_in_anchor_lds() {
+    static bool opted[64] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= 64 || opted[dev]) return hipSuccess;
+    e = hipFuncSetAttribute((const void *)k_anchor_lds<NT, CPT>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxGroupLds);
+    if (e != hipSuccess) return e;
+    opted[dev] = true;
+    return hipSuccess;
+}
+
+template <int NT, int CPT>
+static bool try_anchor_lds(const CombineArgs &c, int32_t npairs, hipStream_t s, hipError_t &e) {
+    const size_t bytes = sizeof(AnchorSmem<NT, CPT>) + 4 * ((size_t)c.hc + 1 + (size_t)c.hs);
+    if (bytes > kMaxGroupLds) return false;
+    e = opt_in_anchor_lds<NT, CPT>();
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL((k_anchor_lds<NT, CPT>), dim3(c.nanch, npairs), dim3(NT), bytes, s, c);
+        e = hipGetLastError();
+    }
+    return true;
+}
+
+hipError_t launch_anchor(const CombineArgs &c, int32_t npairs, hipStream_t s) {
+    // Few anchors (the top levels) get many threads each, so that a depth's
+    // candidates take fewer rounds, but never so many that the work-groups
+    // stop fitting on the chip at once (one 1024-thread or about three
+    // 512-thread work-groups per CU).
+    const int64_t blocks = (int64_t)c.nanch * npairs;
+    const int64_t cus = device_cus();
+    hipError_t e = hipSuccess;
+    if (blocks <= cus) {
+        if (try_anchor_lds<1024, 4>(c, npairs, s, e) || try_anchor_lds<1024, 2>(c, npairs, s, e))
+            return e;
+        hipLaunchKernelGGL((k_anchor<1024, 2>), dim3(c.nanch, npairs), dim3(1024), 0, s, c);
+        return hipGetLastError();
+    }
+    if (blocks <= 3 * cus) {
+        if (try_anchor_lds<512, 4>(c, npairs, s, e)) return e;
+        hipLaunchKernelGGL((k_anchor<512, 4>), dim3(c.nanch, npairs), dim3(512), 0, s, c);
+        return hipGetLastError();
+    }
+    if (try_anchor_lds<kBlock, 4>(c, npairs, s, e)) return e;
+    hipLaunchKernelGGL((k_anchor<kBlock, 4>), dim3(c.nanch, npairs), dim3(kBlock), 0, s, c);
     return hipGetLastError();
 }
 
