@@ -105,33 +105,90 @@ __device__ void nextmatch_block(const uint8_t *__restrict__ b, int32_t n, int32_
 // The finished rows go through LDS so the store to HBM is contiguous: rows
 // v..v+63 of a strip matrix are adjacent in memory.  The waves take turns on
 // one 64-row buffer, and all 256 threads copy each turn out.
-// lds: kWave*(H0+1) int32.
-template <int H0>
-__device__ void base_strip_block(const uint8_t *__restrict__ arow, int32_t h, int32_t n,
-                                 int32_t sigma, const int32_t *__restrict__ nm,
-                                 int32_t *__restrict__ out, int32_t v0, int32_t *err,
-                                 int32_t *lds) {
-    const int32_t INF = n + 1;
-    const int lane = __lane_id();
-    const int w = threadIdx.x / kWave;
-    const int32_t i = v0 + (int32_t)threadIdx.x;
-    int32_t D[H0 + 1];
-    D[0] = (i <= n) ? i : INF;
-#pragma unroll
-    for (int j = 1; j <= H0; ++j) D[j] = INF;
+//
+// Table window (kTab): the ~h^2/2 lookups per vertex are gathers, and served
+// by the vector memory path they cost ~16 cycles per wave instruction; from
+// LDS they cost a few.  The work-group copies columns v0 .. v0+T-1 of every
+// symbol's table into LDS as uint16 values relative to v0 (entry T of each
+// symbol is a marker above every value), keeps D relative to v0, and clamps
+// lookup indices to T.  A clamped lookup stands for a table value above T
+// (the next match after column c is > c), so by induction over the rows
+// every computed entry <= T is exact and every exact entry <= T is computed;
+// only entries > T can be wrong.  Hence the result is exact when the window
+// reaches the sentinel column n + 1, or when no entry ends above T; in the
+// remaining case the work-group recomputes the strip from the global tables.
+// lds: kWave*(H0+1) int32; tab: kBaseTab uint16 (kTab only).
+constexpr int32_t kBaseTab = 8192;    // LDS table entries per work-group
+constexpr int32_t kBaseTabCap = 2047; // at most this many columns per symbol
+
+template <int H0, class Look>
+__device__ __forceinline__ bool base_append_rows(const uint8_t *__restrict__ arow, int32_t h,
+                                                 int32_t sigma, int32_t (&D)[H0 + 1], Look look) {
     bool bad = false;
 #pragma unroll
     for (int r = 0; r < H0; ++r) {
         if (r < h) {
             const int32_t x = arow[r];
             if (x < sigma) {
-                const int32_t *__restrict__ nmx = nm + (size_t)x * (size_t)(n + 2);
 #pragma unroll
-                for (int j = r + 1; j >= 1; --j) D[j] = umin(D[j], nmx[D[j - 1]]);
+                for (int j = r + 1; j >= 1; --j) D[j] = umin(D[j], look(x, D[j - 1]));
             } else {
                 bad = true;
             }
         }
+    }
+    return bad;
+}
+
+template <int H0, bool kTab = false>
+__device__ void base_strip_block(const uint8_t *__restrict__ arow, int32_t h, int32_t n,
+                                 int32_t sigma, const int32_t *__restrict__ nm,
+                                 int32_t *__restrict__ out, int32_t v0, int32_t *err,
+                                 int32_t *lds, uint16_t *tab = nullptr) {
+    const int32_t INF = n + 1;
+    const int lane = __lane_id();
+    const int w = threadIdx.x / kWave;
+    const int32_t i = v0 + (int32_t)threadIdx.x;
+    const size_t ldn = (size_t)(n + 2);
+    int32_t D[H0 + 1];
+    bool bad = false;
+    bool done = false;
+    // The window is used when it is likely to hold every lookup: for random
+    // strings the row matches of a strip lie about H0 * sigma columns past the
+    // vertex, so small alphabets (DNA-like) take it and large ones (protein)
+    // read the global tables directly.
+    if (kTab && n + 2 <= 65535 && kBlock + 2 * H0 * sigma <= imin(kBaseTab / sigma - 1, kBaseTabCap)) {
+        const int32_t T = imin(imin(n + 2 - v0, kBaseTab / sigma - 1), kBaseTabCap);
+        const int32_t ts = T + 1;  // per-symbol stride
+        for (int32_t x = 0; x < sigma; ++x)
+            for (int32_t c = threadIdx.x; c < ts; c += kBlock)
+                tab[x * ts + c] = (c < T) ? (uint16_t)(nm[(size_t)x * ldn + (size_t)(v0 + c)] - v0)
+                                          : (uint16_t)0xFFFF;
+        __syncthreads();
+        D[0] = (i <= n) ? (int32_t)threadIdx.x : INF - v0;
+#pragma unroll
+        for (int j = 1; j <= H0; ++j) D[j] = INF - v0;
+        bad = base_append_rows<H0>(arow, h, sigma, D, [&](int32_t x, int32_t d) {
+            return (int32_t)tab[x * ts + umin(d, T)];
+        });
+        bool unsure = false;
+        if (v0 + T < n + 1) {
+#pragma unroll
+            for (int j = 0; j <= H0; ++j) unsure |= D[j] > T;
+        }
+        done = !__syncthreads_or(unsure);
+        if (done) {
+#pragma unroll
+            for (int j = 0; j <= H0; ++j) D[j] += v0;
+        }
+    }
+    if (!done) {
+        D[0] = (i <= n) ? i : INF;
+#pragma unroll
+        for (int j = 1; j <= H0; ++j) D[j] = INF;
+        bad = base_append_rows<H0>(arow, h, sigma, D, [&](int32_t x, int32_t d) {
+            return nm[(size_t)x * ldn + (size_t)d];
+        });
     }
     if (bad && threadIdx.x == 0) atomicOr(err, kErrSymbol);
     const int32_t hp1 = h + 1;

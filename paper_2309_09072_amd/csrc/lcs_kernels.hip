@@ -21,12 +21,13 @@ __global__ void __launch_bounds__(kBlock) k_base(const uint8_t *a, int32_t n, in
                                                  const int32_t *nm, int32_t *base0, int32_t *last,
                                                  int32_t nstrips, int32_t hlast, int32_t *err) {
     __shared__ int32_t lds[kWave * (H0 + 1)];
+    __shared__ uint16_t tab[kBaseTab];
     const int32_t s = blockIdx.y;
     const bool is_last = (s == nstrips - 1);
     const int32_t h = is_last ? hlast : H0;
     int32_t *out = is_last ? last : base0 + (size_t)s * strip_elems(n, H0);
-    base_strip_block<H0>(a + (size_t)s * H0, h, n, sigma, nm, out, (int32_t)blockIdx.x * kBlock, err,
-                         lds);
+    base_strip_block<H0, true>(a + (size_t)s * H0, h, n, sigma, nm, out, (int32_t)blockIdx.x * kBlock,
+                               err, lds, tab);
 }
 
 // Anchor search with the D_U row and the k* row of the vertex in LDS

@@ -77,6 +77,38 @@ def test_levels_cell_for_cell(base_rows, tile):
         check_against_oracle(a, b, sig, base_rows=base_rows, tile=tile, check_levels=True)
 
 
+def _base_rows_check(a, b, plan, ws, verts):
+    """Every base strip's rows for the sampled vertices against the oracle."""
+    for s in range(plan.levels()[0]):
+        D, row0 = plan.dist(0, s, ws)
+        h = D.shape[1] - 1
+        got = D[verts].cpu().numpy()
+        want = oracle.dist_rows(a, row0, row0 + h, b, verts)
+        bad = np.argwhere(got != want)
+        assert bad.size == 0, "strip %d: vertex %d weight %d got %d want %d" % (
+            s, verts[bad[0][0]], bad[0][1], got[tuple(bad[0])], want[tuple(bad[0])])
+
+
+def test_base_table_window_and_fallback():
+    """Base strips of a small alphabet read a window of the next-match tables
+    from LDS; entries past the window are recomputed from the global tables.
+    Case 1: i.i.d. strings (every work-group exact from its window).  Case 2:
+    symbol 3 is absent from b's first 4000 columns, so strips holding it
+    reach past the window of every vertex block left of ~1950 and take the
+    fallback; blocks further right see the whole table."""
+    r = np.random.default_rng(4242)
+    n = 5000
+    verts = sorted(set(list(range(0, n + 1, 37)) + [1, 255, 256, 257, 1950, 2954, 2955, n - 1, n]))
+    a1 = r.integers(0, 4, 256).astype(np.uint8)
+    b1 = r.integers(0, 4, n).astype(np.uint8)
+    b2 = np.concatenate([r.integers(0, 3, 4000), r.integers(0, 4, n - 4000)]).astype(np.uint8)
+    for a, b in ((a1, b1), (a1, b2)):
+        for h0 in (16, 64):
+            say("base window", h0, int(b[:4000].max()))
+            Lg, plan, ws = check_against_oracle(a, b, 4, base_rows=h0)
+            _base_rows_check(a, b, plan, ws, verts)
+
+
 def test_paper_grid_example():
     """Fig. 1 grid: rows tcaggatt, columns gatttatgcagg; breakouts of Section II-B-1."""
     a = np.frombuffer(b"tcaggatt", np.uint8) - ord("a")
