@@ -571,6 +571,7 @@ __device__ __forceinline__ void anchor_block(const int32_t *__restrict__ U, int3
 // block that holds it (jn = kJ + 1) evaluates it directly, so the
 // bisection works on at most kJ weights.
 constexpr int kCoarseItems = kBlock / 2;  // a level with at most this many outputs is coarse
+constexpr int32_t kCoopPass2MinH = 1024;  // child strip height from which pass 2 is cooperative
 // Shape of a bracket work-group: LDS state type, weights per block, width of
 // the D_U parallelogram.  32-bit state: any size.  16-bit state (values and
 // indices stored in 16 bits, k* stored as k* + 1 so that -1 is 0): needs
@@ -865,7 +866,7 @@ __device__ __forceinline__ void bracket_coarse(BracketSmemT<C> &sm, const int32_
     }
 }
 
-template <class C, bool kLds>
+template <class C, bool kLds, bool kCoop>
 __device__ __forceinline__ void bracket_levels(BracketSmemT<C> &sm, const int32_t *__restrict__ U,
                                                int32_t hU, const int32_t *__restrict__ L,
                                                int32_t hL, int32_t *__restrict__ G, int32_t n,
@@ -904,9 +905,52 @@ __device__ __forceinline__ void bracket_levels(BracketSmemT<C> &sm, const int32_
                                          par, ubase, 0);
         }
         __syncthreads();
-        // pass 2: the queued outputs, one per thread
+        // pass 2: the queued outputs.  kCoop (tall strips) and few of them: g
+        // threads each scan interleaved slices of kBatch candidates, so an
+        // output sees g * kBatch candidates per round trip (slice minima meet
+        // in the LDS (value, k) minimum; the provisional pass-1 result, whose
+        // candidates all lie below, keeps ties).  Otherwise one thread each,
+        // batch after batch.  Measured on both benchmark pairs: queued outputs
+        // of strips below kCoopPass2MinH rows mostly finish in one more batch,
+        // and the second barrier of the cooperative form then costs more than
+        // it saves; above it they take several.
         const int32_t qn = sm.qn[par];
-        if (qn > 0) {
+        if (kCoop && qn > 0 && qn <= kCoarseItems) {
+            int32_t g = 1;
+            while (2 * g * qn <= kBlock) g <<= 1;
+            const int32_t e = (int32_t)threadIdx.x / g, sub = (int32_t)threadIdx.x - e * g;
+            if (e < qn) {
+                const int32_t idq = (int32_t)sm.q[e];
+                const int32_t v = idq / S, jj = idq - v * S;
+                const int32_t j = j0 + jj;
+                const BracketWindow wq = bracket_window<C, kLds>(sm, U, ldU, i0, ubase, v, v - half,
+                                                              imin(v + half, len), jj, j, hU, hL, n);
+                const int32_t best0 = (int32_t)sm.v[idq];
+                int32_t best = best0, bk = -1;
+                for (int32_t k0 = wq.lo + b1 + sub * kBatch; k0 <= wq.hi; k0 += g * kBatch) {
+                    int32_t xs[kBatch], vs[kBatch];
+                    bracket_load_u<C, kBatch, kLds>(sm, U, ldU, hU, i0, ubase, v, k0, wq.hi, n, xs);
+                    batch_load_l<true>(L, ldL, j, k0, 1, wq.hi, xs, vs);
+                    if (batch_reduce(j, k0, 1, wq.hi, wq.xb, wq.vlo, n, xs, vs, best, bk)) break;
+                }
+                if (best < best0)
+                    atomicMin(&sm.key[e], ((unsigned long long)(uint32_t)best << 32) | (uint32_t)bk);
+            }
+            __syncthreads();
+            if ((int32_t)threadIdx.x < qn) {
+                const int32_t idq = (int32_t)sm.q[threadIdx.x];
+                const int32_t v = idq / S, jj = idq - v * S;
+                const unsigned long long key = sm.key[threadIdx.x];
+                sm.key[threadIdx.x] = ~0ull;
+                int32_t best = (int32_t)sm.v[idq], bk = ldk(sm, idq);
+                if (key != ~0ull) {
+                    best = (int32_t)(key >> 32);
+                    bk = (int32_t)(uint32_t)(key & 0xffffffffull);
+                }
+                bracket_store(sm, idq, G + (size_t)(i0 + v) * H + j0 + jj, n, best, bk);
+            }
+            __syncthreads();
+        } else if (qn > 0) {
             for (int32_t e = threadIdx.x; e < qn; e += kBlock) {
                 const int32_t idq = (int32_t)sm.q[e];
                 const int32_t v = idq / S, jj = idq - v * S;
@@ -928,7 +972,7 @@ __device__ __forceinline__ void bracket_levels(BracketSmemT<C> &sm, const int32_
     }
 }
 
-template <class C>
+template <class C, bool kCoop = false>
 __device__ __forceinline__ void bracket_block(const int32_t *__restrict__ U, int32_t hU,
                                               const int32_t *__restrict__ L, int32_t hL,
                                               int32_t *__restrict__ G, int32_t n, int32_t i0,
@@ -937,27 +981,45 @@ __device__ __forceinline__ void bracket_block(const int32_t *__restrict__ U, int
                                               const int32_t *__restrict__ Kb, BracketSmemT<C> &sm) {
     if (len < 2 || jn <= 0) return;
     constexpr int32_t S = C::kJ;  // LDS row stride; item slots per vertex
-    static_assert((kMaxTile / 2) * S <= 4 * kBlock, "a bisection level exceeds 4 outputs per thread");
-    static_assert(S <= kWave, "tile ends are read by one wave");
+    constexpr int32_t NE = (S + kWave - 1) / kWave;  // tile-end weights per lane
     const int32_t INF = n + 1;
     const int32_t H = hU + hL + 1;
     const int32_t ldU = hU + 1, ldL = hL + 1;
     const int32_t js = imin(jn, S);  // weights solved by bisection
     const int32_t lane = __lane_id();
-    // Tile ends, in every wave: lane l holds k*(i0, j0 + l) and k*(i1, j0 + l);
-    // wave 0 also stores them (and the ends' values) in LDS.
-    const bool lend = lane < js;
-    const int32_t kA = lend ? Ka[j0 + lane] : -1;
-    const int32_t kB = lend ? Kb[j0 + lane] : -1;
-    const unsigned long long live = __ballot(kA >= 0);
-    const int32_t ka0 = __shfl(kA, 0, kWave);                     // k*(i0, j0)
-    const int32_t jl = live ? 63 - __clzll((long long)live) : 0;  // last weight reachable from i0
-    const int32_t kbl = __shfl(kB, jl, kWave);                    // k*(i1, jl)
-    if (threadIdx.x < kWave && lend) {
-        stk(sm, lane, kA);
-        stk(sm, len * S + lane, kB);
-        sm.v[lane] = (typename C::St)umin(G[(size_t)i0 * H + j0 + lane], INF);
-        sm.v[len * S + lane] = (typename C::St)umin(G[(size_t)(i0 + len) * H + j0 + lane], INF);
+    // Tile ends, in every wave: lane l holds k*(i0, j0 + l + 64 c) and
+    // k*(i1, j0 + l + 64 c); wave 0 also stores them (and the ends' values)
+    // in LDS.  Reachability from i0 is a prefix of the weights.
+    int32_t kA[NE], kB[NE];
+    bool live = false;
+    int32_t kbl = -1;  // k*(i1, jl), jl the last weight reachable from i0
+#pragma unroll
+    for (int c = 0; c < NE; ++c) {
+        const int32_t jj = lane + c * kWave;
+        const bool lend = jj < js;
+        kA[c] = lend ? Ka[j0 + jj] : -1;
+        kB[c] = lend ? Kb[j0 + jj] : -1;
+    }
+#pragma unroll
+    for (int c = 0; c < NE; ++c) {
+        const unsigned long long lv = __ballot(kA[c] >= 0);
+        if (lv) {  // wave-uniform
+            live = true;
+            kbl = __shfl(kB[c], 63 - __clzll((long long)lv), kWave);
+        }
+    }
+    const int32_t ka0 = __shfl(kA[0], 0, kWave);  // k*(i0, j0)
+    if (threadIdx.x < kWave) {
+#pragma unroll
+        for (int c = 0; c < NE; ++c) {
+            const int32_t jj = lane + c * kWave;
+            if (jj < js) {
+                stk(sm, jj, kA[c]);
+                stk(sm, len * S + jj, kB[c]);
+                sm.v[jj] = (typename C::St)umin(G[(size_t)i0 * H + j0 + jj], INF);
+                sm.v[len * S + jj] = (typename C::St)umin(G[(size_t)(i0 + len) * H + j0 + jj], INF);
+            }
+        }
     }
     if (threadIdx.x < 2) sm.qn[threadIdx.x] = 0;
     if (threadIdx.x < kCoarseItems) sm.key[threadIdx.x] = ~0ull;
@@ -988,9 +1050,9 @@ __device__ __forceinline__ void bracket_block(const int32_t *__restrict__ U, int
     }
     __syncthreads();
     if (lds_u)
-        bracket_levels<C, true>(sm, U, hU, L, hL, G, n, i0, len, j0, js, ka0);
+        bracket_levels<C, true, kCoop>(sm, U, hU, L, hL, G, n, i0, len, j0, js, ka0);
     else
-        bracket_levels<C, false>(sm, U, hU, L, hL, G, n, i0, len, j0, js, ka0);
+        bracket_levels<C, false, kCoop>(sm, U, hU, L, hL, G, n, i0, len, j0, js, ka0);
     __syncthreads();
 }
 
@@ -1113,24 +1175,43 @@ __device__ void trace_split_block(const int32_t *__restrict__ U, int32_t hU,
 // written at witness offsets off .. off + w - 1 in increasing order; wcap
 // (= min(m, n)) bounds every write.
 // lds: (H0+1)*(H0+1) int32.
-template <int H0>
+template <int H0, bool kFast = false>
 __device__ void trace_leaf_block(const uint8_t *__restrict__ arow, int32_t h, int32_t n,
                                  int32_t sigma, const int32_t *__restrict__ nm, int4 node,
                                  int32_t row0, int32_t *__restrict__ a_idx,
                                  int32_t *__restrict__ b_idx, int32_t wcap, int32_t *err,
-                                 int32_t *lds) {
+                                 int32_t *lds, int32_t *cand = nullptr, int32_t *tab = nullptr,
+                                 int32_t tabcap = 0) {
     const int32_t INF = n + 1;
     const int32_t s = umin(node.x, n);
     const int32_t S = H0 + 1;
     const int32_t tid = threadIdx.x;
+    // kFast: columns s .. s+W-1 of every symbol's next-match table in LDS
+    // (lookups at or past column s + W read the global table), and every
+    // row's match candidates kept for the backward walk, which then reads
+    // LDS only.
+    const int32_t W = kFast ? imin(n + 2 - s, tabcap / imax(sigma, 1)) : 0;
+    if (kFast) {
+        for (int32_t x = 0; x < sigma; ++x)
+            for (int32_t c = tid; c < W; c += kBlock) tab[x * W + c] = nm[(size_t)x * (n + 2) + (size_t)(s + c)];
+    }
     if (tid <= h) lds[tid] = (tid == 0) ? s : INF;
     __syncthreads();
     for (int32_t r = 0; r < h; ++r) {
         const int32_t x = arow[r];
         if (tid <= h) {
             int32_t d = lds[r * S + tid];
-            if (tid >= 1 && x < sigma) d = umin(d, nm[(size_t)x * (n + 2) + lds[r * S + tid - 1]]);
+            int32_t cd = INF;
+            if (tid >= 1 && x < sigma) {
+                const int32_t p = lds[r * S + tid - 1];
+                if (kFast && p - s < W)
+                    cd = tab[x * W + (p - s)];
+                else
+                    cd = nm[(size_t)x * (n + 2) + p];
+                d = umin(d, cd);
+            }
             lds[(r + 1) * S + tid] = d;
+            if (kFast) cand[(r + 1) * S + tid] = cd;
         }
         __syncthreads();
     }
@@ -1141,7 +1222,8 @@ __device__ void trace_leaf_block(const uint8_t *__restrict__ arow, int32_t h, in
             const int32_t x = arow[r - 1];
             if (w >= 1 && x < sigma) {
                 const int32_t p = lds[(r - 1) * S + (w - 1)];
-                if (p <= n && nm[(size_t)x * (n + 2) + p] == e) {
+                const int32_t cd = kFast ? cand[r * S + w] : (p <= n ? nm[(size_t)x * (n + 2) + p] : INF);
+                if (p <= n && cd == e) {
                     if (off + w <= wcap) {
                         a_idx[off + w - 1] = row0 + r - 1;
                         b_idx[off + w - 1] = e - 1;

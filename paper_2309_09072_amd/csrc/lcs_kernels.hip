@@ -68,8 +68,11 @@ __global__ void __launch_bounds__(NT) k_anchor(CombineArgs c) {
     }
 }
 
-template <class C>
-__global__ void __launch_bounds__(kBlock) k_bracket(CombineArgs c) {
+// At most 64 VGPRs (8 waves per SIMD): with its ~18 KB of LDS eight
+// work-groups fit on a CU, and the kernel is bound by dependent round trips
+// per work-group, so work-groups in flight count more than a few spills.
+template <class C, bool kCoop>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) k_bracket(CombineArgs c) {
     __shared__ BracketSmemT<C> sm;
     const int32_t p = blockIdx.y;
     const int32_t tile = blockIdx.x / c.nchunks, chunk = blockIdx.x - tile * c.nchunks;
@@ -84,7 +87,7 @@ __global__ void __launch_bounds__(kBlock) k_bracket(CombineArgs c) {
     int32_t *G = parent_strip(c, p);
     const int32_t *Ka = c.anch + ((size_t)p * c.nanch + tile) * (size_t)c.hs;
     const int32_t *Kb = c.anch + ((size_t)p * c.nanch + tile + 1) * (size_t)c.hs;
-    bracket_block<C>(U.d, U.h, L.d, L.h, G, c.n, i0, len, j0, jn, Ka, Kb, sm);
+    bracket_block<C, kCoop>(U.d, U.h, L.d, L.h, G, c.n, i0, len, j0, jn, Ka, Kb, sm);
 }
 
 __global__ void __launch_bounds__(kBlock) k_length(const int32_t *top, int32_t m, int32_t n,
@@ -107,6 +110,7 @@ __global__ void __launch_bounds__(kBlock) k_trace_split(CombineArgs c, const int
                       lds);
 }
 
+constexpr int32_t kLeafTab = 4096;  // next-match table entries a leaf block keeps in LDS
 template <int H0>
 __global__ void __launch_bounds__(kBlock) k_trace_leaf(const uint8_t *a, int32_t n, int32_t sigma,
                                                        const int32_t *nm, int32_t nstrips,
@@ -114,10 +118,12 @@ __global__ void __launch_bounds__(kBlock) k_trace_leaf(const uint8_t *a, int32_t
                                                        int32_t *a_idx, int32_t *b_idx,
                                                        int32_t wcap, int32_t *err) {
     __shared__ int32_t lds[(H0 + 1) * (H0 + 1)];
+    __shared__ int32_t cand[(H0 + 1) * (H0 + 1)];
+    __shared__ int32_t tab[kLeafTab];
     const int32_t s = blockIdx.x;
     const int32_t h = (s == nstrips - 1) ? hlast : H0;
-    trace_leaf_block<H0>(a + (size_t)s * H0, h, n, sigma, nm, nodes[s], s * H0, a_idx, b_idx, wcap,
-                         err, lds);
+    trace_leaf_block<H0, true>(a + (size_t)s * H0, h, n, sigma, nm, nodes[s], s * H0, a_idx, b_idx,
+                               wcap, err, lds, cand, tab, kLeafTab);
 }
 
 __global__ void __launch_bounds__(kBlock) k_semilocal(const int32_t *top, int32_t m, int32_t n,
@@ -260,20 +266,31 @@ hipError_t launch_anchor(const CombineArgs &c, int32_t npairs, hipStream_t s) {
     return hipGetLastError();
 }
 
+// bracket shape of the 16-bit state
+using NarrowBracket = BracketCfg16;
+template <class C>
+static void launch_bracket_cfg(const CombineArgs &c, dim3 grid, hipStream_t s) {
+    // the cooperative pass 2 is compiled only into the kernels for tall
+    // strips, so that the others keep their register allocation
+    if (c.hc >= kCoopPass2MinH)
+        hipLaunchKernelGGL((k_bracket<C, true>), grid, dim3(kBlock), 0, s, c);
+    else
+        hipLaunchKernelGGL((k_bracket<C, false>), grid, dim3(kBlock), 0, s, c);
+}
+
 hipError_t launch_bracket(const CombineArgs &c0, int32_t npairs, hipStream_t s) {
     const int32_t ntiles = (c0.n + c0.tile - 1) / c0.tile;
     if (ntiles <= 0) return hipSuccess;
     // 16-bit state (64 weights per work-group) when every value fits
     const bool narrow = (c0.n + 1 <= 65535) && (c0.hc <= 65534);
     CombineArgs c = c0;
-    c.jchunk = narrow ? BracketCfg16::kJ : BracketCfg32::kJ;
+    c.jchunk = narrow ? NarrowBracket::kJ : BracketCfg32::kJ;
     c.nchunks = imax(1, (c.hs - 1 + c.jchunk - 1) / c.jchunk);  // hs = 2 hc + 1 weights
+    const dim3 grid(ntiles * c.nchunks, npairs);
     if (narrow)
-        hipLaunchKernelGGL(k_bracket<BracketCfg16>, dim3(ntiles * c.nchunks, npairs), dim3(kBlock),
-                           0, s, c);
+        launch_bracket_cfg<NarrowBracket>(c, grid, s);
     else
-        hipLaunchKernelGGL(k_bracket<BracketCfg32>, dim3(ntiles * c.nchunks, npairs), dim3(kBlock),
-                           0, s, c);
+        launch_bracket_cfg<BracketCfg32>(c, grid, s);
     return hipGetLastError();
 }
 
