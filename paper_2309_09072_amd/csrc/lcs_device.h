@@ -338,11 +338,35 @@ __device__ __forceinline__ int32_t wave_prefix_sum(int32_t v) {
     }
     return v;
 }
-// Exclusive prefix sum over the NT threads of a block; total receives the sum
-// of all.  wsum: NT / kWave int32 of LDS, reusable after the next barrier.
+// An anchor search runs on a whole block (NT = block size) or on one wave
+// (NT = kWave, several searches per block).  In the wave form the wave's
+// lanes are the threads and the barriers are wave-level: LDS operations of a
+// wave complete in order, so waiting for them and keeping the compiler from
+// moving memory operations across the point is enough.
+template <int NT>
+__device__ __forceinline__ int32_t anchor_tid() {
+    return NT == kWave ? (int32_t)__lane_id() : (int32_t)threadIdx.x;
+}
+template <int NT>
+__device__ __forceinline__ void anchor_sync() {
+    if constexpr (NT == kWave) {
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+    } else {
+        __syncthreads();
+    }
+}
+
+// Exclusive prefix sum over the NT threads of a block (or the lanes of a
+// wave when NT = kWave); total receives the sum of all.  wsum: NT / kWave
+// int32 of LDS, reusable after the next barrier (unused for one wave).
 template <int NT>
 __device__ __forceinline__ int32_t block_exclusive_sum(int32_t v, int32_t *wsum, int32_t &total) {
     const int32_t incl = wave_prefix_sum(v);
+    if constexpr (NT == kWave) {
+        total = __shfl(incl, kWave - 1, kWave);
+        return incl - v;
+    }
     const int w = (int)threadIdx.x / kWave;
     if (__lane_id() == kWave - 1) wsum[w] = incl;
     __syncthreads();
@@ -370,6 +394,7 @@ __device__ void anchor_block_t(const int32_t *__restrict__ U, int32_t hU,
                                int32_t n, int32_t vtx, int32_t *__restrict__ Krow,
                                AnchorSmem<NT, CPT> &sm, int32_t *us, int32_t *ks) {
     constexpr int32_t CM = AnchorSmem<NT, CPT>::kCols;
+    const int32_t tid = anchor_tid<NT>();
     const int32_t INF = n + 1;
     const int32_t H = hU + hL + 1;
     int32_t P = 1;
@@ -378,16 +403,16 @@ __device__ void anchor_block_t(const int32_t *__restrict__ U, int32_t hU,
     int32_t *__restrict__ grow = G + (size_t)vtx * (size_t)H;
     int32_t *krow = kLds ? ks : Krow;
     const int32_t ldL = hL + 1;
-    if (threadIdx.x == 0) sm.ku = -1;
-    __syncthreads();
+    if (tid == 0) sm.ku = -1;
+    anchor_sync<NT>();
     // D_U row (non-decreasing in k) and KU
-    for (int32_t k = threadIdx.x; k <= hU; k += NT) {
+    for (int32_t k = tid; k <= hU; k += NT) {
         const int32_t x = umin(ld_cell(U, urow + (uint32_t)k), INF);
         const int32_t xn = (k < hU) ? umin(ld_cell(U, urow + (uint32_t)k + 1u), INF) : INF;
         if (kLds) us[k] = x;
         if (x <= n && xn > n) sm.ku = k;
     }
-    __syncthreads();
+    anchor_sync<NT>();
     const int32_t KU = sm.ku;
     for (int32_t S = P; S > 1;) {
         // fan-out: the f - 1 new columns of each interval scan about
@@ -404,7 +429,7 @@ __device__ void anchor_block_t(const int32_t *__restrict__ U, int32_t hU,
             int32_t tsum = 0;
 #pragma unroll
             for (int u = 0; u < CPT; ++u) {
-                const int32_t idx = (int32_t)threadIdx.x * CPT + u;
+                const int32_t idx = tid * CPT + u;
                 const int32_t t = seg + idx;
                 int32_t lo = 0;
                 r[u] = 0;
@@ -438,14 +463,14 @@ __device__ void anchor_block_t(const int32_t *__restrict__ U, int32_t hU,
             int32_t ex = block_exclusive_sum<NT>(tsum, sm.wsum, W);
 #pragma unroll
             for (int u = 0; u < CPT; ++u) {
-                sm.cps[threadIdx.x * CPT + u] = ex;
+                sm.cps[tid * CPT + u] = ex;
                 ex += r[u];
             }
-            if (threadIdx.x == 0) sm.cps[CM] = W;
-            __syncthreads();
+            if (tid == 0) sm.cps[CM] = W;
+            anchor_sync<NT>();
             // candidates e0 .. e1-1 of the flat list
             const int32_t C = (W + NT - 1) / NT;
-            const int32_t e0 = (int32_t)threadIdx.x * C;
+            const int32_t e0 = tid * C;
             const int32_t e1 = imin(e0 + C, W);
             if (e0 < e1) {
                 // the column holding e0: the last index with cps <= e0 (a
@@ -499,11 +524,11 @@ __device__ void anchor_block_t(const int32_t *__restrict__ U, int32_t hU,
                 }
                 atomicMin(&sm.key[rcol], run);
             }
-            __syncthreads();
+            anchor_sync<NT>();
 #pragma unroll
             for (int u = 0; u < CPT; ++u) {
                 if (r[u] > 0) {
-                    const int32_t idx = (int32_t)threadIdx.x * CPT + u;
+                    const int32_t idx = tid * CPT + u;
                     const int32_t c = (seg + idx + 1) * S2 - 1;
                     const unsigned long long key = sm.key[idx];
                     const uint32_t v = (uint32_t)(key >> 32);
@@ -516,13 +541,13 @@ __device__ void anchor_block_t(const int32_t *__restrict__ U, int32_t hU,
                     }
                 }
             }
-            __syncthreads();
+            anchor_sync<NT>();
         }
         S = S2;
     }
     if (kLds) {
-        for (int32_t c = threadIdx.x; c < H; c += NT) Krow[c] = ks[c];
-        __syncthreads();
+        for (int32_t c = tid; c < H; c += NT) Krow[c] = ks[c];
+        anchor_sync<NT>();
     }
 }
 

@@ -51,6 +51,32 @@ __global__ void __launch_bounds__(NT) k_anchor_lds(CombineArgs c) {
     }
 }
 
+// One anchor search per wave (levels with many short anchor rows): each wave
+// has its own slice of dynamic LDS (the search's AnchorSmem, then hc + 1 and
+// 2 hc + 1 int32, `bytes` in all) and no block barrier is used, so a wave
+// without an anchor simply exits.
+template <int CPT>
+__global__ void __launch_bounds__(kBlock) k_anchor_wave(CombineArgs c, int32_t bytes) {
+    extern __shared__ unsigned long long dyn[];
+    const int32_t wv = (int32_t)threadIdx.x / kWave;
+    const int32_t p = blockIdx.y, a = (int32_t)blockIdx.x * kWaves + wv;
+    if (a >= c.nanch) return;
+    const StripRef U = child_strip(c, 2 * p), L = child_strip(c, 2 * p + 1);
+    int32_t *G = parent_strip(c, p);
+    const int32_t vtx = anchor_vertex(a, c.tile, c.n);
+    int32_t *Krow = c.anch + ((size_t)p * c.nanch + a) * (size_t)c.hs;
+    unsigned long long *base = dyn + (size_t)wv * (size_t)(bytes / 8);
+    AnchorSmem<kWave, CPT> &sm = *reinterpret_cast<AnchorSmem<kWave, CPT> *>(base);
+    int32_t *us = reinterpret_cast<int32_t *>(base + sizeof(AnchorSmem<kWave, CPT>) / 8);
+    int32_t *ks = us + (c.hc + 1);
+    anchor_block_t<true, kWave, CPT>(U.d, U.h, L.d, L.h, G, c.n, vtx, Krow, sm, us, ks);
+    if (a == c.nanch - 1) {  // sentinel row n + 1
+        const int32_t H = U.h + L.h + 1;
+        int32_t *srow = G + (size_t)(c.n + 1) * H;
+        for (int32_t j = __lane_id(); j < H; j += kWave) srow[j] = c.n + 1;
+    }
+}
+
 // Anchor search with both rows in global memory (rows too long for LDS).
 template <int NT, int CPT>
 __global__ void __launch_bounds__(NT) k_anchor(CombineArgs c) {
@@ -259,6 +285,21 @@ hipError_t launch_anchor(const CombineArgs &c, int32_t npairs, hipStream_t s) {
     if (blocks <= 3 * cus) {
         if (try_anchor_lds<512, 4>(c, npairs, s, e)) return e;
         hipLaunchKernelGGL((k_anchor<512, 4>), dim3(c.nanch, npairs), dim3(512), 0, s, c);
+        return hipGetLastError();
+    }
+    // many short rows: one search per wave (measured: faster up to 512
+    // weights, slower at 1024, where the wave's smaller candidate budget per
+    // depth needs more depths)
+    if (c.hs <= 512) {
+        const int32_t per_wave = (int32_t)(((c.hs <= 256 ? sizeof(AnchorSmem<kWave, 4>)
+                                                         : sizeof(AnchorSmem<kWave, 8>)) +
+                                            4 * ((size_t)c.hc + 1 + (size_t)c.hs) + 7) & ~(size_t)7);
+        const dim3 grid((c.nanch + kWaves - 1) / kWaves, npairs);
+        const size_t bytes = (size_t)per_wave * kWaves;
+        if (c.hs <= 256)
+            hipLaunchKernelGGL((k_anchor_wave<4>), grid, dim3(kBlock), bytes, s, c, per_wave);
+        else
+            hipLaunchKernelGGL((k_anchor_wave<8>), grid, dim3(kBlock), bytes, s, c, per_wave);
         return hipGetLastError();
     }
     if (try_anchor_lds<kBlock, 4>(c, npairs, s, e)) return e;

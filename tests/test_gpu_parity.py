@@ -109,6 +109,30 @@ def test_base_table_window_and_fallback():
             _base_rows_check(a, b, plan, ws, verts)
 
 
+def test_many_short_anchor_rows():
+    """Levels with many anchors and rows of at most 1024 weights run one
+    anchor search per wave; 512 x 3000 with 16-row strips and tile 4 puts
+    more than 3 x 256 anchors on levels 1-4.  Every level's rows for sampled
+    vertices (anchors, their neighbours and tails) against the oracle."""
+    r = np.random.default_rng(777)
+    m, n = 512, 3000
+    a = r.integers(0, 4, m).astype(np.uint8)
+    b = r.integers(0, 4, n).astype(np.uint8)
+    Lg, plan, ws = check_against_oracle(a, b, 4, base_rows=16, tile=4)
+    verts = sorted(set(list(range(0, n + 1, 9)) + list(range(0, n + 1, 4)[::23]) + [1, 2, 3, n - 1, n]))
+    for lv, cnt in enumerate(plan.levels()):
+        if lv == 0 or lv > 4:
+            continue
+        for s_ in sorted({0, cnt // 2, cnt - 1}):
+            D, row0 = plan.dist(lv, s_, ws)
+            h = D.shape[1] - 1
+            got = D[verts].cpu().numpy()
+            want = oracle.dist_rows(a, row0, row0 + h, b, verts)
+            bad = np.argwhere(got != want)
+            assert bad.size == 0, "level %d strip %d: vertex %d weight %d got %d want %d" % (
+                lv, s_, verts[bad[0][0]], bad[0][1], got[tuple(bad[0])], want[tuple(bad[0])])
+
+
 def test_paper_grid_example():
     """Fig. 1 grid: rows tcaggatt, columns gatttatgcagg; breakouts of Section II-B-1."""
     a = np.frombuffer(b"tcaggatt", np.uint8) - ord("a")
