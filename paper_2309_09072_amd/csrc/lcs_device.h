@@ -609,7 +609,7 @@ struct BracketCfg {
     static constexpr int kUW = UW;
 };
 using BracketCfg32 = BracketCfg<int32_t, 32, 64>;
-using BracketCfg16 = BracketCfg<uint16_t, 64, 96>;
+using BracketCfg16 = BracketCfg<uint16_t, 64, 98>;
 
 template <class C>
 struct BracketSmemT {
@@ -620,6 +620,7 @@ struct BracketSmemT {
     St q[(kMaxTile / 2) * C::kJ];   // queued outputs of one level (slot * kJ + jj)
     unsigned long long key[kCoarseItems];  // slice minima (value, k) of a coarse level
     int32_t qn[2];                         // queue lengths, alternating between levels
+    int32_t xlast[kMaxTile];               // D_U(i0 + v, hU) for the strip's last weight
 };
 using BracketSmem = BracketSmemT<BracketCfg32>;
 
@@ -1012,6 +1013,24 @@ __device__ __forceinline__ void bracket_block(const int32_t *__restrict__ U, int
     const int32_t ldU = hU + 1, ldL = hL + 1;
     const int32_t js = imin(jn, S);  // weights solved by bisection
     const int32_t lane = __lane_id();
+    // Weight j0 + S = hU + hL (a block with jn = S + 1) has the single
+    // candidate k = hU.  Its D_U load travels with the tile-end loads (parked
+    // in LDS, which keeps it out of the registers) and its D_L load with the
+    // parallelogram copy, so it adds no round trip.
+    if ((jn > S) && threadIdx.x >= 1 && (int32_t)threadIdx.x < len)
+        sm.xlast[threadIdx.x] = (int32_t)umin(U[(size_t)(i0 + threadIdx.x) * ldU + hU], INF);
+    // Short upper strips (hU + len + 1 <= kUW): the LDS window holds whole
+    // D_U rows (origin k = 0), so its copy needs no tile end and travels with
+    // the tile-end loads.
+    constexpr int32_t UW = C::kUW;
+    const bool full = hU + len + 1 <= UW;
+    if (full) {
+        for (int32_t e = threadIdx.x; e < (len + 1) * UW; e += kBlock) {
+            const int32_t v = e / UW, c = e - v * UW;
+            const int32_t k = imin(imax(c - v, 0), hU);
+            sm.u[v * UW + c] = (typename C::St)umin(U[(size_t)(i0 + v) * ldU + k], INF);
+        }
+    }
     // Tile ends, in every wave: lane l holds k*(i0, j0 + l + 64 c) and
     // k*(i1, j0 + l + 64 c); wave 0 also stores them (and the ends' values)
     // in LDS.  Reachability from i0 is a prefix of the weights.
@@ -1048,36 +1067,32 @@ __device__ __forceinline__ void bracket_block(const int32_t *__restrict__ U, int
     }
     if (threadIdx.x < 2) sm.qn[threadIdx.x] = 0;
     if (threadIdx.x < kCoarseItems) sm.key[threadIdx.x] = ~0ull;
-    if (jn > S) {  // weight j0 + S = hU + hL: one candidate, k = hU
-        const int32_t j = j0 + S;
-        for (int32_t v = 1 + (int32_t)threadIdx.x; v < len; v += kBlock) {
-            const int32_t vert = i0 + v;
-            const int32_t x = umin(U[(size_t)vert * ldU + hU], INF);
-            G[(size_t)vert * H + j] = L[(size_t)x * ldL + (j - hU)];
-        }
-    }
     if (!live) {  // nothing reachable from i0: the whole block is unreachable
         for (int32_t e = threadIdx.x; e < (len - 1) * S; e += kBlock) {
             const int32_t t = 1 + e / S, jj = e - (t - 1) * S;
             if (jj < js) G[(size_t)(i0 + t) * H + j0 + jj] = INF;
         }
+        if ((jn > S) && threadIdx.x >= 1 && (int32_t)threadIdx.x < len)
+            G[(size_t)(i0 + threadIdx.x) * H + j0 + S] = L[(size_t)sm.xlast[threadIdx.x] * ldL + (j0 + S - hU)];
         __syncthreads();
         return;
     }
-    constexpr int32_t UW = C::kUW;
-    const bool lds_u = (kbl >= 0) && (kbl - ka0 + len + 1 <= UW);
-    if (lds_u) {  // copy the D_U parallelogram (all rows: an idle output reads row 0)
+    const bool lds_u = full || ((kbl >= 0) && (kbl - ka0 + len + 1 <= UW));
+    const int32_t ubase = full ? 0 : ka0;
+    if (lds_u && !full) {  // copy the D_U parallelogram (all rows: an idle output reads row 0)
         for (int32_t e = threadIdx.x; e < (len + 1) * UW; e += kBlock) {
             const int32_t v = e / UW, c = e - v * UW;
             const int32_t k = imin(imax(ka0 - v + c, 0), hU);
             sm.u[v * UW + c] = (typename C::St)umin(U[(size_t)(i0 + v) * ldU + k], INF);
         }
     }
+    if ((jn > S) && threadIdx.x >= 1 && (int32_t)threadIdx.x < len)
+        G[(size_t)(i0 + threadIdx.x) * H + j0 + S] = L[(size_t)sm.xlast[threadIdx.x] * ldL + (j0 + S - hU)];
     __syncthreads();
     if (lds_u)
-        bracket_levels<C, true, kCoop>(sm, U, hU, L, hL, G, n, i0, len, j0, js, ka0);
+        bracket_levels<C, true, kCoop>(sm, U, hU, L, hL, G, n, i0, len, j0, js, ubase);
     else
-        bracket_levels<C, false, kCoop>(sm, U, hU, L, hL, G, n, i0, len, j0, js, ka0);
+        bracket_levels<C, false, kCoop>(sm, U, hU, L, hL, G, n, i0, len, j0, js, ubase);
     __syncthreads();
 }
 
