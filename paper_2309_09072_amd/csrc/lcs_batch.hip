@@ -313,6 +313,7 @@ __global__ void __launch_bounds__(kBlock) k_pair_queue(BatchArgs A, const int32_
 // first[j] <= t < first[j + 1] (binary search).
 struct StageArgs {
     int32_t kind, level, npairs;
+    int32_t jchunk;         // weights per bracket task (the bracket shape's kJ)
     const int32_t *pair;    // participating pairs
     const int64_t *first;   // their first item, plus the total at [npairs]
 };
@@ -338,6 +339,90 @@ __global__ void __launch_bounds__(kBlock) k_stage(BatchArgs A, StageArgs S) {
     }
     __syncthreads();
     exec_task<H0>(A, A.ws + A.pairs[s_pu[0]].ws_off, s_pu[0], KIND, S.level, s_pu[1], sm);
+}
+
+// Staged base-strip tasks (one strip x one 256-vertex block each) with the
+// next-match table window in LDS, as in the single-pair path.
+template <int H0>
+__global__ void __launch_bounds__(kBlock) k_stage_base(BatchArgs A, StageArgs S) {
+    __shared__ int32_t lds[kWave * (H0 + 1)];
+    __shared__ uint16_t tab[kBaseTab];
+    __shared__ int32_t s_pu[2];
+    const int64_t t = blockIdx.x;
+    if (threadIdx.x == 0) {
+        int32_t lo = 0, hi = S.npairs - 1;
+        while (lo < hi) {
+            const int32_t mid = (lo + hi + 1) >> 1;
+            if (S.first[mid] <= t)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        s_pu[0] = S.pair[lo];
+        s_pu[1] = (int32_t)(t - S.first[lo]);
+    }
+    __syncthreads();
+    const int32_t p = s_pu[0], u = s_pu[1];
+    const PairRec &P = A.pairs[p];
+    uint8_t *ws = A.ws + P.ws_off;
+    int32_t *hdr = reinterpret_cast<int32_t *>(ws + P.off_hdr);
+    const int32_t *nm = reinterpret_cast<const int32_t *>(ws + P.off_nm);
+    const uint8_t *a = A.symbols + P.a_off;
+    const LevelGeom &g = P.lev[0];
+    const int32_t nvb = vertex_blocks(P.n);
+    const int32_t s0 = u / nvb;
+    const bool last = (s0 == g.nstrips - 1);
+    const int32_t h = last ? g.hlast : H0;
+    int32_t *out = reinterpret_cast<int32_t *>(ws + (last ? g.last_off : g.base)) +
+                   (last ? 0 : (size_t)s0 * strip_elems(P.n, H0));
+    const int32_t vb = u - s0 * nvb;
+    base_strip_block<H0, true>(a + (size_t)s0 * H0, h, P.n, A.sigma, nm, out, vb * kBlock, hdr, lds,
+                               tab);
+}
+
+// Staged bracket tasks (one tile x one weight chunk each) in the bracket shape
+// C: the 16-bit one (64 weights per task) when every pair of the plan fits
+// 16-bit values, as in the single-pair path, with the same 64-VGPR limit.
+template <int H0, class C>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8)))
+k_stage_bracket(BatchArgs A, StageArgs S) {
+    __shared__ BracketSmemT<C> sm;
+    __shared__ int32_t s_pu[2];
+    const int64_t t = blockIdx.x;
+    if (threadIdx.x == 0) {
+        int32_t lo = 0, hi = S.npairs - 1;
+        while (lo < hi) {
+            const int32_t mid = (lo + hi + 1) >> 1;
+            if (S.first[mid] <= t)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        s_pu[0] = S.pair[lo];
+        s_pu[1] = (int32_t)(t - S.first[lo]);
+    }
+    __syncthreads();
+    const int32_t p = s_pu[0], u = s_pu[1];
+    const PairRec &P = A.pairs[p];
+    uint8_t *ws = A.ws + P.ws_off;
+    const CombineArgs c = pair_combine_args(P, ws, S.level, A.tile);
+    const int32_t ntile = P.nanch - 1;
+    const int32_t Hf = 2 * P.lev[S.level - 1].hfull + 1;  // weights of a full-height parent
+    const int32_t nchl = imax(1, (Hf - 1 + C::kJ - 1) / C::kJ);
+    const int32_t qt = u / nchl;
+    const int32_t q = qt / ntile, tl = qt - q * ntile, ch = u - qt * nchl;
+    const StripRef U = child_strip(c, 2 * q), L = child_strip(c, 2 * q + 1);
+    int32_t *G = parent_strip(c, q);
+    const int32_t H = U.h + L.h + 1;
+    const int32_t nch = imax(1, (H - 1 + C::kJ - 1) / C::kJ);
+    if (ch >= nch) return;
+    const int32_t i0 = tl * A.tile;
+    const int32_t len = imin(A.tile, P.n - i0);
+    const int32_t *Ka = c.anch + ((size_t)q * c.nanch + tl) * (size_t)c.hs;
+    const int32_t *Kb = c.anch + ((size_t)q * c.nanch + tl + 1) * (size_t)c.hs;
+    const int32_t j0 = ch * C::kJ;
+    const int32_t jn = (ch == nch - 1) ? H - j0 : C::kJ;
+    bracket_block<C>(U.d, U.h, L.d, L.h, G, P.n, i0, len, j0, jn, Ka, Kb, sm);
 }
 
 // Staged anchor search with the vertex's D_U row and k* row in dynamic LDS
@@ -380,6 +465,45 @@ __global__ void __launch_bounds__(kBlock) k_stage_anchor_lds(BatchArgs A, StageA
     }
 }
 
+// Staged anchor searches, one per wave, for short rows (hs = 2 hc + 1 <= 512
+// weights): each wave finds its own task and has its own slice of dynamic
+// LDS (`bytes`: the search's AnchorSmem, then hc + 1 and 2 hc + 1 int32); no
+// block barrier is used, so a wave without a task simply exits.
+template <int CPT>
+__global__ void __launch_bounds__(kBlock) k_stage_anchor_wave(BatchArgs A, StageArgs S, int32_t hc,
+                                                              int32_t bytes, int64_t items) {
+    extern __shared__ unsigned long long dyn[];
+    const int32_t wv = (int32_t)threadIdx.x / kWave;
+    const int64_t t = (int64_t)blockIdx.x * kWaves + wv;
+    if (t >= items) return;
+    int32_t lo = 0, hi = S.npairs - 1;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (S.first[mid] <= t)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const int32_t p = S.pair[lo], u = (int32_t)(t - S.first[lo]);
+    const PairRec &P = A.pairs[p];
+    uint8_t *ws = A.ws + P.ws_off;
+    const CombineArgs c = pair_combine_args(P, ws, S.level, A.tile);
+    const int32_t q = u / P.nanch, an = u - q * P.nanch;
+    const StripRef U = child_strip(c, 2 * q), L = child_strip(c, 2 * q + 1);
+    int32_t *G = parent_strip(c, q);
+    unsigned long long *base = dyn + (size_t)wv * (size_t)(bytes / 8);
+    AnchorSmem<kWave, CPT> &sm = *reinterpret_cast<AnchorSmem<kWave, CPT> *>(base);
+    int32_t *us = reinterpret_cast<int32_t *>(base + sizeof(AnchorSmem<kWave, CPT>) / 8);
+    int32_t *ks = us + (hc + 1);
+    anchor_block_t<true, kWave, CPT>(U.d, U.h, L.d, L.h, G, P.n, anchor_vertex(an, A.tile, P.n),
+                                     c.anch + ((size_t)q * c.nanch + an) * (size_t)c.hs, sm, us, ks);
+    if (an == c.nanch - 1) {
+        const int32_t H = U.h + L.h + 1;
+        int32_t *srow = G + (size_t)(P.n + 1) * H;
+        for (int32_t j = __lane_id(); j < H; j += kWave) srow[j] = P.n + 1;
+    }
+}
+
 // dynamic LDS a staged anchor search may take: what one work-group of gfx950
 // can hold (160 KB) minus room for the kernel's static LDS
 constexpr size_t kStageMaxLds = 159 * 1024;
@@ -406,6 +530,22 @@ template <int H0>
 static hipError_t launch_stage(const BatchArgs &A, const StageArgs &S, dim3 grid, hipStream_t st) {
     if (S.kind == ST_ANCHOR && S.level >= 1 && S.level < kMaxLev) {
         const int32_t hc = H0 << (S.level - 1);
+        const int32_t hs = 2 * hc + 1;
+        if (hs <= 512) {  // short rows: one search per wave
+            const int32_t per_wave = (int32_t)(((hs <= 256 ? sizeof(AnchorSmem<kWave, 4>)
+                                                           : sizeof(AnchorSmem<kWave, 8>)) +
+                                                4 * ((size_t)hc + 1 + (size_t)hs) + 7) & ~(size_t)7);
+            const int64_t items = grid.x;
+            const dim3 g((unsigned)((items + kWaves - 1) / kWaves));
+            const size_t bytes = (size_t)per_wave * kWaves;
+            if (hs <= 256)
+                hipLaunchKernelGGL((k_stage_anchor_wave<4>), g, dim3(kBlock), bytes, st, A, S, hc,
+                                   per_wave, items);
+            else
+                hipLaunchKernelGGL((k_stage_anchor_wave<8>), g, dim3(kBlock), bytes, st, A, S, hc,
+                                   per_wave, items);
+            return hipGetLastError();
+        }
         const size_t bytes = sizeof(AnchorSmemBlock) + 4 * ((size_t)hc + 1 + 2 * (size_t)hc + 1);
         if (bytes <= kStageMaxLds) {
             const hipError_t e = opt_in_stage_lds();
@@ -417,9 +557,14 @@ static hipError_t launch_stage(const BatchArgs &A, const StageArgs &S, dim3 grid
     switch (S.kind) {
         case ST_EMPTY: hipLaunchKernelGGL((k_stage<H0, ST_EMPTY>), grid, dim3(kBlock), 0, st, A, S); break;
         case ST_NM_SYM: hipLaunchKernelGGL((k_stage<H0, ST_NM_SYM>), grid, dim3(kBlock), 0, st, A, S); break;
-        case ST_BASE_BLK: hipLaunchKernelGGL((k_stage<H0, ST_BASE_BLK>), grid, dim3(kBlock), 0, st, A, S); break;
+        case ST_BASE_BLK: hipLaunchKernelGGL((k_stage_base<H0>), grid, dim3(kBlock), 0, st, A, S); break;
         case ST_ANCHOR: hipLaunchKernelGGL((k_stage<H0, ST_ANCHOR>), grid, dim3(kBlock), 0, st, A, S); break;
-        case ST_BRACKET_CH: hipLaunchKernelGGL((k_stage<H0, ST_BRACKET_CH>), grid, dim3(kBlock), 0, st, A, S); break;
+        case ST_BRACKET_CH:
+            if (S.jchunk == BracketCfg16::kJ)
+                hipLaunchKernelGGL((k_stage_bracket<H0, BracketCfg16>), grid, dim3(kBlock), 0, st, A, S);
+            else
+                hipLaunchKernelGGL((k_stage_bracket<H0, BracketCfg32>), grid, dim3(kBlock), 0, st, A, S);
+            break;
         case ST_LENGTH: hipLaunchKernelGGL((k_stage<H0, ST_LENGTH>), grid, dim3(kBlock), 0, st, A, S); break;
         case ST_SPLIT: hipLaunchKernelGGL((k_stage<H0, ST_SPLIT>), grid, dim3(kBlock), 0, st, A, S); break;
         case ST_LEAF: hipLaunchKernelGGL((k_stage<H0, ST_LEAF>), grid, dim3(kBlock), 0, st, A, S); break;
@@ -457,6 +602,13 @@ struct lcs_batch_s {
     int64_t off_stage = 0, stage_bytes = 0;
     uint8_t *host_stage = nullptr;  // pinned staging of the staged-mode item tables
 };
+
+// Weights per staged bracket task: the 16-bit bracket shape when every value
+// of every pair of the plan fits in 16 bits (n + 1 <= 65535; strip heights
+// are at most max_len), else the 32-bit one.
+static int32_t stage_jchunk(int32_t max_len) {
+    return (max_len + 1 <= 65535) ? BracketCfg16::kJ : BracketCfg32::kJ;
+}
 
 static int32_t counters_per_pair(int32_t max_len, int32_t h0) {
     // 2 + 3 * sum over levels of the strip count
@@ -761,6 +913,7 @@ extern "C" int32_t lcs_batch_submit(lcs_batch_t B, const lcs_pair_desc *pairs, i
                 launches.push_back(sl);
             };
             const int32_t sig = B->d.alphabet;
+            const int32_t sjc = stage_jchunk(B->d.max_len);
             add_stage(ST_EMPTY, 0, [](const PairRec &R) -> int64_t { return R.nlev == 0 ? 1 : 0; });
             add_stage(ST_NM_SYM, 0, [sig](const PairRec &R) -> int64_t { return R.nlev ? sig : 0; });
             add_stage(ST_BASE_BLK, 0, [](const PairRec &R) -> int64_t {
@@ -770,10 +923,10 @@ extern "C" int32_t lcs_batch_submit(lcs_batch_t B, const lcs_pair_desc *pairs, i
                 add_stage(ST_ANCHOR, l, [l](const PairRec &R) -> int64_t {
                     return R.nlev > l ? (int64_t)R.lev[l].npairs * R.nanch : 0;
                 });
-                add_stage(ST_BRACKET_CH, l, [l](const PairRec &R) -> int64_t {
+                add_stage(ST_BRACKET_CH, l, [l, sjc](const PairRec &R) -> int64_t {
                     if (R.nlev <= l) return 0;
                     const int32_t H = 2 * R.lev[l - 1].hfull + 1;
-                    const int32_t nch = std::max(1, (H - 1 + kJChunk - 1) / kJChunk);
+                    const int32_t nch = std::max(1, (H - 1 + sjc - 1) / sjc);
                     return (int64_t)R.lev[l].npairs * (R.nanch - 1) * nch;
                 });
             }
@@ -828,6 +981,7 @@ extern "C" int32_t lcs_batch_submit(lcs_batch_t B, const lcs_pair_desc *pairs, i
                 S.kind = sl.kind;
                 S.level = sl.level;
                 S.npairs = sl.npairs;
+                S.jchunk = stage_jchunk(B->d.max_len);
                 S.pair = reinterpret_cast<const int32_t *>(ws + B->off_stage + sl.pair_off);
                 S.first = reinterpret_cast<const int64_t *>(ws + B->off_stage + sl.first_off);
                 if (sl.items >= (int64_t)1 << 31) return LCS_E_TOO_BIG;
