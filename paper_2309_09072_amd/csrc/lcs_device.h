@@ -597,6 +597,7 @@ __device__ __forceinline__ void anchor_block(const int32_t *__restrict__ U, int3
 // bisection works on at most kJ weights.
 constexpr int kCoarseItems = kBlock / 2;  // a level with at most this many outputs is coarse
 constexpr int32_t kCoopPass2MinH = 1024;  // child strip height from which pass 2 is cooperative
+constexpr int32_t kWideWindowMinH = 2048;  // child strip height from which the D_U window is wide
 // Shape of a bracket work-group: LDS state type, weights per block, width of
 // the D_U parallelogram.  32-bit state: any size.  16-bit state (values and
 // indices stored in 16 bits, k* stored as k* + 1 so that -1 is 0): needs
@@ -610,6 +611,7 @@ struct BracketCfg {
 };
 using BracketCfg32 = BracketCfg<int32_t, 32, 64>;
 using BracketCfg16 = BracketCfg<uint16_t, 64, 98>;
+using BracketCfg16Wide = BracketCfg<uint16_t, 64, 160>;  // tall strips: wider D_U window
 
 template <class C>
 struct BracketSmemT {

@@ -309,11 +309,18 @@ hipError_t launch_anchor(const CombineArgs &c, int32_t npairs, hipStream_t s) {
 
 // bracket shape of the 16-bit state
 using NarrowBracket = BracketCfg16;
-template <class C>
+template <class C, class Wide>
 static void launch_bracket_cfg(const CombineArgs &c, dim3 grid, hipStream_t s) {
-    // the cooperative pass 2 is compiled only into the kernels for tall
-    // strips, so that the others keep their register allocation
-    if (c.hc >= kCoopPass2MinH)
+    // The cooperative pass 2 is compiled only into the kernels for tall
+    // strips, so that the others keep their register allocation.  Strips of
+    // kWideWindowMinH rows and more take the shape with the wider D_U window:
+    // there k* moves further across a block (measured at 4096² and 16384²:
+    // with the narrow window 27% of the top level's live blocks read D_U from
+    // global memory, two round trips per batch), which is worth one
+    // work-group per CU less.
+    if (c.hc >= kWideWindowMinH)
+        hipLaunchKernelGGL((k_bracket<Wide, true>), grid, dim3(kBlock), 0, s, c);
+    else if (c.hc >= kCoopPass2MinH)
         hipLaunchKernelGGL((k_bracket<C, true>), grid, dim3(kBlock), 0, s, c);
     else
         hipLaunchKernelGGL((k_bracket<C, false>), grid, dim3(kBlock), 0, s, c);
@@ -329,9 +336,9 @@ hipError_t launch_bracket(const CombineArgs &c0, int32_t npairs, hipStream_t s) 
     c.nchunks = imax(1, (c.hs - 1 + c.jchunk - 1) / c.jchunk);  // hs = 2 hc + 1 weights
     const dim3 grid(ntiles * c.nchunks, npairs);
     if (narrow)
-        launch_bracket_cfg<NarrowBracket>(c, grid, s);
+        launch_bracket_cfg<NarrowBracket, BracketCfg16Wide>(c, grid, s);
     else
-        launch_bracket_cfg<BracketCfg32>(c, grid, s);
+        launch_bracket_cfg<BracketCfg32, BracketCfg32>(c, grid, s);
     return hipGetLastError();
 }
 
