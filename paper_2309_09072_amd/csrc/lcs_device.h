@@ -611,6 +611,7 @@ struct BracketCfg {
 };
 using BracketCfg32 = BracketCfg<int32_t, 32, 64>;
 using BracketCfg16 = BracketCfg<uint16_t, 64, 98>;
+using BracketCfg16Mid = BracketCfg<uint16_t, 64, 128>;    // 1024+ rows: still 8 work-groups per CU
 using BracketCfg16Wide = BracketCfg<uint16_t, 64, 160>;  // tall strips: wider D_U window
 
 template <class C>

@@ -309,7 +309,7 @@ hipError_t launch_anchor(const CombineArgs &c, int32_t npairs, hipStream_t s) {
 
 // bracket shape of the 16-bit state
 using NarrowBracket = BracketCfg16;
-template <class C, class Wide>
+template <class C, class Mid, class Wide>
 static void launch_bracket_cfg(const CombineArgs &c, dim3 grid, hipStream_t s) {
     // The cooperative pass 2 is compiled only into the kernels for tall
     // strips, so that the others keep their register allocation.  Strips of
@@ -321,7 +321,7 @@ static void launch_bracket_cfg(const CombineArgs &c, dim3 grid, hipStream_t s) {
     if (c.hc >= kWideWindowMinH)
         hipLaunchKernelGGL((k_bracket<Wide, true>), grid, dim3(kBlock), 0, s, c);
     else if (c.hc >= kCoopPass2MinH)
-        hipLaunchKernelGGL((k_bracket<C, true>), grid, dim3(kBlock), 0, s, c);
+        hipLaunchKernelGGL((k_bracket<Mid, true>), grid, dim3(kBlock), 0, s, c);
     else
         hipLaunchKernelGGL((k_bracket<C, false>), grid, dim3(kBlock), 0, s, c);
 }
@@ -336,9 +336,9 @@ hipError_t launch_bracket(const CombineArgs &c0, int32_t npairs, hipStream_t s) 
     c.nchunks = imax(1, (c.hs - 1 + c.jchunk - 1) / c.jchunk);  // hs = 2 hc + 1 weights
     const dim3 grid(ntiles * c.nchunks, npairs);
     if (narrow)
-        launch_bracket_cfg<NarrowBracket, BracketCfg16Wide>(c, grid, s);
+        launch_bracket_cfg<NarrowBracket, BracketCfg16Mid, BracketCfg16Wide>(c, grid, s);
     else
-        launch_bracket_cfg<BracketCfg32, BracketCfg32>(c, grid, s);
+        launch_bracket_cfg<BracketCfg32, BracketCfg32, BracketCfg32>(c, grid, s);
     return hipGetLastError();
 }
 
