@@ -192,11 +192,20 @@ int32_t enqueue_trace(const Layout &L, uint8_t *ws, const uint8_t *a, int32_t *a
     if (L.lev.empty()) return LCS_OK;
     int32_t *hdr = reinterpret_cast<int32_t *>(ws + L.off_hdr);
     int32_t *nm = reinterpret_cast<int32_t *>(ws + L.off_nm);
-    for (size_t l = L.lev.size() - 1; l >= 1; --l) {
-        R.begin(LCS_PHASE_TRACE_SPLIT, (int32_t)l, 8 * (int64_t)L.lev[l].nstrips * (L.lev[l - 1].hfull + 1));
-        hipError_t e = launch_trace_split(combine_args(L, ws, l), L.lev[l].nstrips,
-                                          reinterpret_cast<const int4 *>(ws + L.node_off[l]),
-                                          reinterpret_cast<int4 *>(ws + L.node_off[l - 1]), hdr, s);
+    const size_t top = L.lev.size() - 1;
+    if (top >= 1) {
+        if (top >= (size_t)kTraceMaxLev) return LCS_E_TOO_BIG;
+        TraceSplitArgs t{};
+        int64_t bytes = 0;
+        for (size_t l = 1; l <= top; ++l) {
+            t.lev[l] = combine_args(L, ws, l);
+            bytes += 8 * (int64_t)L.lev[l].nstrips * (L.lev[l - 1].hfull + 1);
+        }
+        for (size_t l = 0; l <= top; ++l) t.node[l] = reinterpret_cast<int4 *>(ws + L.node_off[l]);
+        t.top = (int32_t)top;
+        t.err = hdr;
+        R.begin(LCS_PHASE_TRACE_SPLIT, (int32_t)top, bytes);
+        hipError_t e = launch_trace_splits(t, s);
         R.end();
         if (e != hipSuccess) return LCS_E_HIP;
     }

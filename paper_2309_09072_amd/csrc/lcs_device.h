@@ -1223,20 +1223,83 @@ __device__ void trace_leaf_block(const uint8_t *__restrict__ arow, int32_t h, in
                                  int32_t sigma, const int32_t *__restrict__ nm, int4 node,
                                  int32_t row0, int32_t *__restrict__ a_idx,
                                  int32_t *__restrict__ b_idx, int32_t wcap, int32_t *err,
-                                 int32_t *lds, int32_t *cand = nullptr, int32_t *tab = nullptr,
-                                 int32_t tabcap = 0) {
+                                 int32_t *lds, int32_t *tab = nullptr, int32_t tabcap = 0) {
     const int32_t INF = n + 1;
     const int32_t s = umin(node.x, n);
     const int32_t S = H0 + 1;
     const int32_t tid = threadIdx.x;
-    // kFast: columns s .. s+W-1 of every symbol's next-match table in LDS
-    // (lookups at or past column s + W read the global table), and every
-    // row's match candidates kept for the backward walk, which then reads
-    // LDS only.
-    const int32_t W = kFast ? imin(n + 2 - s, tabcap / imax(sigma, 1)) : 0;
-    if (kFast) {
-        for (int32_t x = 0; x < sigma; ++x)
-            for (int32_t c = tid; c < W; c += kBlock) tab[x * W + c] = nm[(size_t)x * (n + 2) + (size_t)(s + c)];
+    if constexpr (kFast) {
+        // One wave (blockDim = kWave); lane l owns column l + 1 of the row
+        // vector D_r(s, .), in a register; column 0 is s.  Columns
+        // s .. s+W-1 of every symbol's next-match table are in LDS (lookups
+        // at or past s + W read the global table).  Appending row r: the
+        // column to the left comes from the neighbouring lane, the candidate
+        // from the table, and the lanes where the candidate gives the new
+        // value form the row's match mask (a ballot), kept by lane r.  The
+        // walk back (Section II-C, the smaller upper weight first) then only
+        // needs those masks: at row r with weight w it takes the match when
+        // bit w - 1 of the mask is set, and the matched rows are written out
+        // by their lanes afterwards, with D_r(s, w) read from LDS.
+        static_assert(H0 <= kWave, "one lane per column");
+        // the row matches of one source lie about H0 * sigma columns past it
+        const int32_t W = imin(imin(n + 2 - s, tabcap / imax(sigma, 1)), 8 * H0);
+        for (int32_t x = 0; x < sigma; ++x) {
+            const int32_t *src = nm + (size_t)x * (n + 2) + s;
+            int32_t *dst = tab + x * W;
+            for (int32_t c0 = 0; c0 < W; c0 += 8 * kWave) {
+                int32_t v[8];
+#pragma unroll
+                for (int t = 0; t < 8; ++t) v[t] = src[imin(c0 + t * kWave + tid, W - 1)];
+#pragma unroll
+                for (int t = 0; t < 8; ++t)
+                    if (c0 + t * kWave + tid < W) dst[c0 + t * kWave + tid] = v[t];
+            }
+        }
+        const int32_t xrow = (tid < h) ? (int32_t)arow[tid] : 0;  // row symbols, one per lane
+        const int32_t j = tid + 1;
+        int32_t d = INF;                      // D_r(s, j)
+        uint32_t mlo = 0, mhi = 0;            // lane r: match mask of row r + 1
+        __syncthreads();                      // table in LDS
+        for (int32_t r = 0; r < h; ++r) {
+            const int32_t x = __builtin_amdgcn_readlane(xrow, r);
+            // D_r(s, j - 1): lane l - 1's value by a whole-wave DPP shift
+            // (wave_shr:1); lane 0 keeps `s`, column 0
+            const int32_t p = __builtin_amdgcn_update_dpp(s, d, 0x138, 0xF, 0xF, false);
+            int32_t cd = INF;
+            if (x < sigma && p <= n) cd = (p - s < W) ? tab[x * W + (p - s)] : nm[(size_t)x * (n + 2) + p];
+            const int32_t dn = umin(d, cd);
+            const bool hit = (j <= h) && (x < sigma) && (p <= n) && (cd == dn);
+            const unsigned long long mk = __ballot(hit);
+            if (tid == r) {
+                mlo = (uint32_t)mk;
+                mhi = (uint32_t)(mk >> 32);
+            }
+            d = (j <= h) ? dn : INF;
+            if (j <= h) lds[(r + 1) * S + j] = d;
+        }
+        // walk: uniform over the wave; lane w - 1 notes the row that matched
+        // weight w
+        const int32_t w0 = imin(imax(node.y, 0), h);
+        const int32_t off = imax(node.w, 0);
+        int32_t w = w0, mrow = 0;
+        for (int32_t r = h; r >= 1 && w >= 1; --r) {
+            const uint32_t lo = __builtin_amdgcn_readlane(mlo, r - 1);
+            const uint32_t hi = __builtin_amdgcn_readlane(mhi, r - 1);
+            const unsigned long long mk = ((unsigned long long)hi << 32) | lo;
+            if ((mk >> (w - 1)) & 1ull) {
+                if (tid == w - 1) mrow = r;
+                --w;
+            }
+        }
+        __syncthreads();  // LDS rows written above are read by other lanes
+        const int32_t dend = (w0 >= 1) ? lds[h * S + w0] : s;
+        if (tid == 0 && (w != 0 || dend != node.z)) atomicOr(err, kErrTrace);
+        if (w == 0 && j <= w0 && mrow >= 1 && off + j <= wcap) {
+            a_idx[off + j - 1] = row0 + mrow - 1;
+            b_idx[off + j - 1] = lds[mrow * S + j] - 1;
+        }
+        __syncthreads();
+        return;
     }
     if (tid <= h) lds[tid] = (tid == 0) ? s : INF;
     __syncthreads();
@@ -1244,17 +1307,8 @@ __device__ void trace_leaf_block(const uint8_t *__restrict__ arow, int32_t h, in
         const int32_t x = arow[r];
         if (tid <= h) {
             int32_t d = lds[r * S + tid];
-            int32_t cd = INF;
-            if (tid >= 1 && x < sigma) {
-                const int32_t p = lds[r * S + tid - 1];
-                if (kFast && p - s < W)
-                    cd = tab[x * W + (p - s)];
-                else
-                    cd = nm[(size_t)x * (n + 2) + p];
-                d = umin(d, cd);
-            }
+            if (tid >= 1 && x < sigma) d = umin(d, nm[(size_t)x * (n + 2) + lds[r * S + tid - 1]]);
             lds[(r + 1) * S + tid] = d;
-            if (kFast) cand[(r + 1) * S + tid] = cd;
         }
         __syncthreads();
     }
@@ -1265,8 +1319,7 @@ __device__ void trace_leaf_block(const uint8_t *__restrict__ arow, int32_t h, in
             const int32_t x = arow[r - 1];
             if (w >= 1 && x < sigma) {
                 const int32_t p = lds[(r - 1) * S + (w - 1)];
-                const int32_t cd = kFast ? cand[r * S + w] : (p <= n ? nm[(size_t)x * (n + 2) + p] : INF);
-                if (p <= n && cd == e) {
+                if (p <= n && nm[(size_t)x * (n + 2) + p] == e) {
                     if (off + w <= wcap) {
                         a_idx[off + w - 1] = row0 + r - 1;
                         b_idx[off + w - 1] = e - 1;

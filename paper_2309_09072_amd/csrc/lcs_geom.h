@@ -52,6 +52,16 @@ struct CombineArgs {
     int32_t nchunks;       // bracket blocks along the weights of the widest pair
 };
 
+// Every split level of a witness trace, for one launch (levels 1..top).
+constexpr int kTraceMaxLev = 32;  // more than any layout has (fewer than 2^30 cells per matrix)
+struct TraceSplitArgs {
+    CombineArgs lev[kTraceMaxLev];  // lev[l]: the combine of level l
+    int4 *node[kTraceMaxLev];       // node[l]: trace nodes of level l (one per strip)
+    int32_t top;                    // top level
+    int32_t *err;
+};
+static_assert(sizeof(TraceSplitArgs) <= 4096, "kernel arguments are limited to 4 KB");
+
 struct StripRef {
     const int32_t *d;
     int32_t h;

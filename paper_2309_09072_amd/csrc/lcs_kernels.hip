@@ -122,34 +122,112 @@ __global__ void __launch_bounds__(kBlock) k_length(const int32_t *top, int32_t m
     length_block(top, m, n, hdr, root, lds);
 }
 
-__global__ void __launch_bounds__(kBlock) k_trace_split(CombineArgs c, const int4 *nodes_in,
-                                                        int4 *nodes_out, int32_t *err) {
-    __shared__ int32_t lds[1];
-    const int32_t p = blockIdx.x;
-    const int4 node = nodes_in[p];
-    if (2 * p + 1 >= c.nc) {  // carried-up strip: same node one level down
-        if (threadIdx.x == 0) nodes_out[2 * p] = node;
-        return;
+// Every split level of the trace in one work-group (Section II-C: the
+// cross column of the node's combine, the smallest k with
+// D_L(D_U(s, k), w - k) == e).  Level by level from the top, each parent node
+// gets g threads; each thread takes every g-th k of the node's range, R at a
+// time with the D_U loads, then the D_L loads, all in flight, and stops at its
+// first hit; the hits meet in an LDS minimum.  A level's children are read by
+// the next level after a barrier of the same work-group, so one launch
+// replaces one launch per level; the nodes of the inner levels stay in LDS
+// (up to kSplitNodes per level; only level 0's go to memory, for the leaves).
+constexpr int32_t kSplitThreads = 1024;
+constexpr int32_t kSplitNodes = 1024;
+__global__ void __launch_bounds__(kSplitThreads) k_trace_splits(TraceSplitArgs A) {
+    constexpr int32_t R = 4;
+    __shared__ int32_t found[kSplitThreads];
+    __shared__ int4 nbuf[2][kSplitNodes];
+    const int32_t tid = threadIdx.x;
+    bool in_lds = false;  // this level's nodes are in nbuf[cur]
+    int32_t cur = 0;
+    for (int32_t l = A.top; l >= 1; --l) {
+        const CombineArgs &c = A.lev[l];
+        const bool out_lds = l > 1 && c.nc <= kSplitNodes;
+        const int4 *nin = in_lds ? nbuf[cur] : A.node[l];
+        int4 *nout = out_lds ? nbuf[cur ^ 1] : A.node[l - 1];
+        const int32_t np = c.np, n = c.n;
+        int32_t g = kSplitThreads;  // threads per node (power of two)
+        while (g > 1 && (int64_t)g * np > kSplitThreads) g >>= 1;
+        const int32_t per = kSplitThreads / g;
+        for (int32_t b0 = 0; b0 < np; b0 += per) {
+            const int32_t pl = tid / g, sub = tid - pl * g, p = b0 + pl;
+            if (sub == 0) found[pl] = 0x7fffffff;
+            __syncthreads();
+            int4 node = make_int4(0, 0, 0, 0);
+            bool split = false;
+            int32_t s = 0, w = 0, e = 0;
+            const int32_t *urow = nullptr;
+            StripRef U{}, L{};
+            if (p < np) {
+                node = nin[p];
+                if (2 * p + 1 < c.nc) {
+                    split = true;
+                    U = child_strip(c, 2 * p);
+                    L = child_strip(c, 2 * p + 1);
+                    s = umin(node.x, n);
+                    w = node.y;
+                    e = node.z;
+                    urow = U.d + (size_t)s * (U.h + 1);
+                    const int32_t lo = imax(0, w - L.h), hi = imin(w, U.h);
+                    const int32_t ldL = L.h + 1;
+                    bool hit = false;
+                    for (int32_t kb = lo + sub; kb <= hi && !hit; kb += g * R) {
+                        int32_t xs[R], vs[R];
+#pragma unroll
+                        for (int t = 0; t < R; ++t) xs[t] = urow[imin(kb + t * g, hi)];
+#pragma unroll
+                        for (int t = 0; t < R; ++t) {
+                            const int32_t k = imin(kb + t * g, hi);
+                            vs[t] = ((uint32_t)xs[t] <= (uint32_t)n) ? L.d[(size_t)xs[t] * ldL + (w - k)] : -1;
+                        }
+#pragma unroll
+                        for (int t = 0; t < R; ++t) {
+                            const int32_t k = kb + t * g;
+                            if (!hit && k <= hi && vs[t] == e) {
+                                atomicMin(&found[pl], k);
+                                hit = true;
+                            }
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+            if (p < np && sub == 0) {
+                if (!split) {
+                    nout[2 * p] = node;  // carried-up strip: same node one level down
+                } else {
+                    const int32_t k = found[pl];
+                    if (k == 0x7fffffff) {
+                        atomicOr(A.err, kErrTrace);
+                        nout[2 * p] = make_int4(s, 0, s, node.w);
+                        nout[2 * p + 1] = make_int4(s, 0, s, node.w);
+                    } else {
+                        const int32_t x = umin(urow[k], n);
+                        nout[2 * p] = make_int4(s, k, x, node.w);
+                        nout[2 * p + 1] = make_int4(x, w - k, e, node.w + k);
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        in_lds = out_lds;
+        if (out_lds) cur ^= 1;
     }
-    const StripRef U = child_strip(c, 2 * p), L = child_strip(c, 2 * p + 1);
-    trace_split_block(U.d, U.h, L.d, L.h, c.n, node, nodes_out + 2 * p, nodes_out + 2 * p + 1, err,
-                      lds);
 }
 
 constexpr int32_t kLeafTab = 4096;  // next-match table entries a leaf block keeps in LDS
 template <int H0>
-__global__ void __launch_bounds__(kBlock) k_trace_leaf(const uint8_t *a, int32_t n, int32_t sigma,
+__global__ void __launch_bounds__(kWave) k_trace_leaf(const uint8_t *a, int32_t n, int32_t sigma,
                                                        const int32_t *nm, int32_t nstrips,
                                                        int32_t hlast, const int4 *nodes,
                                                        int32_t *a_idx, int32_t *b_idx,
                                                        int32_t wcap, int32_t *err) {
     __shared__ int32_t lds[(H0 + 1) * (H0 + 1)];
-    __shared__ int32_t cand[(H0 + 1) * (H0 + 1)];
     __shared__ int32_t tab[kLeafTab];
     const int32_t s = blockIdx.x;
     const int32_t h = (s == nstrips - 1) ? hlast : H0;
     trace_leaf_block<H0, true>(a + (size_t)s * H0, h, n, sigma, nm, nodes[s], s * H0, a_idx, b_idx,
-                               wcap, err, lds, cand, tab, kLeafTab);
+                               wcap, err, lds, tab, kLeafTab);
 }
 
 __global__ void __launch_bounds__(kBlock) k_semilocal(const int32_t *top, int32_t m, int32_t n,
@@ -348,9 +426,10 @@ hipError_t launch_length(const int32_t *top, int32_t m, int32_t n, int32_t *hdr,
     return hipGetLastError();
 }
 
-hipError_t launch_trace_split(const CombineArgs &c, int32_t nparent, const int4 *nodes_in,
-                              int4 *nodes_out, int32_t *err, hipStream_t s) {
-    hipLaunchKernelGGL(k_trace_split, dim3(nparent), dim3(kBlock), 0, s, c, nodes_in, nodes_out, err);
+hipError_t launch_trace_splits(const TraceSplitArgs &t, hipStream_t s) {
+    if (t.top < 1) return hipSuccess;
+    if (t.top >= kTraceMaxLev) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_trace_splits, dim3(1), dim3(kSplitThreads), 0, s, t);
     return hipGetLastError();
 }
 
@@ -360,15 +439,15 @@ hipError_t launch_trace_leaf(int32_t h0, const uint8_t *a, int32_t n, int32_t si
                              hipStream_t s) {
     switch (h0) {
         case 16:
-            hipLaunchKernelGGL(k_trace_leaf<16>, dim3(nstrips), dim3(kBlock), 0, s, a, n, sigma, nm,
+            hipLaunchKernelGGL(k_trace_leaf<16>, dim3(nstrips), dim3(kWave), 0, s, a, n, sigma, nm,
                                nstrips, hlast, nodes, a_idx, b_idx, wcap, err);
             break;
         case 32:
-            hipLaunchKernelGGL(k_trace_leaf<32>, dim3(nstrips), dim3(kBlock), 0, s, a, n, sigma, nm,
+            hipLaunchKernelGGL(k_trace_leaf<32>, dim3(nstrips), dim3(kWave), 0, s, a, n, sigma, nm,
                                nstrips, hlast, nodes, a_idx, b_idx, wcap, err);
             break;
         case 64:
-            hipLaunchKernelGGL(k_trace_leaf<64>, dim3(nstrips), dim3(kBlock), 0, s, a, n, sigma, nm,
+            hipLaunchKernelGGL(k_trace_leaf<64>, dim3(nstrips), dim3(kWave), 0, s, a, n, sigma, nm,
                                nstrips, hlast, nodes, a_idx, b_idx, wcap, err);
             break;
         default:

@@ -16,8 +16,7 @@ hipError_t launch_anchor(const CombineArgs &c, int32_t npairs, hipStream_t s);
 hipError_t launch_bracket(const CombineArgs &c, int32_t npairs, hipStream_t s);
 hipError_t launch_length(const int32_t *top, int32_t m, int32_t n, int32_t *hdr, int4 *root,
                          hipStream_t s);
-hipError_t launch_trace_split(const CombineArgs &c, int32_t nparent, const int4 *nodes_in,
-                              int4 *nodes_out, int32_t *err, hipStream_t s);
+hipError_t launch_trace_splits(const TraceSplitArgs &t, hipStream_t s);
 hipError_t launch_trace_leaf(int32_t h0, const uint8_t *a, int32_t n, int32_t sigma,
                              const int32_t *nm, int32_t nstrips, int32_t hlast, const int4 *nodes,
                              int32_t *a_idx, int32_t *b_idx, int32_t wcap, int32_t *err,
