@@ -596,6 +596,8 @@ __device__ __forceinline__ void anchor_block(const int32_t *__restrict__ U, int3
 // block that holds it (jn = kJ + 1) evaluates it directly, so the
 // bisection works on at most kJ weights.
 constexpr int kCoarseItems = kBlock / 2;  // a level with at most this many outputs is coarse
+constexpr int kCoarseBatch = 8;  // consecutive candidates per thread slice of a coarse level
+constexpr int kPass2Batch = 8;   // candidates per batch of pass 2, one thread per output
 constexpr int32_t kCoopPass2MinH = 1024;  // child strip height from which pass 2 is cooperative
 constexpr int32_t kWideWindowMinH = 2048;  // child strip height from which the D_U window is wide
 // Shape of a bracket work-group: LDS state type, weights per block, width of
@@ -603,15 +605,16 @@ constexpr int32_t kWideWindowMinH = 2048;  // child strip height from which the 
 // indices stored in 16 bits, k* stored as k* + 1 so that -1 is 0): needs
 // n + 1 <= 65535 and strip heights <= 65534, and holds twice the weights in
 // about the same LDS, which halves the per-work-group overhead per output.
-template <typename T, int J, int UW>
+template <typename T, int J, int UW, int CB = 8>
 struct BracketCfg {
     using St = T;
     static constexpr int kJ = J;
     static constexpr int kUW = UW;
+    static constexpr int kCoopB = CB;  // candidates per thread slice of the cooperative pass 2
 };
 using BracketCfg32 = BracketCfg<int32_t, 32, 64>;
 using BracketCfg16 = BracketCfg<uint16_t, 64, 98>;
-using BracketCfg16Mid = BracketCfg<uint16_t, 64, 128>;    // 1024+ rows: still 8 work-groups per CU
+using BracketCfg16Mid = BracketCfg<uint16_t, 64, 128, 6>;  // 1024+ rows: still 8 work-groups per CU
 using BracketCfg16Wide = BracketCfg<uint16_t, 64, 160>;  // tall strips: wider D_U window
 
 template <class C>
@@ -810,8 +813,8 @@ __device__ __forceinline__ void bracket_pass1(BracketSmemT<C> &sm, const int32_t
 }
 
 // Coarse bisection level (at most kCoarseItems outputs, wide windows): g
-// threads per output scan consecutive slices of kBatch candidates of its
-// window in the same round, so the output sees g * kBatch candidates for one
+// threads per output scan consecutive slices of kCoarseBatch candidates of its
+// window in the same round, so the output sees g * kCoarseBatch candidates for one
 // round trip.  Slice minima meet through a 64-bit LDS atomic min of
 // (value, k), which keeps the smallest minimising k.  The stop tests then run
 // on the whole range; an unfinished output resumes in pass 2 after it.
@@ -834,13 +837,13 @@ __device__ __forceinline__ void bracket_coarse(BracketSmemT<C> &sm, const int32_
             const int32_t v = half + t * st, j = j0 + jj;
             const BracketWindow w = bracket_window<C, kLds>(sm, U, ldU, i0, ubase, v, v - half,
                                                          imin(v + half, len), jj, j, hU, hL, n);
-            const int32_t k0 = w.lo + sub * kBatch;
+            const int32_t k0 = w.lo + sub * kCoarseBatch;
             if (!w.dead && k0 <= w.hi) {
-                int32_t xs[kBatch], vs[kBatch];
-                bracket_load_u<C, kBatch, kLds>(sm, U, ldU, hU, i0, ubase, v, k0, w.hi, n, xs);
-                batch_load_l<false>(L, ldL, j, k0, 1, w.hi, xs, vs);
+                int32_t xs[kCoarseBatch], vs[kCoarseBatch];
+                bracket_load_u<C, kCoarseBatch, kLds>(sm, U, ldU, hU, i0, ubase, v, k0, w.hi, n, xs);
+                batch_load_l<false, kCoarseBatch>(L, ldL, j, k0, 1, w.hi, xs, vs);
                 int32_t best = n + 2, bk = -1;
-                batch_reduce(j, k0, 1, w.hi, w.xb, w.vlo, n, xs, vs, best, bk);
+                batch_reduce<kCoarseBatch>(j, k0, 1, w.hi, w.xb, w.vlo, n, xs, vs, best, bk);
                 if (best <= n)
                     atomicMin(&sm.key[e], ((unsigned long long)(uint32_t)best << 32) | (uint32_t)bk);
             }
@@ -868,13 +871,13 @@ __device__ __forceinline__ void bracket_coarse(BracketSmemT<C> &sm, const int32_
                 best = (int32_t)(key >> 32);
                 bk = (int32_t)(uint32_t)(key & 0xffffffffull);
             }
-            const int32_t kend = w.lo + g * kBatch - 1;
+            const int32_t kend = w.lo + g * kCoarseBatch - 1;
             const int32_t xl = bracket_u<C, kLds>(sm, U, ldU, hU, i0, ubase, v, imin(kend, w.hi), n);
             const bool done = (kend >= w.hi) | (xl > w.xb) | (best == w.vlo) |
                               ((best <= n) & (xl - kend >= best - j));
             if (done) {
                 bracket_store(sm, id, g_out, n, best, bk);
-            } else {  // provisional state; pass 2 resumes at lo + g * kBatch
+            } else {  // provisional state; pass 2 resumes at lo + g * kCoarseBatch
                 stk(sm, id, bk);
                 sm.v[id] = (typename C::St)imin(best, n + 1);
                 queued = true;
@@ -918,7 +921,7 @@ __device__ __forceinline__ void bracket_levels(BracketSmemT<C> &sm, const int32_
         if (nitems <= kCoarseItems) {
             int32_t g = 2;
             while (2 * g * nitems <= kBlock) g <<= 1;
-            b1 = g * kBatch;
+            b1 = g * kCoarseBatch;
             bracket_coarse<C, kLds>(sm, U, hU, L, hL, G, n, i0, len, j0, js, half, st, nitems,
                                     par, ubase, g);
         } else if (nitems > kBlock) {
@@ -937,8 +940,8 @@ __device__ __forceinline__ void bracket_levels(BracketSmemT<C> &sm, const int32_
         }
         __syncthreads();
         // pass 2: the queued outputs.  kCoop (tall strips) and few of them: g
-        // threads each scan interleaved slices of kBatch candidates, so an
-        // output sees g * kBatch candidates per round trip (slice minima meet
+        // threads each scan interleaved slices of C::kCoopB candidates, so an
+        // output sees g * C::kCoopB candidates per round trip (slice minima meet
         // in the LDS (value, k) minimum; the provisional pass-1 result, whose
         // candidates all lie below, keeps ties).  Otherwise one thread each,
         // batch after batch.  Measured on both benchmark pairs: queued outputs
@@ -958,11 +961,12 @@ __device__ __forceinline__ void bracket_levels(BracketSmemT<C> &sm, const int32_
                                                               imin(v + half, len), jj, j, hU, hL, n);
                 const int32_t best0 = (int32_t)sm.v[idq];
                 int32_t best = best0, bk = -1;
-                for (int32_t k0 = wq.lo + b1 + sub * kBatch; k0 <= wq.hi; k0 += g * kBatch) {
-                    int32_t xs[kBatch], vs[kBatch];
-                    bracket_load_u<C, kBatch, kLds>(sm, U, ldU, hU, i0, ubase, v, k0, wq.hi, n, xs);
-                    batch_load_l<true>(L, ldL, j, k0, 1, wq.hi, xs, vs);
-                    if (batch_reduce(j, k0, 1, wq.hi, wq.xb, wq.vlo, n, xs, vs, best, bk)) break;
+                constexpr int CB = C::kCoopB;
+                for (int32_t k0 = wq.lo + b1 + sub * CB; k0 <= wq.hi; k0 += g * CB) {
+                    int32_t xs[CB], vs[CB];
+                    bracket_load_u<C, CB, kLds>(sm, U, ldU, hU, i0, ubase, v, k0, wq.hi, n, xs);
+                    batch_load_l<true, CB>(L, ldL, j, k0, 1, wq.hi, xs, vs);
+                    if (batch_reduce<CB>(j, k0, 1, wq.hi, wq.xb, wq.vlo, n, xs, vs, best, bk)) break;
                 }
                 if (best < best0)
                     atomicMin(&sm.key[e], ((unsigned long long)(uint32_t)best << 32) | (uint32_t)bk);
@@ -989,11 +993,11 @@ __device__ __forceinline__ void bracket_levels(BracketSmemT<C> &sm, const int32_
                 const BracketWindow wq = bracket_window<C, kLds>(sm, U, ldU, i0, ubase, v, v - half,
                                                               imin(v + half, len), jj, j, hU, hL, n);
                 int32_t best = (int32_t)sm.v[idq], bk = ldk(sm, idq);
-                for (int32_t k0 = wq.lo + b1;; k0 += kBatch) {
-                    int32_t xs[kBatch], vs[kBatch];
-                    bracket_load_u<C, kBatch, kLds>(sm, U, ldU, hU, i0, ubase, v, k0, wq.hi, n, xs);
-                    batch_load_l<true>(L, ldL, j, k0, 1, wq.hi, xs, vs);
-                    if (batch_reduce(j, k0, 1, wq.hi, wq.xb, wq.vlo, n, xs, vs, best, bk))
+                for (int32_t k0 = wq.lo + b1;; k0 += kPass2Batch) {
+                    int32_t xs[kPass2Batch], vs[kPass2Batch];
+                    bracket_load_u<C, kPass2Batch, kLds>(sm, U, ldU, hU, i0, ubase, v, k0, wq.hi, n, xs);
+                    batch_load_l<true, kPass2Batch>(L, ldL, j, k0, 1, wq.hi, xs, vs);
+                    if (batch_reduce<kPass2Batch>(j, k0, 1, wq.hi, wq.xb, wq.vlo, n, xs, vs, best, bk))
                         break;
                 }
                 bracket_store(sm, idq, G + (size_t)(i0 + v) * H + j, n, best, bk);
