@@ -249,14 +249,24 @@ def test_config_4096():
     Lg, plan, ws = check_against_oracle(p.a, p.b, p.sigma, base_rows=64)
     # sampled rows of the top matrix (the oracle computes one row per dynamic program)
     _top_rows_check(p.a, p.b, plan, ws, [0, 1, 63, 64, 65, 2048, 4000, 4095, 4096])
-    # sampled rows of every level's first and last strip
+    # sampled rows of every level's first and last strip; the top two levels
+    # (the bracket shapes of 1024- and 2048-row strips: 128- and 160-wide D_U
+    # windows, cooperative pass 2) at vertices around tile boundaries and
+    # spread over the row range
+    rng = np.random.default_rng(4096)
+    top_verts = sorted(set([1, 2, 15, 16, 17, 31, 32, 33, 63, 64, 65, 95, 2047, 2048, 2049, 4064, 4095]
+                           + [int(v) for v in rng.integers(0, 4097, 24)]))
+    nlev = len(plan.levels())
     for lv, cnt in enumerate(plan.levels()):
         for s in sorted({0, cnt - 1}):
             D, row0 = plan.dist(lv, s, ws)
             h = D.shape[1] - 1
-            verts = [0, 777, 4033, 4096]
+            verts = [0, 777, 4033, 4096] + (top_verts if lv >= nlev - 2 else [])
             got = D[verts].cpu().numpy()
-            assert np.array_equal(got, oracle.dist_rows(p.a, row0, row0 + h, p.b, verts)), (lv, s)
+            want = oracle.dist_rows(p.a, row0, row0 + h, p.b, verts)
+            bad = np.argwhere(got != want)
+            assert bad.size == 0, "level %d strip %d vertex %d weight %d got %d want %d" % (
+                lv, s, verts[bad[0][0]], bad[0][1], got[tuple(bad[0])], want[tuple(bad[0])])
 
 
 def test_config_16384_mutated():
