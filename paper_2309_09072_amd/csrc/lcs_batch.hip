@@ -314,6 +314,7 @@ __global__ void __launch_bounds__(kBlock) k_pair_queue(BatchArgs A, const int32_
 struct StageArgs {
     int32_t kind, level, npairs;
     int32_t jchunk;         // weights per bracket task (the bracket shape's kJ)
+    int32_t base_mode;      // table form of the base-strip tasks (kBase*Mode)
     const int32_t *pair;    // participating pairs
     const int64_t *first;   // their first item, plus the total at [npairs]
 };
@@ -343,10 +344,10 @@ __global__ void __launch_bounds__(kBlock) k_stage(BatchArgs A, StageArgs S) {
 
 // Staged base-strip tasks (one strip x one 256-vertex block each) with the
 // next-match table window in LDS, as in the single-pair path.
-template <int H0>
+template <int H0, int kMode>
 __global__ void __launch_bounds__(kBlock) k_stage_base(BatchArgs A, StageArgs S) {
-    __shared__ int32_t lds[kWave * (H0 + 1)];
-    __shared__ uint16_t tab[kBaseTab];
+    static_assert(kMode == kBaseTab16Mode, "the global-table form runs in k_stage");
+    __shared__ __align__(16) uint8_t smem[base_smem_bytes<H0, kMode>()];  // table, then transposition
     __shared__ int32_t s_pu[2];
     const int64_t t = blockIdx.x;
     if (threadIdx.x == 0) {
@@ -376,8 +377,8 @@ __global__ void __launch_bounds__(kBlock) k_stage_base(BatchArgs A, StageArgs S)
     int32_t *out = reinterpret_cast<int32_t *>(ws + (last ? g.last_off : g.base)) +
                    (last ? 0 : (size_t)s0 * strip_elems(P.n, H0));
     const int32_t vb = u - s0 * nvb;
-    base_strip_block<H0, true>(a + (size_t)s0 * H0, h, P.n, A.sigma, nm, out, vb * kBlock, hdr, lds,
-                               tab);
+    base_strip_block<H0, kMode>(a + (size_t)s0 * H0, h, P.n, A.sigma, nm, out, vb * kBlock, hdr,
+                                reinterpret_cast<int32_t *>(smem), smem);
 }
 
 // Staged bracket tasks (one tile x one weight chunk each) in the bracket shape
@@ -557,7 +558,13 @@ static hipError_t launch_stage(const BatchArgs &A, const StageArgs &S, dim3 grid
     switch (S.kind) {
         case ST_EMPTY: hipLaunchKernelGGL((k_stage<H0, ST_EMPTY>), grid, dim3(kBlock), 0, st, A, S); break;
         case ST_NM_SYM: hipLaunchKernelGGL((k_stage<H0, ST_NM_SYM>), grid, dim3(kBlock), 0, st, A, S); break;
-        case ST_BASE_BLK: hipLaunchKernelGGL((k_stage_base<H0>), grid, dim3(kBlock), 0, st, A, S); break;
+        case ST_BASE_BLK:
+            // table form by the plan's longest string (every pair's n is at most that)
+            if (S.base_mode == kBaseTab16Mode)
+                hipLaunchKernelGGL((k_stage_base<H0, kBaseTab16Mode>), grid, dim3(kBlock), 0, st, A, S);
+            else  // the generic step kernel keeps a smaller register allocation here
+                hipLaunchKernelGGL((k_stage<H0, ST_BASE_BLK>), grid, dim3(kBlock), 0, st, A, S);
+            break;
         case ST_ANCHOR: hipLaunchKernelGGL((k_stage<H0, ST_ANCHOR>), grid, dim3(kBlock), 0, st, A, S); break;
         case ST_BRACKET_CH:
             if (S.jchunk == BracketCfg16::kJ)
@@ -982,6 +989,11 @@ extern "C" int32_t lcs_batch_submit(lcs_batch_t B, const lcs_pair_desc *pairs, i
                 S.level = sl.level;
                 S.npairs = sl.npairs;
                 S.jchunk = stage_jchunk(B->d.max_len);
+                switch (B->d.base_rows) {
+                    case 16: S.base_mode = base_tab_mode<16>(B->d.max_len, B->d.alphabet); break;
+                    case 32: S.base_mode = base_tab_mode<32>(B->d.max_len, B->d.alphabet); break;
+                    default: S.base_mode = base_tab_mode<64>(B->d.max_len, B->d.alphabet); break;
+                }
                 S.pair = reinterpret_cast<const int32_t *>(ws + B->off_stage + sl.pair_off);
                 S.first = reinterpret_cast<const int64_t *>(ws + B->off_stage + sl.first_off);
                 if (sl.items >= (int64_t)1 << 31) return LCS_E_TOO_BIG;

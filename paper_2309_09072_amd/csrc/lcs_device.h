@@ -106,21 +106,53 @@ __device__ void nextmatch_block(const uint8_t *__restrict__ b, int32_t n, int32_
 // v..v+63 of a strip matrix are adjacent in memory.  The waves take turns on
 // one 64-row buffer, and all 256 threads copy each turn out.
 //
-// Table window (kTab): the ~h^2/2 lookups per vertex are gathers, and served
-// by the vector memory path they cost ~16 cycles per wave instruction; from
-// LDS they cost a few.  The work-group copies columns v0 .. v0+T-1 of every
-// symbol's table into LDS as uint16 values relative to v0 (entry T of each
-// symbol is a marker above every value), keeps D relative to v0, and clamps
-// lookup indices to T.  A clamped lookup stands for a table value above T
-// (the next match after column c is > c), so by induction over the rows
-// every computed entry <= T is exact and every exact entry <= T is computed;
-// only entries > T can be wrong.  Hence the result is exact when the window
-// reaches the sentinel column n + 1, or when no entry ends above T; in the
-// remaining case the work-group recomputes the strip from the global tables.
-// lds: kWave*(H0+1) int32; tab: kBaseTab uint16 (kTab only).
-constexpr int32_t kBaseTab = 8192;    // LDS table entries per work-group
-constexpr int32_t kBaseTabCap = 2047; // at most this many columns per symbol
+// Table window: the ~h^2/2 lookups per vertex are gathers, and served by the
+// vector memory path they cost ~16 cycles per wave instruction; from LDS they
+// cost a few.  The work-group copies columns v0 .. v0+T-1 of every symbol's
+// table into LDS as uint16 values relative to v0 (entry T of each symbol is a
+// marker above every value), keeps D relative to v0, and clamps lookup
+// indices to T.  A clamped lookup stands for a table value above T (the next
+// match after column c is > c), so by induction over the rows every computed
+// entry <= T is exact and every exact entry <= T is computed; only entries > T
+// can be wrong.  Hence the result is exact when the window reaches the
+// sentinel column n + 1, or when no entry ends above T; in the remaining case
+// the work-group recomputes the strip from the global tables.
+// The window is for small alphabets: for random strings the matches of a
+// strip's rows lie about H0 * sigma columns past the vertex, so a large
+// alphabet needs a window sigma times wider per symbol, and there the global
+// tables are read directly.  (A one-byte table of gaps to the next match,
+// which fits alphabet 20, measured no faster than the global tables on the
+// 16384 x 16384 alphabet-20 pair: 2.72 vs 2.65 ms.)
+// smem: base_smem_bytes<H0, kMode>() bytes, shared by the table and, once
+// the rows are done, the 64-row transposition buffer (kWave*(H0+1) int32).
+constexpr int32_t kBaseTab16 = 8192;   // table entries at most
+constexpr int32_t kBaseTabCap = 2047;  // at most this many columns per symbol
+template <int H0>
+struct BaseSmem {
+    static constexpr int32_t kTrans = kWave * (H0 + 1) * 4;  // transposition buffer
+    static constexpr int32_t kTab = 2 * kBaseTab16;
+    static constexpr int32_t kBytes = kTab > kTrans ? kTab : kTrans;
+};
 
+// Table form of a base-strip launch: global tables or the uint16 window
+// (host and device; the launcher picks the kernel instance with it).
+constexpr int32_t kBaseGlobal = 0, kBaseTab16Mode = 1;
+__host__ __device__ inline int32_t base_tab_cols(int32_t sigma) {
+    return imin(kBaseTab16 / sigma - 1, kBaseTabCap);
+}
+template <int H0>
+__host__ __device__ inline int32_t base_tab_mode(int32_t n, int32_t sigma) {
+    if (n + 2 > 65535 || sigma < 1) return kBaseGlobal;
+    return (kBlock + 2 * H0 * sigma <= base_tab_cols(sigma)) ? kBaseTab16Mode : kBaseGlobal;
+}
+// bytes of LDS a base-strip work-group of this table form takes
+template <int H0, int kMode>
+constexpr int32_t base_smem_bytes() {
+    return kMode == kBaseTab16Mode ? BaseSmem<H0>::kBytes : BaseSmem<H0>::kTrans;
+}
+
+// Appends the strip's rows to D: look(x, d) is the next-match table of
+// symbol x at column d (the candidate for the entry to its right).
 template <int H0, class Look>
 __device__ __forceinline__ bool base_append_rows(const uint8_t *__restrict__ arow, int32_t h,
                                                  int32_t sigma, int32_t (&D)[H0 + 1], Look look) {
@@ -140,11 +172,11 @@ __device__ __forceinline__ bool base_append_rows(const uint8_t *__restrict__ aro
     return bad;
 }
 
-template <int H0, bool kTab = false>
+template <int H0, int kMode = kBaseGlobal>
 __device__ void base_strip_block(const uint8_t *__restrict__ arow, int32_t h, int32_t n,
                                  int32_t sigma, const int32_t *__restrict__ nm,
                                  int32_t *__restrict__ out, int32_t v0, int32_t *err,
-                                 int32_t *lds, uint16_t *tab = nullptr) {
+                                 int32_t *lds, uint8_t *smem = nullptr) {
     const int32_t INF = n + 1;
     const int lane = __lane_id();
     const int w = threadIdx.x / kWave;
@@ -153,17 +185,25 @@ __device__ void base_strip_block(const uint8_t *__restrict__ arow, int32_t h, in
     int32_t D[H0 + 1];
     bool bad = false;
     bool done = false;
-    // The window is used when it is likely to hold every lookup: for random
-    // strings the row matches of a strip lie about H0 * sigma columns past the
-    // vertex, so small alphabets (DNA-like) take it and large ones (protein)
-    // read the global tables directly.
-    if (kTab && n + 2 <= 65535 && kBlock + 2 * H0 * sigma <= imin(kBaseTab / sigma - 1, kBaseTabCap)) {
-        const int32_t T = imin(imin(n + 2 - v0, kBaseTab / sigma - 1), kBaseTabCap);
+    // (the launcher checked n + 2 <= 65535; testing it again at run time
+    // measurably keeps the register allocation of this path small)
+    if (kMode == kBaseTab16Mode && n + 2 <= 65535) {
+        const int32_t T = imin(n + 2 - v0, base_tab_cols(sigma));
         const int32_t ts = T + 1;  // per-symbol stride
-        for (int32_t x = 0; x < sigma; ++x)
-            for (int32_t c = threadIdx.x; c < ts; c += kBlock)
-                tab[x * ts + c] = (c < T) ? (uint16_t)(nm[(size_t)x * ldn + (size_t)(v0 + c)] - v0)
-                                          : (uint16_t)0xFFFF;
+        uint16_t *tab = reinterpret_cast<uint16_t *>(smem);
+        for (int32_t x = 0; x < sigma; ++x) {  // 8 loads in flight per thread
+            const int32_t *src = nm + (size_t)x * ldn + v0;
+            for (int32_t c0 = threadIdx.x; c0 < ts; c0 += 8 * kBlock) {
+                int32_t nv[8];
+#pragma unroll
+                for (int t = 0; t < 8; ++t) nv[t] = src[imin(c0 + t * kBlock, T - 1)];
+#pragma unroll
+                for (int t = 0; t < 8; ++t) {
+                    const int32_t c = c0 + t * kBlock;
+                    if (c < ts) tab[x * ts + c] = (c < T) ? (uint16_t)(nv[t] - v0) : (uint16_t)0xFFFF;
+                }
+            }
+        }
         __syncthreads();
         D[0] = (i <= n) ? (int32_t)threadIdx.x : INF - v0;
 #pragma unroll
@@ -191,6 +231,7 @@ __device__ void base_strip_block(const uint8_t *__restrict__ arow, int32_t h, in
         });
     }
     if (bad && threadIdx.x == 0) atomicOr(err, kErrSymbol);
+    __syncthreads();  // the table (if any) is dead; its memory is the transposition buffer
     const int32_t hp1 = h + 1;
     for (int w2 = 0; w2 < kWaves; ++w2) {
         if (w == w2) {

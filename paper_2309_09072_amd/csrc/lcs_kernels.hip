@@ -16,18 +16,17 @@ __global__ void __launch_bounds__(kBlock) k_nextmatch(const uint8_t *b, int32_t 
     nextmatch_block(b, n, x, nm + (size_t)x * (size_t)(n + 2), lds);
 }
 
-template <int H0>
+template <int H0, int kMode>
 __global__ void __launch_bounds__(kBlock) k_base(const uint8_t *a, int32_t n, int32_t sigma,
                                                  const int32_t *nm, int32_t *base0, int32_t *last,
                                                  int32_t nstrips, int32_t hlast, int32_t *err) {
-    __shared__ int32_t lds[kWave * (H0 + 1)];
-    __shared__ uint16_t tab[kBaseTab];
+    __shared__ __align__(16) uint8_t smem[base_smem_bytes<H0, kMode>()];  // table, then transposition
     const int32_t s = blockIdx.y;
     const bool is_last = (s == nstrips - 1);
     const int32_t h = is_last ? hlast : H0;
     int32_t *out = is_last ? last : base0 + (size_t)s * strip_elems(n, H0);
-    base_strip_block<H0, true>(a + (size_t)s * H0, h, n, sigma, nm, out, (int32_t)blockIdx.x * kBlock,
-                               err, lds, tab);
+    base_strip_block<H0, kMode>(a + (size_t)s * H0, h, n, sigma, nm, out, (int32_t)blockIdx.x * kBlock,
+                                err, reinterpret_cast<int32_t *>(smem), smem);
 }
 
 // Anchor search with the D_U row and the k* row of the vertex in LDS
@@ -279,25 +278,30 @@ hipError_t launch_nextmatch(const uint8_t *b, int32_t n, int32_t sigma, int32_t 
     return hipGetLastError();
 }
 
+template <int H0>
+static void launch_base_h(dim3 grid, hipStream_t s, const uint8_t *a, int32_t n, int32_t sigma,
+                          const int32_t *nm, int32_t *base0, int32_t *last, int32_t nstrips,
+                          int32_t hlast, int32_t *err) {
+    switch (base_tab_mode<H0>(n, sigma)) {
+        case kBaseTab16Mode:
+            hipLaunchKernelGGL((k_base<H0, kBaseTab16Mode>), grid, dim3(kBlock), 0, s, a, n, sigma, nm,
+                               base0, last, nstrips, hlast, err);
+            break;
+        default:
+            hipLaunchKernelGGL((k_base<H0, kBaseGlobal>), grid, dim3(kBlock), 0, s, a, n, sigma, nm,
+                               base0, last, nstrips, hlast, err);
+    }
+}
+
 hipError_t launch_base(int32_t h0, const uint8_t *a, int32_t n, int32_t sigma, const int32_t *nm,
                        int32_t *base0, int32_t *last, int32_t nstrips, int32_t hlast, int32_t *err,
                        hipStream_t s) {
     const dim3 grid((n + 2 + kBlock - 1) / kBlock, nstrips);
     switch (h0) {
-        case 16:
-            hipLaunchKernelGGL(k_base<16>, grid, dim3(kBlock), 0, s, a, n, sigma, nm, base0, last,
-                               nstrips, hlast, err);
-            break;
-        case 32:
-            hipLaunchKernelGGL(k_base<32>, grid, dim3(kBlock), 0, s, a, n, sigma, nm, base0, last,
-                               nstrips, hlast, err);
-            break;
-        case 64:
-            hipLaunchKernelGGL(k_base<64>, grid, dim3(kBlock), 0, s, a, n, sigma, nm, base0, last,
-                               nstrips, hlast, err);
-            break;
-        default:
-            return hipErrorInvalidValue;
+        case 16: launch_base_h<16>(grid, s, a, n, sigma, nm, base0, last, nstrips, hlast, err); break;
+        case 32: launch_base_h<32>(grid, s, a, n, sigma, nm, base0, last, nstrips, hlast, err); break;
+        case 64: launch_base_h<64>(grid, s, a, n, sigma, nm, base0, last, nstrips, hlast, err); break;
+        default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }

@@ -109,6 +109,26 @@ def test_base_table_window_and_fallback():
             _base_rows_check(a, b, plan, ws, verts)
 
 
+def test_base_strips_alphabet_20():
+    """Alphabet 20 (the global next-match tables): base strips of every
+    height against the oracle.  Case 1: i.i.d. strings.  Case 2: symbols 18
+    and 19 are absent from b's first 3000 columns (matches jump far ahead).
+    Case 3: a mutated copy (long matching runs)."""
+    r = np.random.default_rng(2020)
+    n = 5000
+    verts = sorted(set(list(range(0, n + 1, 41)) + [1, 255, 256, 257, 2999, 3000, 3001, n - 1, n]))
+    a1 = r.integers(0, 20, 192).astype(np.uint8)
+    b1 = r.integers(0, 20, n).astype(np.uint8)
+    b2 = np.concatenate([r.integers(0, 18, 3000), r.integers(0, 20, n - 3000)]).astype(np.uint8)
+    p3 = synth.pair_mutated(192, 192, 20, 77, 0.10, 0.05, 0.05)
+    b3 = np.concatenate([p3.b, r.integers(0, 20, n - p3.b.size)]).astype(np.uint8)
+    for a, b in ((a1, b1), (a1, b2), (p3.a, b3)):
+        for h0 in (16, 32, 64):
+            say("alphabet 20 base", h0, b.size)
+            Lg, plan, ws = check_against_oracle(a, b, 20, base_rows=h0)
+            _base_rows_check(a, b, plan, ws, verts)
+
+
 def test_many_short_anchor_rows():
     """Levels with many anchors and rows of at most 1024 weights run one
     anchor search per wave; 512 x 3000 with 16-row strips and tile 4 puts
