@@ -15,12 +15,17 @@
 // LCS_BATCH_PERSISTENT runs the whole batch -- every pair's next-match tables,
 // base strips, combine levels, length and witness trace -- in ONE launch of a
 // persistent kernel: as many work-groups as fit on the device at once pop task
-// indices from a device counter in increasing order.  Tasks are numbered pair
-// by pair in dependency order, and every task waits (bounded spin) only on
-// counters raised by tasks with smaller numbers, which were popped earlier by
-// running work-groups; so the queue always drains.  Pair p uses workspace slot
-// p mod slots, and its first task also waits until pair p - slots has finished
-// its trace, which bounds the memory of a batch of any size.
+// indices from a device counter in increasing order.  The tasks are the items
+// of the staged mode (one symbol, one strip block, one anchor vertex, one tile
+// x weight chunk, ...).  They are numbered wave by wave of the pairs that hold
+// the slots at one time, and inside a wave step by step of the method across
+// all of its pairs, so the work-groups in flight work on one step of many
+// pairs rather than on the dependency chain of one.  Every task waits
+// (bounded spin) only on counters raised by tasks with smaller numbers, which
+// were popped earlier by running work-groups; so the queue always drains.
+// Pair p uses workspace slot p mod slots, and its first tasks also wait until
+// pair p - slots has finished its trace, which bounds the memory of a batch of
+// any size.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <string.h>
@@ -49,29 +54,37 @@ struct BatchArgs {
     const PairRec *pairs;
     int32_t npairs;
     int32_t slots;
-    int64_t ntasks;
+    int64_t nchunks;       // persistent mode: chunks of the task order
+    int32_t chunk;         // tasks per chunk at most
     uint8_t *ws;
     const uint8_t *symbols;
     int32_t *lengths;
     int32_t *a_idx;
     int32_t *b_idx;
     int32_t *ctr;          // all pair counters
-    unsigned long long *next;  // task dispenser
+    unsigned long long *next;  // chunk (or pair) dispenser
     int32_t *gerr;         // bit 0: a dependency wait timed out
     int32_t sigma;
     int32_t tile;
+    const Seg *segs;     // persistent mode: the global task order
+    int64_t nseg;
+    int32_t base_mode;   // table form of the base-strip tasks (kBase*Mode)
 };
 
 constexpr uint32_t kSpinLimit = 1u << 22;  // ~ seconds: a dependency bug ends as an error, not a hang
 
-__device__ __forceinline__ int32_t ld_acq(const int32_t *p) {
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+// Counter polling and raising are relaxed atomics at device scope; the
+// persistent kernel orders the data around them with one acquire fence after
+// all waits of a chunk and one release fence before its raises (each such
+// fence is cache maintenance of the whole L2 of the die).
+__device__ __forceinline__ int32_t ld_ctr(const int32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // thread 0 only; false when the bounded wait ran out
 __device__ bool wait_ge(const int32_t *p, int32_t target, int32_t *gerr) {
     uint32_t spins = 0;
-    while (ld_acq(p) < target) {
+    while (ld_ctr(p) < target) {
         __builtin_amdgcn_s_sleep(4);
         if (++spins > kSpinLimit) {
             atomicOr(gerr, 1);
@@ -81,9 +94,8 @@ __device__ bool wait_ge(const int32_t *p, int32_t target, int32_t *gerr) {
     return true;
 }
 
-__device__ __forceinline__ void signal(int32_t *p) {
-    __threadfence();
-    __hip_atomic_fetch_add(p, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+__device__ __forceinline__ void raise_ctr(int32_t *p, int32_t v) {
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ __forceinline__ CombineArgs pair_combine_args(const PairRec &P, uint8_t *ws, int32_t l,
@@ -110,27 +122,69 @@ __device__ __forceinline__ CombineArgs pair_combine_args(const PairRec &P, uint8
 
 union PersistentSmem {
     int32_t nm[kWaves];
-    int32_t base[kWave * 65];
+    int32_t base[kWave * 65];  // also the table form's window, then its transposition
     AnchorSmemBlock anchor;
     BracketSmem bracket;
+    BracketSmemT<BracketCfg16> bracket16;
     int32_t len[1];
     int32_t split[1];
     int32_t leaf[65 * 65];
 };
+static_assert(sizeof(int32_t) * kWave * 65 >= base_smem_bytes<64, kBaseTab16Mode>(),
+              "the base member holds a table-form base strip of 64 rows");
 
-// fine-grained task kinds of the staged mode (coarse ones are in lcs_sched.h)
-constexpr int32_t ST_NM_SYM = 16;       // u = symbol
-constexpr int32_t ST_BASE_BLK = 17;     // u = strip * vertex_blocks + block
-constexpr int32_t ST_BRACKET_CH = 18;   // u = (q * tiles + tile) * chunks + chunk
+__device__ __forceinline__ int32_t vertex_blocks(int32_t n) { return vertex_blocks_of(n, kBlock); }
 
-__device__ __forceinline__ int32_t vertex_blocks(int32_t n) { return (n + 2 + kBlock - 1) / kBlock; }
-__device__ __forceinline__ int32_t level_chunks(const PairRec &P, int32_t l) {
-    const int32_t H = 2 * P.lev[l - 1].hfull + 1;
-    return imax(1, (H - 1 + kJChunk - 1) / kJChunk);
+// Base-strip task u of pair P (one strip x one 256-vertex block) in table
+// form kMode; smem: base_smem_bytes<H0, kMode>() bytes.
+template <int H0, int kMode>
+__device__ __forceinline__ void base_task(const BatchArgs &A, uint8_t *ws, const PairRec &P,
+                                          int32_t u, int32_t *lds, uint8_t *smem) {
+    int32_t *hdr = reinterpret_cast<int32_t *>(ws + P.off_hdr);
+    const int32_t *nm = reinterpret_cast<const int32_t *>(ws + P.off_nm);
+    const uint8_t *a = A.symbols + P.a_off;
+    const LevelGeom &g = P.lev[0];
+    const int32_t nvb = vertex_blocks(P.n);
+    const int32_t s0 = u / nvb;
+    const bool last = (s0 == g.nstrips - 1);
+    const int32_t h = last ? g.hlast : H0;
+    int32_t *out = reinterpret_cast<int32_t *>(ws + (last ? g.last_off : g.base)) +
+                   (last ? 0 : (size_t)s0 * strip_elems(P.n, H0));
+    const int32_t vb = u - s0 * nvb;
+    base_strip_block<H0, kMode>(a + (size_t)s0 * H0, h, P.n, A.sigma, nm, out, vb * kBlock, hdr, lds,
+                                smem);
 }
 
-// One task of pair p (all threads of the work-group).
-template <int H0>
+// Bracket task u of level l of pair P (one tile x one weight chunk of C::kJ
+// weights; a chunk beyond a short last strip's weights does nothing).
+template <class C>
+__device__ __forceinline__ void bracket_task(const BatchArgs &A, uint8_t *ws, const PairRec &P,
+                                             int32_t l, int32_t u, BracketSmemT<C> &sm) {
+    const CombineArgs c = pair_combine_args(P, ws, l, A.tile);
+    const int32_t ntile = P.nanch - 1;
+    const int32_t Hf = 2 * P.lev[l - 1].hfull + 1;  // weights of a full-height parent
+    const int32_t nchl = imax(1, (Hf - 1 + C::kJ - 1) / C::kJ);
+    const int32_t qt = u / nchl;
+    const int32_t q = qt / ntile, tl = qt - q * ntile, ch = u - qt * nchl;
+    const StripRef U = child_strip(c, 2 * q), L = child_strip(c, 2 * q + 1);
+    int32_t *G = parent_strip(c, q);
+    const int32_t H = U.h + L.h + 1;
+    const int32_t nch = imax(1, (H - 1 + C::kJ - 1) / C::kJ);
+    if (ch >= nch) return;
+    const int32_t i0 = tl * A.tile;
+    const int32_t len = imin(A.tile, P.n - i0);
+    const int32_t *Ka = c.anch + ((size_t)q * c.nanch + tl) * (size_t)c.hs;
+    const int32_t *Kb = c.anch + ((size_t)q * c.nanch + tl + 1) * (size_t)c.hs;
+    const int32_t j0 = ch * C::kJ;
+    const int32_t jn = (ch == nch - 1) ? H - j0 : C::kJ;
+    bracket_block<C>(U.d, U.h, L.d, L.h, G, P.n, i0, len, j0, jn, Ka, Kb, sm);
+}
+
+// One task of pair p (all threads of the work-group).  kAll: every table
+// form and bracket shape, chosen at run time (the persistent and pair-queue
+// kernels); otherwise the global-table base strips only (the step kernel,
+// which the staged mode uses for them).
+template <int H0, bool kAll = true>
 __device__ __forceinline__ void exec_task(const BatchArgs &A, uint8_t *ws, int32_t p, int32_t kind,
                                           int32_t l, int32_t u, PersistentSmem &sm) {
     const PairRec &P = A.pairs[p];
@@ -142,31 +196,18 @@ __device__ __forceinline__ void exec_task(const BatchArgs &A, uint8_t *ws, int32
         case ST_EMPTY:
             if (threadIdx.x == 0) A.lengths[p] = 0;
             break;
-        case ST_NM:
-        case ST_NM_SYM: {
-            if (kind == ST_NM || u == 0)
+        case ST_NM_SYM:
+            if (u == 0)
                 for (int32_t i = threadIdx.x; i < kHeaderWords; i += kBlock) hdr[i] = 0;
-            const int32_t x0 = kind == ST_NM ? 0 : u, x1 = kind == ST_NM ? A.sigma : u + 1;
-            for (int32_t x = x0; x < x1; ++x)
-                nextmatch_block(b, P.n, x, nm + (size_t)x * (size_t)(P.n + 2), sm.nm);
+            nextmatch_block(b, P.n, u, nm + (size_t)u * (size_t)(P.n + 2), sm.nm);
             break;
-        }
-        case ST_BASE:
-        case ST_BASE_BLK: {
-            const LevelGeom &g = P.lev[0];
-            const int32_t nvb = vertex_blocks(P.n);
-            const int32_t s0 = kind == ST_BASE ? u : u / nvb;
-            const bool last = (s0 == g.nstrips - 1);
-            const int32_t h = last ? g.hlast : H0;
-            int32_t *out = reinterpret_cast<int32_t *>(ws + (last ? g.last_off : g.base)) +
-                           (last ? 0 : (size_t)s0 * strip_elems(P.n, H0));
-            const int32_t vb0 = kind == ST_BASE ? 0 : u - s0 * nvb;
-            const int32_t vb1 = kind == ST_BASE ? nvb : vb0 + 1;
-            for (int32_t vb = vb0; vb < vb1; ++vb)
-                base_strip_block<H0>(a + (size_t)s0 * H0, h, P.n, A.sigma, nm, out, vb * kBlock, hdr,
-                                     sm.base);
+        case ST_BASE_BLK:
+            if (kAll && A.base_mode == kBaseTab16Mode)
+                base_task<H0, kBaseTab16Mode>(A, ws, P, u, sm.base,
+                                              reinterpret_cast<uint8_t *>(sm.base));
+            else
+                base_task<H0, kBaseGlobal>(A, ws, P, u, sm.base, nullptr);
             break;
-        }
         case ST_ANCHOR: {
             const CombineArgs c = pair_combine_args(P, ws, l, A.tile);
             const int32_t q = u / P.nanch, an = u - q * P.nanch;
@@ -181,39 +222,12 @@ __device__ __forceinline__ void exec_task(const BatchArgs &A, uint8_t *ws, int32
             }
             break;
         }
-        case ST_BRACKET:
-        case ST_BRACKET_CH: {
-            const CombineArgs c = pair_combine_args(P, ws, l, A.tile);
-            const int32_t ntile = P.nanch - 1;
-            const int32_t nchl = level_chunks(P, l);
-            int32_t q, tl, ch0, ch1;
-            if (kind == ST_BRACKET) {
-                q = u / ntile;
-                tl = u - q * ntile;
-                ch0 = 0;
-                ch1 = 1 << 30;
-            } else {
-                const int32_t qt = u / nchl;
-                q = qt / ntile;
-                tl = qt - q * ntile;
-                ch0 = u - qt * nchl;
-                ch1 = ch0 + 1;
-            }
-            const StripRef U = child_strip(c, 2 * q), L = child_strip(c, 2 * q + 1);
-            int32_t *G = parent_strip(c, q);
-            const int32_t H = U.h + L.h + 1;
-            const int32_t nch = imax(1, (H - 1 + kJChunk - 1) / kJChunk);
-            const int32_t i0 = tl * A.tile;
-            const int32_t len = imin(A.tile, P.n - i0);
-            const int32_t *Ka = c.anch + ((size_t)q * c.nanch + tl) * (size_t)c.hs;
-            const int32_t *Kb = c.anch + ((size_t)q * c.nanch + tl + 1) * (size_t)c.hs;
-            for (int32_t ch = ch0; ch < imin(ch1, nch); ++ch) {
-                const int32_t j0 = ch * kJChunk;
-                const int32_t jn = (ch == nch - 1) ? H - j0 : kJChunk;
-                bracket_block(U.d, U.h, L.d, L.h, G, P.n, i0, len, j0, jn, Ka, Kb, sm.bracket);
-            }
+        case ST_BRACKET_CH:
+            if (kAll && P.jchunk == BracketCfg16::kJ)
+                bracket_task<BracketCfg16>(A, ws, P, l, u, sm.bracket16);
+            else
+                bracket_task<BracketCfg32>(A, ws, P, l, u, sm.bracket);
             break;
-        }
         case ST_LENGTH: {
             const LevelGeom &top = P.lev[P.nlev - 1];
             length_block(reinterpret_cast<const int32_t *>(ws + top.last_off), P.m, P.n, hdr,
@@ -250,30 +264,59 @@ __device__ __forceinline__ void exec_task(const BatchArgs &A, uint8_t *ws, int32
 template <int H0>
 __global__ void __launch_bounds__(kBlock) k_persistent(BatchArgs A) {
     __shared__ PersistentSmem sm;
-    __shared__ Task s_task;
-    __shared__ int32_t s_ok;
+    __shared__ int32_t s_pair, s_stage, s_u0, s_cnt, s_ok;
     for (;;) {
         if (threadIdx.x == 0) {
-            const long long t = (long long)atomicAdd(A.next, 1ull);
-            s_task.kind = -1;
-            if (t < A.ntasks) {
-                s_task = decode_task(A.pairs, A.npairs, A.slots, t);
-                // wait for the inputs (bounded); on a timeout the task is skipped
+            const long long g = (long long)atomicAdd(A.next, 1ull);
+            s_cnt = 0;
+            if (g < A.nchunks) {
+                const Seg &sg = A.segs[find_seg(A.segs, A.nseg, g)];
+                const int32_t u0 = (int32_t)(g - sg.start) * A.chunk;
+                const int32_t cnt = imin(A.chunk, stage_tasks(A.pairs[sg.pair], sg.stage) - u0);
+                // wait for the inputs of every task of the chunk (bounded); on a
+                // timeout the chunk is skipped
                 int32_t ok = 1;
-                for (int32_t w = 0; w < s_task.nwait; ++w)
-                    ok &= wait_ge(A.ctr + s_task.wait_idx[w], s_task.wait_tgt[w], A.gerr);
+                for (int32_t u = u0; u < u0 + cnt; ++u) {
+                    const Task T = decode_task(A.pairs, A.slots, sg.pair, sg.stage, u);
+                    for (int32_t w = 0; w < T.nwait; ++w)
+                        ok &= wait_ge(A.ctr + T.wait_idx[w], T.wait_tgt[w], A.gerr);
+                }
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                s_pair = sg.pair;
+                s_stage = sg.stage;
+                s_u0 = u0;
+                s_cnt = cnt;
                 s_ok = ok;
             }
         }
         __syncthreads();
-        const int32_t kind = s_task.kind;
-        if (kind < 0) break;
+        const int32_t cnt = s_cnt;
+        if (cnt == 0) break;
+        const int32_t p = s_pair, st = s_stage, u0 = s_u0;
+        const PairRec &P = A.pairs[p];
         if (s_ok)
-            exec_task<H0>(A, A.ws + A.pairs[s_task.pair].ws_off, s_task.pair, kind, s_task.level,
-                          s_task.u, sm);
-        __syncthreads();
-        if (threadIdx.x == 0)
-            for (int32_t i = 0; i < s_task.nsig; ++i) signal(A.ctr + s_task.sig_idx[i]);
+            for (int32_t u = u0; u < u0 + cnt; ++u) {
+                exec_task<H0>(A, A.ws + P.ws_off, p, P.stage_kind[st], P.stage_level[st], u, sm);
+                __syncthreads();
+            }
+        if (threadIdx.x == 0) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            // raise the chunk's counters, equal consecutive ones at once
+            int32_t last = -1, run = 0;
+            for (int32_t u = u0; u < u0 + cnt; ++u) {
+                const Task T = decode_task(A.pairs, A.slots, p, st, u);
+                for (int32_t i = 0; i < T.nsig; ++i) {
+                    if (T.sig_idx[i] == last) {
+                        ++run;
+                        continue;
+                    }
+                    if (run) raise_ctr(A.ctr + last, run);
+                    last = T.sig_idx[i];
+                    run = 1;
+                }
+            }
+            if (run) raise_ctr(A.ctr + last, run);
+        }
         __syncthreads();
     }
 }
@@ -314,7 +357,6 @@ __global__ void __launch_bounds__(kBlock) k_pair_queue(BatchArgs A, const int32_
 struct StageArgs {
     int32_t kind, level, npairs;
     int32_t jchunk;         // weights per bracket task (the bracket shape's kJ)
-    int32_t base_mode;      // table form of the base-strip tasks (kBase*Mode)
     const int32_t *pair;    // participating pairs
     const int64_t *first;   // their first item, plus the total at [npairs]
 };
@@ -339,7 +381,7 @@ __global__ void __launch_bounds__(kBlock) k_stage(BatchArgs A, StageArgs S) {
         s_pu[1] = (int32_t)(t - S.first[lo]);
     }
     __syncthreads();
-    exec_task<H0>(A, A.ws + A.pairs[s_pu[0]].ws_off, s_pu[0], KIND, S.level, s_pu[1], sm);
+    exec_task<H0, false>(A, A.ws + A.pairs[s_pu[0]].ws_off, s_pu[0], KIND, S.level, s_pu[1], sm);
 }
 
 // Staged base-strip tasks (one strip x one 256-vertex block each) with the
@@ -363,22 +405,8 @@ __global__ void __launch_bounds__(kBlock) k_stage_base(BatchArgs A, StageArgs S)
         s_pu[1] = (int32_t)(t - S.first[lo]);
     }
     __syncthreads();
-    const int32_t p = s_pu[0], u = s_pu[1];
-    const PairRec &P = A.pairs[p];
-    uint8_t *ws = A.ws + P.ws_off;
-    int32_t *hdr = reinterpret_cast<int32_t *>(ws + P.off_hdr);
-    const int32_t *nm = reinterpret_cast<const int32_t *>(ws + P.off_nm);
-    const uint8_t *a = A.symbols + P.a_off;
-    const LevelGeom &g = P.lev[0];
-    const int32_t nvb = vertex_blocks(P.n);
-    const int32_t s0 = u / nvb;
-    const bool last = (s0 == g.nstrips - 1);
-    const int32_t h = last ? g.hlast : H0;
-    int32_t *out = reinterpret_cast<int32_t *>(ws + (last ? g.last_off : g.base)) +
-                   (last ? 0 : (size_t)s0 * strip_elems(P.n, H0));
-    const int32_t vb = u - s0 * nvb;
-    base_strip_block<H0, kMode>(a + (size_t)s0 * H0, h, P.n, A.sigma, nm, out, vb * kBlock, hdr,
-                                reinterpret_cast<int32_t *>(smem), smem);
+    const PairRec &P = A.pairs[s_pu[0]];
+    base_task<H0, kMode>(A, A.ws + P.ws_off, P, s_pu[1], reinterpret_cast<int32_t *>(smem), smem);
 }
 
 // Staged bracket tasks (one tile x one weight chunk each) in the bracket shape
@@ -403,27 +431,8 @@ k_stage_bracket(BatchArgs A, StageArgs S) {
         s_pu[1] = (int32_t)(t - S.first[lo]);
     }
     __syncthreads();
-    const int32_t p = s_pu[0], u = s_pu[1];
-    const PairRec &P = A.pairs[p];
-    uint8_t *ws = A.ws + P.ws_off;
-    const CombineArgs c = pair_combine_args(P, ws, S.level, A.tile);
-    const int32_t ntile = P.nanch - 1;
-    const int32_t Hf = 2 * P.lev[S.level - 1].hfull + 1;  // weights of a full-height parent
-    const int32_t nchl = imax(1, (Hf - 1 + C::kJ - 1) / C::kJ);
-    const int32_t qt = u / nchl;
-    const int32_t q = qt / ntile, tl = qt - q * ntile, ch = u - qt * nchl;
-    const StripRef U = child_strip(c, 2 * q), L = child_strip(c, 2 * q + 1);
-    int32_t *G = parent_strip(c, q);
-    const int32_t H = U.h + L.h + 1;
-    const int32_t nch = imax(1, (H - 1 + C::kJ - 1) / C::kJ);
-    if (ch >= nch) return;
-    const int32_t i0 = tl * A.tile;
-    const int32_t len = imin(A.tile, P.n - i0);
-    const int32_t *Ka = c.anch + ((size_t)q * c.nanch + tl) * (size_t)c.hs;
-    const int32_t *Kb = c.anch + ((size_t)q * c.nanch + tl + 1) * (size_t)c.hs;
-    const int32_t j0 = ch * C::kJ;
-    const int32_t jn = (ch == nch - 1) ? H - j0 : C::kJ;
-    bracket_block<C>(U.d, U.h, L.d, L.h, G, P.n, i0, len, j0, jn, Ka, Kb, sm);
+    const PairRec &P = A.pairs[s_pu[0]];
+    bracket_task<C>(A, A.ws + P.ws_off, P, S.level, s_pu[1], sm);
 }
 
 // Staged anchor search with the vertex's D_U row and k* row in dynamic LDS
@@ -560,7 +569,7 @@ static hipError_t launch_stage(const BatchArgs &A, const StageArgs &S, dim3 grid
         case ST_NM_SYM: hipLaunchKernelGGL((k_stage<H0, ST_NM_SYM>), grid, dim3(kBlock), 0, st, A, S); break;
         case ST_BASE_BLK:
             // table form by the plan's longest string (every pair's n is at most that)
-            if (S.base_mode == kBaseTab16Mode)
+            if (A.base_mode == kBaseTab16Mode)
                 hipLaunchKernelGGL((k_stage_base<H0, kBaseTab16Mode>), grid, dim3(kBlock), 0, st, A, S);
             else  // the generic step kernel keeps a smaller register allocation here
                 hipLaunchKernelGGL((k_stage<H0, ST_BASE_BLK>), grid, dim3(kBlock), 0, st, A, S);
@@ -750,7 +759,7 @@ extern "C" int32_t lcs_batch_destroy(lcs_batch_t b) {
 
 // Pair record: layout inside the slot, counters and task stages.
 static bool make_pair(const lcs_batch_s *B, const lcs_pair_desc &pd, int32_t p, int64_t wit_off,
-                      int64_t task_base, PairRec &R) {
+                      PairRec &R) {
     memset(&R, 0, sizeof(R));
     Layout L;
     if (!make_layout(pd.m, pd.n, B->d.alphabet, B->d.base_rows, B->d.tile, L)) return false;
@@ -759,7 +768,6 @@ static bool make_pair(const lcs_batch_s *B, const lcs_pair_desc &pd, int32_t p, 
     R.a_off = pd.a_off;
     R.b_off = pd.b_off;
     R.wit_off = wit_off;
-    R.task_base = task_base;
     R.off_hdr = L.off_hdr;
     R.off_nm = L.off_nm;
     R.total = L.total;
@@ -768,6 +776,9 @@ static bool make_pair(const lcs_batch_s *B, const lcs_pair_desc &pd, int32_t p, 
     R.nlev = (int32_t)L.lev.size();
     R.nanch = L.nanch;
     R.ctr_base = p * B->ctr_per_pair;
+    R.sigma = B->d.alphabet;
+    R.nvb = vertex_blocks_of(pd.n, kBlock);
+    R.jchunk = stage_jchunk(B->d.max_len);
     int32_t c = kCtrHead;
     for (int32_t l = 0; l < R.nlev; ++l) {
         R.lev[l] = L.lev[l];
@@ -787,11 +798,11 @@ static bool make_pair(const lcs_batch_s *B, const lcs_pair_desc &pd, int32_t p, 
     if (R.nlev == 0) {
         add(ST_EMPTY, 0, 1);
     } else {
-        add(ST_NM, 0, 1);
-        add(ST_BASE, 0, L.lev[0].nstrips);
+        add(ST_NM_SYM, 0, R.sigma);
+        add(ST_BASE_BLK, 0, L.lev[0].nstrips * R.nvb);
         for (int32_t l = 1; l < R.nlev; ++l) {
             add(ST_ANCHOR, l, L.lev[l].npairs * L.nanch);
-            add(ST_BRACKET, l, L.lev[l].npairs * (L.nanch - 1));
+            add(ST_BRACKET_CH, l, L.lev[l].npairs * (L.nanch - 1) * level_chunks_of(R, l));
         }
         add(ST_LENGTH, R.nlev - 1, 1);
         for (int32_t l = R.nlev - 1; l >= 1; --l) add(ST_SPLIT, l, L.lev[l].nstrips);
@@ -802,6 +813,45 @@ static bool make_pair(const lcs_batch_s *B, const lcs_pair_desc &pd, int32_t p, 
     R.ntasks = start;
     R.nctr = c;
     return R.nctr <= B->ctr_per_pair && R.total <= B->slot_bytes;
+}
+
+// Tasks per chunk of the persistent mode: a chunk pays one acquire and one
+// release (each a maintenance of the die's whole L2) instead of one per task,
+// and runs its tasks one after another in one work-group.
+constexpr int32_t kPersistChunk = 8;
+
+// Global task order of the persistent mode: for every wave of `slots` pairs,
+// the steps of the method in order (step_rank), and for each step the stage
+// of every pair of the wave that has it, cut into chunks of at most `chunk`
+// tasks.  Writes the segments (at most cap) and returns their number, or -1;
+// *nchunks and *ntasks = the totals.
+static int64_t build_segments(const PairRec *R, int32_t count, int32_t slots, int32_t chunk, Seg *segs,
+                              int64_t cap, int64_t *nchunks, int64_t *ntasks) {
+    int64_t ns = 0, g = 0, t = 0;
+    std::vector<int32_t> cur;
+    for (int32_t p0 = 0; p0 < count; p0 += slots) {
+        const int32_t p1 = std::min(count, p0 + slots);
+        cur.assign((size_t)(p1 - p0), 0);
+        for (int32_t r = 0; r <= step_rank(ST_LEAF, 0); ++r)
+            for (int32_t p = p0; p < p1; ++p) {
+                const PairRec &P = R[p];
+                int32_t &st = cur[(size_t)(p - p0)];
+                if (st >= P.nstages || step_rank(P.stage_kind[st], P.stage_level[st]) != r) continue;
+                const int32_t c = stage_tasks(P, st);
+                if (c > 0) {
+                    if (ns >= cap) return -1;
+                    segs[ns++] = Seg{g, p, st};
+                    g += (c + chunk - 1) / chunk;
+                    t += c;
+                }
+                ++st;
+            }
+        for (int32_t p = p0; p < p1; ++p)  // every stage placed (ranks increase along a pair)
+            if (cur[(size_t)(p - p0)] != R[p].nstages) return -1;
+    }
+    *nchunks = g;
+    *ntasks = t;
+    return ns;
 }
 
 static uint64_t mix(uint64_t h, uint64_t v) { return (h ^ v) * 0x100000001b3ull; }
@@ -859,12 +909,20 @@ extern "C" int32_t lcs_batch_submit(lcs_batch_t B, const lcs_pair_desc *pairs, i
     // The previous submit's copy of the staging records must have run before
     // they are rewritten.
     if (hipEventSynchronize(B->copied) != hipSuccess) return LCS_E_HIP;
-    int64_t woff = 0, tbase = 0;
-    uint64_t key = 0xcbf29ce484222325ull;
+    int64_t woff = 0, tbase = 0, nseg = 0, nchunks = 0;
+    uint64_t key = 0xcbf29ce484222325ull;  // graph key: the pairs' shapes, buffers and mode
     for (int32_t p = 0; p < count; ++p) {
-        if (!make_pair(B, pairs[p], p, woff, tbase, B->host_pairs[p])) return LCS_E_TOO_BIG;
+        if (!make_pair(B, pairs[p], p, woff, B->host_pairs[p])) return LCS_E_TOO_BIG;
         woff += pairs[p].m < pairs[p].n ? pairs[p].m : pairs[p].n;
         tbase += B->host_pairs[p].ntasks;
+        key = mix(mix(key, (uint64_t)pairs[p].m), (uint64_t)pairs[p].n);
+    }
+    if (!(mode & (LCS_BATCH_STAGED | LCS_BATCH_PAIR_QUEUE))) {  // persistent: the task order
+        int64_t total = 0;
+        nseg = build_segments(B->host_pairs, count, B->d.slots, kPersistChunk,
+                              reinterpret_cast<Seg *>(B->host_stage), B->stage_bytes / (int64_t)sizeof(Seg),
+                              &nchunks, &total);
+        if (nseg < 1 || total != tbase) return LCS_E_TOO_BIG;
     }
     // staged mode: pack the pairs' layouts into the slot area in waves and
     // list, per step, the items of every pair of the wave
@@ -958,7 +1016,8 @@ extern "C" int32_t lcs_batch_submit(lcs_batch_t B, const lcs_pair_desc *pairs, i
     A.pairs = reinterpret_cast<const PairRec *>(ws + B->off_pairs);
     A.npairs = count;
     A.slots = B->d.slots;
-    A.ntasks = tbase;
+    A.nchunks = nchunks;
+    A.chunk = kPersistChunk;
     A.ws = ws;
     A.symbols = symbols;
     A.lengths = lengths;
@@ -969,6 +1028,13 @@ extern "C" int32_t lcs_batch_submit(lcs_batch_t B, const lcs_pair_desc *pairs, i
     A.gerr = reinterpret_cast<int32_t *>(ws + B->off_ctl + 8);
     A.sigma = B->d.alphabet;
     A.tile = B->d.tile;
+    A.segs = reinterpret_cast<const Seg *>(ws + B->off_stage);
+    A.nseg = nseg;
+    switch (B->d.base_rows) {
+        case 16: A.base_mode = base_tab_mode<16>(B->d.max_len, B->d.alphabet); break;
+        case 32: A.base_mode = base_tab_mode<32>(B->d.max_len, B->d.alphabet); break;
+        default: A.base_mode = base_tab_mode<64>(B->d.max_len, B->d.alphabet); break;
+    }
     const int64_t nctr = (int64_t)B->ctr_per_pair * count;
     const int32_t grid = B->resident;
 
@@ -989,11 +1055,6 @@ extern "C" int32_t lcs_batch_submit(lcs_batch_t B, const lcs_pair_desc *pairs, i
                 S.level = sl.level;
                 S.npairs = sl.npairs;
                 S.jchunk = stage_jchunk(B->d.max_len);
-                switch (B->d.base_rows) {
-                    case 16: S.base_mode = base_tab_mode<16>(B->d.max_len, B->d.alphabet); break;
-                    case 32: S.base_mode = base_tab_mode<32>(B->d.max_len, B->d.alphabet); break;
-                    default: S.base_mode = base_tab_mode<64>(B->d.max_len, B->d.alphabet); break;
-                }
                 S.pair = reinterpret_cast<const int32_t *>(ws + B->off_stage + sl.pair_off);
                 S.first = reinterpret_cast<const int64_t *>(ws + B->off_stage + sl.first_off);
                 if (sl.items >= (int64_t)1 << 31) return LCS_E_TOO_BIG;
@@ -1025,6 +1086,9 @@ extern "C" int32_t lcs_batch_submit(lcs_batch_t B, const lcs_pair_desc *pairs, i
             }
             return hipGetLastError() == hipSuccess ? LCS_OK : LCS_E_HIP;
         }
+        if (hipMemcpyAsync(ws + B->off_stage, B->host_stage, sizeof(Seg) * (size_t)nseg,
+                           hipMemcpyHostToDevice, st) != hipSuccess)
+            return LCS_E_HIP;
         if (hipEventRecord(B->copied, st) != hipSuccess) return LCS_E_HIP;
         hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, st, reinterpret_cast<int32_t *>(ws + B->off_ctl),
                            (int64_t)16, 0);
@@ -1093,8 +1157,12 @@ extern "C" int32_t lcs_batch_status(lcs_batch_t B, void *workspace, void *stream
 // builds the pair records exactly as lcs_batch_submit does, then checks that
 //  - every counter index a task waits on or raises lies inside the counters of
 //    its own pair (or, for the slot-reuse wait, of the pair it waits for);
-//  - run one task at a time in task-number order, every wait is already met
-//    (so every dependency points to a smaller task number: the queue drains);
+//  - the task order's segments cover every stage of every pair once, in
+//    order, each with the chunks it needs;
+//  - run one stage at a time in that order, every wait of every task of the
+//    stage is already met by earlier stages (so every dependency points to a
+//    smaller chunk number and a chunk may wait for all its inputs before it
+//    runs: the queue drains);
 //  - every wait's target equals the total number of raises of its counter
 //    (a met wait proves that all of its producers have finished);
 //  - every task of a pair is an ancestor of that pair's finishing tasks, so
@@ -1114,15 +1182,37 @@ extern "C" int32_t lcs_batch_selftest(const lcs_batch_desc *desc, const lcs_pair
     for (int32_t p = 0; p < count; ++p) {
         if (pairs[p].m < 0 || pairs[p].n < 0 || pairs[p].m > b.d.max_len || pairs[p].n > b.d.max_len)
             return LCS_E_TOO_BIG;
-        if (!make_pair(&b, pairs[p], p, woff, tbase, R[p])) return LCS_E_STATE;
+        if (!make_pair(&b, pairs[p], p, woff, R[p])) return LCS_E_STATE;
         woff += pairs[p].m < pairs[p].n ? pairs[p].m : pairs[p].n;
         tbase += R[p].ntasks;
     }
+    std::vector<Seg> segs((size_t)count * kMaxStages + 1);
+    int64_t ntot = 0, nch = 0;
+    const int64_t nseg = count ? build_segments(R.data(), count, b.d.slots, kPersistChunk, segs.data(),
+                                                (int64_t)segs.size(), &nch, &ntot)
+                               : 0;
+    if (nseg < 0 || ntot != tbase) return LCS_E_STATE;
+    // every chunk number belongs to exactly one stage, in order, with the
+    // chunks that stage needs
+    for (int64_t i = 0; i < nseg; ++i) {
+        const Seg &g = segs[(size_t)i];
+        const int64_t end = i + 1 < nseg ? segs[(size_t)i + 1].start : nch;
+        if (end - g.start != (stage_tasks(R[g.pair], g.stage) + kPersistChunk - 1) / kPersistChunk)
+            return LCS_E_STATE;
+    }
+    // the tasks in the global order, stage by stage
     const int64_t nctr = (int64_t)b.ctr_per_pair * count;
     std::vector<int32_t> ctr((size_t)nctr, 0), total((size_t)nctr, 0);
     std::vector<Task> tasks((size_t)tbase);
+    std::vector<int64_t> first((size_t)nseg + 1, 0);  // first task of each stage
+    for (int64_t i = 0, t = 0; i < nseg; ++i) {
+        const Seg &g = segs[(size_t)i];
+        first[(size_t)i] = t;
+        for (int32_t u = 0; u < stage_tasks(R[g.pair], g.stage); ++u)
+            tasks[(size_t)t++] = decode_task(R.data(), b.d.slots, g.pair, g.stage, u);
+        first[(size_t)i + 1] = t;
+    }
     for (int64_t t = 0; t < tbase; ++t) {
-        tasks[t] = decode_task(R.data(), count, b.d.slots, t);
         const Task &T = tasks[t];
         const PairRec &P = R[T.pair];
         for (int32_t i = 0; i < T.nsig; ++i) {
@@ -1133,21 +1223,27 @@ extern "C" int32_t lcs_batch_selftest(const lcs_batch_desc *desc, const lcs_pair
     }
     // consumers of each counter, for the ancestor check
     std::vector<std::vector<int64_t>> consumers((size_t)nctr);
-    for (int64_t t = 0; t < tbase; ++t) {
-        const Task &T = tasks[t];
-        const PairRec &P = R[T.pair];
-        for (int32_t w = 0; w < T.nwait; ++w) {
-            const int32_t c = T.wait_idx[w];
-            if (c < 0 || c >= nctr) return LCS_E_STATE;
-            const bool own = c >= P.ctr_base && c < P.ctr_base + P.nctr;
-            const bool prev = (T.kind == ST_NM || T.kind == ST_EMPTY) && T.pair >= b.d.slots &&
-                              c == R[T.pair - b.d.slots].ctr_base + kCtrLeaves;
-            if (!own && !prev) return LCS_E_STATE;
-            if (ctr[c] < T.wait_tgt[w]) return LCS_E_STATE;       // not met in task order
-            if (T.wait_tgt[w] != total[c]) return LCS_E_STATE;    // met before all producers ran
-            if (own) consumers[c].push_back(t);
+    // run stage by stage: every wait of every task of a stage is met by the
+    // stages before it (so a chunk may wait for all of its tasks' inputs
+    // before it runs any of them), then the stage's raises are applied
+    for (int64_t i = 0; i < nseg; ++i) {
+        for (int64_t t = first[(size_t)i]; t < first[(size_t)i + 1]; ++t) {
+            const Task &T = tasks[t];
+            const PairRec &P = R[T.pair];
+            for (int32_t w = 0; w < T.nwait; ++w) {
+                const int32_t c = T.wait_idx[w];
+                if (c < 0 || c >= nctr) return LCS_E_STATE;
+                const bool own = c >= P.ctr_base && c < P.ctr_base + P.nctr;
+                const bool prev = (T.kind == ST_NM_SYM || T.kind == ST_EMPTY) && T.pair >= b.d.slots &&
+                                  c == R[T.pair - b.d.slots].ctr_base + kCtrLeaves;
+                if (!own && !prev) return LCS_E_STATE;
+                if (ctr[c] < T.wait_tgt[w]) return LCS_E_STATE;       // not met in stage order
+                if (T.wait_tgt[w] != total[c]) return LCS_E_STATE;    // met before all producers ran
+                if (own) consumers[c].push_back(t);
+            }
         }
-        for (int32_t i = 0; i < T.nsig; ++i) ++ctr[T.sig_idx[i]];
+        for (int64_t t = first[(size_t)i]; t < first[(size_t)i + 1]; ++t)
+            for (int32_t k = 0; k < tasks[t].nsig; ++k) ++ctr[tasks[t].sig_idx[k]];
     }
     // every task must lead (through its own pair's counters) to a finishing task
     std::vector<char> reach((size_t)tbase, 0);

@@ -1,12 +1,19 @@
 // Task schedule of the persistent batch kernel, shared by the device (decode
-// of a task number) and the host (construction of the per-pair records and a
-// sequential simulation that checks the schedule without a GPU).
+// of a task number) and the host (construction of the per-pair records and of
+// the task order, and a sequential simulation that checks the schedule
+// without a GPU).
 //
-// Tasks are numbered pair by pair; inside a pair the stages follow the
-// dependency order of the method: next-match tables, base strips, for every
-// combine level its anchors then its bracketed tiles, the length, the trace
-// splits from the top level down, the base-strip traces.  A task waits only on
-// counters raised by tasks with smaller numbers.
+// Each pair's work is a list of stages in the dependency order of the method:
+// next-match tables (one task per symbol), base strips (one task per strip and
+// 256-vertex block), for every combine level its anchors (one per anchor
+// vertex) then its bracketed tiles (one per tile and weight chunk), the
+// length, the trace splits from the top level down, the base-strip traces.
+// The global task order runs over waves of pairs (the pairs that hold the
+// workspace slots at one time): inside a wave, step by step of the method, the
+// stage of every pair of the wave that has this step, pair by pair.  A task
+// waits only on counters raised by tasks of earlier stages in this order, never
+// on a task of its own stage, so the kernel hands out chunks of consecutive
+// tasks of one stage and synchronises once per chunk.
 #pragma once
 #include <stddef.h>
 #include <stdint.h>
@@ -19,20 +26,19 @@ constexpr int kMaxLev = 16;
 constexpr int kMaxStages = 4 + 3 * kMaxLev;
 
 enum Stage : int32_t {
-    ST_EMPTY = 0,    // m == 0 or n == 0: length 0
-    ST_NM = 1,       // next-match tables (all symbols)
-    ST_BASE = 2,     // one base strip
-    ST_ANCHOR = 3,   // one anchor vertex of one combine
-    ST_BRACKET = 4,  // one tile (all weight chunks) of one combine
-    ST_LENGTH = 5,   // length + root trace node
-    ST_SPLIT = 6,    // one trace split
-    ST_LEAF = 7,     // trace inside one base strip
+    ST_EMPTY = 0,        // m == 0 or n == 0: length 0
+    ST_ANCHOR = 3,       // one anchor vertex of one combine
+    ST_LENGTH = 5,       // length + root trace node
+    ST_SPLIT = 6,        // one trace split
+    ST_LEAF = 7,         // trace inside one base strip
+    ST_NM_SYM = 16,      // next-match table of one symbol (u = symbol)
+    ST_BASE_BLK = 17,    // u = strip * vertex_blocks + block
+    ST_BRACKET_CH = 18,  // u = (q * tiles + tile) * chunks + chunk
 };
 
 struct PairRec {
     int64_t ws_off;  // byte offset of this pair's slot in the workspace
     int64_t a_off, b_off, wit_off;
-    int64_t task_base;  // first global task number of the pair
     int64_t off_hdr, off_nm, total;
     int64_t node_off[kMaxLev];
     int64_t anch_off[kMaxLev];
@@ -45,7 +51,22 @@ struct PairRec {
     int32_t ctr_base;
     int32_t m, n, nlev, nanch;
     int32_t ntasks, nctr;
+    int32_t sigma;   // next-match tasks (one per symbol)
+    int32_t nvb;     // 256-vertex blocks of a base strip
+    int32_t jchunk;  // weights per bracket task
 };
+
+// One stage of one pair in the global order, cut into chunks of at most
+// `chunk` consecutive tasks: its chunks are numbered start, start + 1, ...
+// The table is sorted by start.
+struct Seg {
+    int64_t start;  // global number of the stage's first chunk
+    int32_t pair, stage;
+};
+
+LCS_HD int32_t stage_tasks(const PairRec &P, int32_t st) {
+    return P.stage_start[st + 1] - P.stage_start[st];
+}
 
 // counters of a pair: [0] next-match done, [1] base-strip traces done, then
 // per level l: strip_done[S_l], anc_done[S_l], node_done[S_l]
@@ -57,6 +78,15 @@ struct Task {
     int32_t wait_idx[2], wait_tgt[2];  // absolute counter indices and targets
     int32_t sig_idx[2];
 };
+
+LCS_HD int32_t vertex_blocks_of(int32_t n, int32_t block) { return (n + 2 + block - 1) / block; }
+
+// weight chunks of every bracket tile of level l (a full-height parent)
+LCS_HD int32_t level_chunks_of(const PairRec &P, int32_t l) {
+    const int32_t w = 2 * P.lev[l - 1].hfull;  // weights of a full-height parent, minus one
+    const int32_t c = (w + P.jchunk - 1) / P.jchunk;
+    return c > 1 ? c : 1;
+}
 
 // "the work of pair Q is over": its base-strip traces have all run, or its
 // single empty-pair task has
@@ -70,40 +100,40 @@ LCS_HD void strip_done_ctr(const PairRec &P, int32_t l, int32_t s, int32_t *idx,
         --l;
     }
     *idx = P.ctr_base + P.ctr_lev[l] + s;
-    *tgt = (l == 0) ? 1 : P.nanch - 1;  // one base task, or one bracket task per tile
+    // its base blocks, or its bracket tasks (tiles x weight chunks)
+    *tgt = (l == 0) ? P.nvb : (P.nanch - 1) * level_chunks_of(P, l);
 }
 
-LCS_HD int32_t find_pair(const PairRec *pairs, int32_t npairs, int64_t t) {
-    int32_t lo = 0, hi = npairs - 1;
+// the segment holding chunk t (the last one with start <= t)
+LCS_HD int32_t find_seg(const Seg *segs, int64_t nseg, int64_t t) {
+    int64_t lo = 0, hi = nseg - 1;
     while (lo < hi) {
-        const int32_t mid = (lo + hi + 1) >> 1;
-        if (pairs[mid].task_base <= t)
+        const int64_t mid = (lo + hi + 1) >> 1;
+        if (segs[mid].start <= t)
             lo = mid;
         else
             hi = mid - 1;
     }
-    return lo;
+    return (int32_t)lo;
 }
 
-// Everything task t waits on and signals.
-LCS_HD Task decode_task(const PairRec *pairs, int32_t npairs, int32_t slots, int64_t t) {
+// Everything task u of stage st of pair p waits on and signals.
+LCS_HD Task decode_task(const PairRec *pairs, int32_t slots, int32_t p, int32_t st, int32_t u) {
     Task T;
-    const int32_t p = find_pair(pairs, npairs, t);
     const PairRec &P = pairs[p];
-    const int32_t local = (int32_t)(t - P.task_base);
-    int32_t st = 0;
-    while (st + 1 < P.nstages && P.stage_start[st + 1] <= local) ++st;
     T.pair = p;
     T.kind = P.stage_kind[st];
     T.level = P.stage_level[st];
-    T.u = local - P.stage_start[st];
+    T.u = u;
     T.nwait = 0;
     T.nsig = 0;
     const int32_t cb = P.ctr_base;
-    const int32_t l = T.level, u = T.u;
+    const int32_t l = T.level;
     switch (T.kind) {
         case ST_EMPTY:
-        case ST_NM:
+        case ST_NM_SYM:
+            // every task of the first stage writes into the slot: all of them
+            // wait until its previous occupant is done
             if (p >= slots) {
                 const PairRec &Q = pairs[p - slots];
                 T.wait_idx[T.nwait] = Q.ctr_base + kCtrLeaves;
@@ -111,10 +141,10 @@ LCS_HD Task decode_task(const PairRec *pairs, int32_t npairs, int32_t slots, int
             }
             T.sig_idx[T.nsig++] = cb + (T.kind == ST_EMPTY ? kCtrLeaves : kCtrNm);
             break;
-        case ST_BASE:
+        case ST_BASE_BLK:
             T.wait_idx[T.nwait] = cb + kCtrNm;
-            T.wait_tgt[T.nwait++] = 1;
-            T.sig_idx[T.nsig++] = cb + P.ctr_lev[0] + u;
+            T.wait_tgt[T.nwait++] = P.sigma;
+            T.sig_idx[T.nsig++] = cb + P.ctr_lev[0] + u / P.nvb;
             break;
         case ST_ANCHOR: {
             const int32_t q = u / P.nanch;
@@ -124,8 +154,8 @@ LCS_HD Task decode_task(const PairRec *pairs, int32_t npairs, int32_t slots, int
             T.sig_idx[T.nsig++] = cb + P.ctr_lev[l] + P.lev[l].nstrips + q;
             break;
         }
-        case ST_BRACKET: {
-            const int32_t q = u / (P.nanch - 1);
+        case ST_BRACKET_CH: {
+            const int32_t q = u / ((P.nanch - 1) * level_chunks_of(P, l));
             T.wait_idx[T.nwait] = cb + P.ctr_lev[l] + P.lev[l].nstrips + q;
             T.wait_tgt[T.nwait++] = P.nanch;
             T.sig_idx[T.nsig++] = cb + P.ctr_lev[l] + q;
@@ -151,6 +181,21 @@ LCS_HD Task decode_task(const PairRec *pairs, int32_t npairs, int32_t slots, int
             break;
     }
     return T;
+}
+
+// Position of a (kind, level) step in the method's order, the same for
+// every pair; a pair's own stages are in increasing rank.
+LCS_HD int32_t step_rank(int32_t kind, int32_t level) {
+    switch (kind) {
+        case ST_EMPTY: return 0;
+        case ST_NM_SYM: return 1;
+        case ST_BASE_BLK: return 2;
+        case ST_ANCHOR: return 3 + 2 * (level - 1);
+        case ST_BRACKET_CH: return 4 + 2 * (level - 1);
+        case ST_LENGTH: return 3 + 2 * kMaxLev;
+        case ST_SPLIT: return 4 + 2 * kMaxLev + (kMaxLev - 1 - level);
+        default: return 4 + 3 * kMaxLev;  // ST_LEAF
+    }
 }
 
 }  // namespace lcs
