@@ -261,8 +261,14 @@ __device__ __forceinline__ void exec_task(const BatchArgs &A, uint8_t *ws, int32
     }
 }
 
+// One kernel runs every kind of task, so it would carry the largest register
+// allocation of them all (the base strip's, about 210 VGPRs: 2 waves per
+// SIMD).  It is held to 4 waves per SIMD instead; the base-strip task then
+// spills a little, and the latency-bound bracket tasks, most of the work,
+// have twice the waves in flight.
 template <int H0>
-__global__ void __launch_bounds__(kBlock) k_persistent(BatchArgs A) {
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4)))
+k_persistent(BatchArgs A) {
     __shared__ PersistentSmem sm;
     __shared__ int32_t s_pair, s_stage, s_u0, s_cnt, s_ok;
     for (;;) {
@@ -818,7 +824,7 @@ static bool make_pair(const lcs_batch_s *B, const lcs_pair_desc &pd, int32_t p, 
 // Tasks per chunk of the persistent mode: a chunk pays one acquire and one
 // release (each a maintenance of the die's whole L2) instead of one per task,
 // and runs its tasks one after another in one work-group.
-constexpr int32_t kPersistChunk = 8;
+constexpr int32_t kPersistChunk = 16;
 
 // Global task order of the persistent mode: for every wave of `slots` pairs,
 // the steps of the method in order (step_rank), and for each step the stage
