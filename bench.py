@@ -131,7 +131,7 @@ def bench_batched(reps: int):
                        ("one_pair_per_launch", lcs.BATCH_PER_PAIR)):
         plan.submit(sym, batch.a_off, batch.b_off, batch.m, batch.n, ws, lengths, ai, bi, mode)
         torch.cuda.synchronize()
-        n = reps if mode & (lcs.BATCH_STAGED | lcs.BATCH_PAIR_QUEUE) else 1
+        n = 1 if mode & lcs.BATCH_PER_PAIR else reps
         t0 = time.perf_counter()
         for _ in range(n):
             plan.submit(sym, batch.a_off, batch.b_off, batch.m, batch.n, ws, lengths, ai, bi, mode)
