@@ -299,3 +299,29 @@ def test_config_16384_mutated():
     for k in range(0, p.b.size + 1, 97):
         assert int(np.sum(D0 <= k)) - 1 == row[k]
     _top_rows_check(p.a, p.b, plan, ws, [16300, 16383, 16384])
+
+
+def test_wide_rows_across_16bit_limits():
+    """Rows as wide as the 16-bit shapes allow and just beyond: the base strips
+    keep their next-match window in 16-bit LDS entries while n + 2 <= 65535,
+    and the bracketed combine keeps 16-bit state while n + 1 <= 65535; at
+    n = 65535 and above both take their 32-bit forms.  Length, witness and
+    sampled breakout rows of every level against the oracle."""
+    r = np.random.default_rng(65535)
+    m = 1000
+    a = r.integers(0, 4, m).astype(np.uint8)
+    for n in (65533, 65534, 65535, 70001):
+        b = r.integers(0, 4, n).astype(np.uint8)
+        b[n - 1500:n - 500] = a[r.permutation(m)]   # a shuffled copy of a near the end
+        say("wide rows", m, n)
+        Lg, plan, ws = check_against_oracle(a, b, 4, base_rows=64, tile=32)
+        verts = [0, 1, 63, 64, 65, n // 2, n - 1600, n - 1000, n - 700, n - 65, n - 1, n]
+        for lv, cnt in enumerate(plan.levels()):
+            for s in sorted({0, cnt - 1}):
+                D, row0 = plan.dist(lv, s, ws)
+                h = D.shape[1] - 1
+                got = D[verts].cpu().numpy()
+                want = oracle.dist_rows(a, row0, row0 + h, b, verts)
+                bad = np.argwhere(got != want)
+                assert bad.size == 0, "n %d level %d strip %d vertex %d weight %d got %d want %d" % (
+                    n, lv, s, verts[bad[0][0]], bad[0][1], got[tuple(bad[0])], want[tuple(bad[0])])
