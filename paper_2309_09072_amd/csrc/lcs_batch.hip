@@ -157,7 +157,7 @@ __device__ __forceinline__ void base_task(const BatchArgs &A, uint8_t *ws, const
 
 // Bracket task u of level l of pair P (one tile x one weight chunk of C::kJ
 // weights; a chunk beyond a short last strip's weights does nothing).
-template <class C>
+template <class C, bool kCoop = false>
 __device__ __forceinline__ void bracket_task(const BatchArgs &A, uint8_t *ws, const PairRec &P,
                                              int32_t l, int32_t u, BracketSmemT<C> &sm) {
     const CombineArgs c = pair_combine_args(P, ws, l, A.tile);
@@ -177,7 +177,7 @@ __device__ __forceinline__ void bracket_task(const BatchArgs &A, uint8_t *ws, co
     const int32_t *Kb = c.anch + ((size_t)q * c.nanch + tl + 1) * (size_t)c.hs;
     const int32_t j0 = ch * C::kJ;
     const int32_t jn = (ch == nch - 1) ? H - j0 : C::kJ;
-    bracket_block<C>(U.d, U.h, L.d, L.h, G, P.n, i0, len, j0, jn, Ka, Kb, sm);
+    bracket_block<C, kCoop>(U.d, U.h, L.d, L.h, G, P.n, i0, len, j0, jn, Ka, Kb, sm);
 }
 
 // One task of pair p (all threads of the work-group).  kAll: every table
@@ -418,7 +418,7 @@ __global__ void __launch_bounds__(kBlock) k_stage_base(BatchArgs A, StageArgs S)
 // Staged bracket tasks (one tile x one weight chunk each) in the bracket shape
 // C: the 16-bit one (64 weights per task) when every pair of the plan fits
 // 16-bit values, as in the single-pair path, with the same 64-VGPR limit.
-template <int H0, class C>
+template <int H0, class C, bool kCoop = false>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8)))
 k_stage_bracket(BatchArgs A, StageArgs S) {
     __shared__ BracketSmemT<C> sm;
@@ -438,7 +438,7 @@ k_stage_bracket(BatchArgs A, StageArgs S) {
     }
     __syncthreads();
     const PairRec &P = A.pairs[s_pu[0]];
-    bracket_task<C>(A, A.ws + P.ws_off, P, S.level, s_pu[1], sm);
+    bracket_task<C, kCoop>(A, A.ws + P.ws_off, P, S.level, s_pu[1], sm);
 }
 
 // Staged anchor search with the vertex's D_U row and k* row in dynamic LDS
@@ -582,7 +582,9 @@ static hipError_t launch_stage(const BatchArgs &A, const StageArgs &S, dim3 grid
             break;
         case ST_ANCHOR: hipLaunchKernelGGL((k_stage<H0, ST_ANCHOR>), grid, dim3(kBlock), 0, st, A, S); break;
         case ST_BRACKET_CH:
-            if (S.jchunk == BracketCfg16::kJ)
+            if (S.jchunk == BracketCfg16::kJ && S.level >= 1 && (H0 << (S.level - 1)) >= kCoopPass2MinH)
+                hipLaunchKernelGGL((k_stage_bracket<H0, BracketCfg16Mid, true>), grid, dim3(kBlock), 0, st, A, S);
+            else if (S.jchunk == BracketCfg16::kJ)
                 hipLaunchKernelGGL((k_stage_bracket<H0, BracketCfg16>), grid, dim3(kBlock), 0, st, A, S);
             else
                 hipLaunchKernelGGL((k_stage_bracket<H0, BracketCfg32>), grid, dim3(kBlock), 0, st, A, S);
