@@ -94,6 +94,12 @@ __device__ bool wait_ge(const int32_t *p, int32_t target, int32_t *gerr) {
     return true;
 }
 
+// A value every lane of the wave holds alike (read from LDS, or derived from
+// the wave index): taken from the first lane, so that the compiler keeps it
+// and everything derived from it (pair record fields, matrix addresses,
+// sizes) in scalar registers.
+__device__ __forceinline__ int32_t uniform(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
 __device__ __forceinline__ void raise_ctr(int32_t *p, int32_t v) {
     __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -296,11 +302,11 @@ k_persistent(BatchArgs A) {
             }
         }
         __syncthreads();
-        const int32_t cnt = s_cnt;
+        const int32_t cnt = uniform(s_cnt);
         if (cnt == 0) break;
-        const int32_t p = s_pair, st = s_stage, u0 = s_u0;
+        const int32_t p = uniform(s_pair), st = uniform(s_stage), u0 = uniform(s_u0);
         const PairRec &P = A.pairs[p];
-        if (s_ok)
+        if (uniform(s_ok))
             for (int32_t u = u0; u < u0 + cnt; ++u) {
                 exec_task<H0>(A, A.ws + P.ws_off, p, P.stage_kind[st], P.stage_level[st], u, sm);
                 __syncthreads();
@@ -341,7 +347,7 @@ __global__ void __launch_bounds__(kBlock) k_pair_queue(BatchArgs A, const int32_
     for (;;) {
         if (threadIdx.x == 0) s_q = (int32_t)atomicAdd(A.next, 1ull);
         __syncthreads();
-        const int32_t q = s_q;
+        const int32_t q = uniform(s_q);
         __syncthreads();
         if (q >= A.npairs) break;
         const int32_t p = order[q];
@@ -387,7 +393,8 @@ __global__ void __launch_bounds__(kBlock) k_stage(BatchArgs A, StageArgs S) {
         s_pu[1] = (int32_t)(t - S.first[lo]);
     }
     __syncthreads();
-    exec_task<H0, false>(A, A.ws + A.pairs[s_pu[0]].ws_off, s_pu[0], KIND, S.level, s_pu[1], sm);
+    const int32_t p = uniform(s_pu[0]), u = uniform(s_pu[1]);
+    exec_task<H0, false>(A, A.ws + A.pairs[p].ws_off, p, KIND, S.level, u, sm);
 }
 
 // Staged base-strip tasks (one strip x one 256-vertex block each) with the
@@ -411,8 +418,8 @@ __global__ void __launch_bounds__(kBlock) k_stage_base(BatchArgs A, StageArgs S)
         s_pu[1] = (int32_t)(t - S.first[lo]);
     }
     __syncthreads();
-    const PairRec &P = A.pairs[s_pu[0]];
-    base_task<H0, kMode>(A, A.ws + P.ws_off, P, s_pu[1], reinterpret_cast<int32_t *>(smem), smem);
+    const PairRec &P = A.pairs[uniform(s_pu[0])];
+    base_task<H0, kMode>(A, A.ws + P.ws_off, P, uniform(s_pu[1]), reinterpret_cast<int32_t *>(smem), smem);
 }
 
 // Staged bracket tasks (one tile x one weight chunk each) in the bracket shape
@@ -437,15 +444,18 @@ k_stage_bracket(BatchArgs A, StageArgs S) {
         s_pu[1] = (int32_t)(t - S.first[lo]);
     }
     __syncthreads();
-    const PairRec &P = A.pairs[s_pu[0]];
-    bracket_task<C, kCoop>(A, A.ws + P.ws_off, P, S.level, s_pu[1], sm);
+    const PairRec &P = A.pairs[uniform(s_pu[0])];
+    bracket_task<C, kCoop>(A, A.ws + P.ws_off, P, S.level, uniform(s_pu[1]), sm);
 }
 
 // Staged anchor search with the vertex's D_U row and k* row in dynamic LDS
 // (the search's AnchorSmem, hc + 1 and 2 hc + 1 int32; hc = child strip height, the
 // same for every pair at one level).
+// (Left to itself the compiler gives this kernel 184 VGPRs, 2 waves per
+// SIMD; the search fits in 80 without spills, as in the single-pair path.)
 template <int H0>
-__global__ void __launch_bounds__(kBlock) k_stage_anchor_lds(BatchArgs A, StageArgs S, int32_t hc) {
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6)))
+k_stage_anchor_lds(BatchArgs A, StageArgs S, int32_t hc) {
     extern __shared__ unsigned long long dyn[];
     __shared__ int32_t s_pu[2];
     const int64_t t = blockIdx.x;
@@ -462,7 +472,7 @@ __global__ void __launch_bounds__(kBlock) k_stage_anchor_lds(BatchArgs A, StageA
         s_pu[1] = (int32_t)(t - S.first[lo]);
     }
     __syncthreads();
-    const int32_t p = s_pu[0], u = s_pu[1];
+    const int32_t p = uniform(s_pu[0]), u = uniform(s_pu[1]);
     const PairRec &P = A.pairs[p];
     uint8_t *ws = A.ws + P.ws_off;
     const CombineArgs c = pair_combine_args(P, ws, S.level, A.tile);
@@ -489,7 +499,7 @@ template <int CPT>
 __global__ void __launch_bounds__(kBlock) k_stage_anchor_wave(BatchArgs A, StageArgs S, int32_t hc,
                                                               int32_t bytes, int64_t items) {
     extern __shared__ unsigned long long dyn[];
-    const int32_t wv = (int32_t)threadIdx.x / kWave;
+    const int32_t wv = uniform((int32_t)threadIdx.x / kWave);  // the same on every lane of a wave
     const int64_t t = (int64_t)blockIdx.x * kWaves + wv;
     if (t >= items) return;
     int32_t lo = 0, hi = S.npairs - 1;
