@@ -639,7 +639,7 @@ __device__ __forceinline__ void anchor_block(const int32_t *__restrict__ U, int3
 constexpr int kCoarseItems = kBlock / 2;  // a level with at most this many outputs is coarse
 constexpr int kCoarseBatch = 8;  // consecutive candidates per thread slice of a coarse level
 constexpr int kPass2Batch = 8;   // candidates per batch of pass 2, one thread per output
-constexpr int32_t kCoopPass2MinH = 1024;  // child strip height from which pass 2 is cooperative
+constexpr int32_t kCoopPass2MinH = 512;  // child strip height from which pass 2 is cooperative
 constexpr int32_t kWideWindowMinH = 2048;  // child strip height from which the D_U window is wide
 // Shape of a bracket work-group: LDS state type, weights per block, width of
 // the D_U parallelogram.  32-bit state: any size.  16-bit state (values and
@@ -655,7 +655,7 @@ struct BracketCfg {
 };
 using BracketCfg32 = BracketCfg<int32_t, 32, 64>;
 using BracketCfg16 = BracketCfg<uint16_t, 64, 98>;
-using BracketCfg16Mid = BracketCfg<uint16_t, 64, 128, 6>;  // 1024+ rows: still 8 work-groups per CU
+using BracketCfg16Mid = BracketCfg<uint16_t, 64, 128, 6>;  // 512+ rows: still 8 work-groups per CU
 using BracketCfg16Wide = BracketCfg<uint16_t, 64, 160>;  // tall strips: wider D_U window
 
 template <class C>

@@ -270,7 +270,7 @@ def test_config_4096():
     # sampled rows of the top matrix (the oracle computes one row per dynamic program)
     _top_rows_check(p.a, p.b, plan, ws, [0, 1, 63, 64, 65, 2048, 4000, 4095, 4096])
     # sampled rows of every level's first and last strip; the top two levels
-    # (the bracket shapes of 1024- and 2048-row strips: 128- and 160-wide D_U
+    # (the bracket shapes of 1024- and 2048-row child strips: 128- and 160-wide D_U
     # windows, cooperative pass 2) at vertices around tile boundaries and
     # spread over the row range
     rng = np.random.default_rng(4096)
