@@ -592,7 +592,10 @@ static hipError_t launch_stage(const BatchArgs &A, const StageArgs &S, dim3 grid
             break;
         case ST_ANCHOR: hipLaunchKernelGGL((k_stage<H0, ST_ANCHOR>), grid, dim3(kBlock), 0, st, A, S); break;
         case ST_BRACKET_CH:
-            if (S.jchunk == BracketCfg16::kJ && S.level >= 1 && (H0 << (S.level - 1)) >= kCoopPass2MinH)
+            // the single-pair path's shape for the level's child strip height
+            if (S.jchunk == BracketCfg16::kJ && S.level >= 1 && (H0 << (S.level - 1)) >= kWideWindowMinH)
+                hipLaunchKernelGGL((k_stage_bracket<H0, BracketCfg16Wide, true>), grid, dim3(kBlock), 0, st, A, S);
+            else if (S.jchunk == BracketCfg16::kJ && S.level >= 1 && (H0 << (S.level - 1)) >= kCoopPass2MinH)
                 hipLaunchKernelGGL((k_stage_bracket<H0, BracketCfg16Mid, true>), grid, dim3(kBlock), 0, st, A, S);
             else if (S.jchunk == BracketCfg16::kJ)
                 hipLaunchKernelGGL((k_stage_bracket<H0, BracketCfg16>), grid, dim3(kBlock), 0, st, A, S);

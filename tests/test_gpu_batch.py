@@ -128,3 +128,20 @@ def test_mixed_workload_sample():
     for mode in (L.BATCH_STAGED, L.BATCH_PERSISTENT, L.BATCH_PAIR_QUEUE):
         res = L.run_batch(batch, mode, 64, 32, 0)
         check(batch, *res)
+
+
+def test_tall_pairs_every_bracket_shape():
+    """Pairs tall enough for child strips of 512, 1024 and 2048 rows (the
+    cooperative and wide-window bracket shapes) next to a short one, in every
+    one-launch mode."""
+    r = np.random.default_rng(4200)
+    a0 = r.integers(0, 4, 4200).astype(np.uint8)
+    b0 = synth.fit_length(r, synth.mutate(r, a0, 4, 0.1, 0.05, 0.05), 3000, 4)
+    a1 = r.integers(0, 4, 2500).astype(np.uint8)
+    b1 = r.integers(0, 4, 2600).astype(np.uint8)
+    a2 = r.integers(0, 4, 100).astype(np.uint8)
+    b2 = r.integers(0, 4, 90).astype(np.uint8)
+    batch = synth.batch_from_pairs([(a0, b0), (a1, b1), (a2, b2)], 4, 4200, "tall")
+    for mode in (L.BATCH_STAGED, L.BATCH_PERSISTENT, L.BATCH_PAIR_QUEUE):
+        say("tall pairs, mode", mode)
+        check(batch, *L.run_batch(batch, mode, 64, 32, 0))
