@@ -246,7 +246,9 @@ typedef struct lcs_pair_desc {
     int32_t n;
 } lcs_pair_desc;
 
-#define LCS_BATCH_PERSISTENT 0u /* one persistent launch drains a device work queue */
+#define LCS_BATCH_PERSISTENT 0u /* one persistent launch drains a device work queue of
+                                   the staged mode's items, step by step across the
+                                   pairs that hold the slots, in chunks of one stage */
 #define LCS_BATCH_PER_PAIR 1u   /* same kernels, launched pair after pair */
 #define LCS_BATCH_GRAPH 2u      /* OR-able: replay the launch as a captured hipGraph */
 #define LCS_BATCH_STAGED 4u     /* one launch per step of the method across all pairs
@@ -310,12 +312,15 @@ int32_t lcs_batch_status(lcs_batch_t batch, void *workspace, void *stream);
 
 /*
  * Host simulation of the persistent schedule for `count` pairs (no device
- * work; for tests): builds the task records as lcs_batch_submit does and
- * checks, running the tasks one at a time in task order, that every wait is
- * already met, that every wait target equals the number of producers of its
- * counter, that every task of a pair leads to the pair's finish (so reuse of
- * a workspace slot is ordered after all work of its previous pair) and that
- * each pair's layout fits its slot.  LCS_OK, or LCS_E_STATE on a defect.
+ * work; for tests): builds the task records and the task order as
+ * lcs_batch_submit does and checks that the order covers every stage of every
+ * pair once, that, running the order one stage at a time, every wait of a
+ * stage's tasks is already met by earlier stages (so a chunk of one stage can
+ * wait for all of its inputs first), that every wait target equals the number
+ * of producers of its counter, that every task of a pair leads to the pair's
+ * finish (so reuse of a workspace slot is ordered after all work of its
+ * previous pair) and that each pair's layout fits its slot.  LCS_OK, or
+ * LCS_E_STATE on a defect.
  */
 int32_t lcs_batch_selftest(const lcs_batch_desc *desc, const lcs_pair_desc *pairs, int32_t count);
 
