@@ -121,8 +121,8 @@ __device__ __forceinline__ CombineArgs pair_combine_args(const PairRec &P, uint8
     a.nanch = P.nanch;
     a.hs = 2 * c.hfull + 1;
     a.anch = reinterpret_cast<int32_t *>(ws + P.anch_off[l]);
-    a.jchunk = kJChunk;
-    a.nchunks = 0;
+    a.jchunk = P.jchunk;
+    a.nchunks = imax(1, (a.hs - 1 + a.jchunk - 1) / a.jchunk);
     return a;
 }
 

@@ -17,7 +17,6 @@ namespace lcs {
 constexpr int kBlock = 256;  // threads per work-group for every task
 constexpr int kWave = 64;
 constexpr int kWaves = kBlock / kWave;
-constexpr int kJChunk = 32;  // weights per bracket block (a block may take kJChunk + 1)
 constexpr int kBatch = 8;    // candidates whose loads are issued together
 constexpr int kAnchorEval = 8;  // anchor search: candidates per thread per depth
 constexpr int kMaxTile = 32;
