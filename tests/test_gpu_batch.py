@@ -145,3 +145,14 @@ def test_tall_pairs_every_bracket_shape():
     for mode in (L.BATCH_STAGED, L.BATCH_PERSISTENT, L.BATCH_PAIR_QUEUE):
         say("tall pairs, mode", mode)
         check(batch, *L.run_batch(batch, mode, 64, 32, 0))
+
+
+@pytest.mark.parametrize("sigma", [20, 256])
+def test_large_alphabets_every_mode(sigma):
+    """Alphabets whose next-match stage spans several chunks of the persistent
+    task queue (one task per symbol, 16 per chunk), and at 256 symbols base
+    strips with the global next-match tables; fewer slots than pairs."""
+    batch = mixed_small(30, 90 + sigma, maxlen=400, sigma=sigma)
+    for mode in (L.BATCH_PERSISTENT, L.BATCH_STAGED, L.BATCH_PAIR_QUEUE):
+        say("alphabet", sigma, "mode", mode)
+        check(batch, *L.run_batch(batch, mode, 32, 16, 5))
