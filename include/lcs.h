@@ -360,11 +360,16 @@ typedef struct lcs_result {
 int32_t lcs_server_open(const lcs_server_desc *desc, void *arena, size_t arena_bytes,
                         lcs_server_t *out);
 
-/* Arena bytes a request of sizes (m, n) occupies while it runs. */
+/* Arena bytes a request of sizes (m, n) occupies while it runs, at most (the
+   next-match tables are sized for the server's largest alphabet here; a request
+   of a smaller alphabet takes a little less). */
 int32_t lcs_server_footprint(lcs_server_t server, int32_t m, int32_t n, size_t *bytes);
 
 /*
- * Queue one request.  a and b are HOST strings (copied at submit); a_idx and
+ * Queue one request.  a and b are HOST strings (copied at submit) over the
+ * request's own alphabet (1..the server's alphabet): its build uses that many
+ * next-match tables, and a symbol >= alphabet ends the request with status
+ * LCS_E_SYMBOL.  a_idx and
  * b_idx are device int32 arrays of at least min(m, n) entries that receive the
  * witness (both NULL: length only).  The request runs on a stream of the
  * server, so the caller must have no pending device work on a_idx / b_idx

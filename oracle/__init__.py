@@ -12,6 +12,8 @@ Functions and the passage each one follows:
 * ``lcs_witness``    -- the same table plus a LEFT > DIAG > UP walk back from
   (m, n): the optimal path that enters every row as far left as possible
   (the cross vertices of Section II-C taken leftmost; the tie rule of Alg. 2).
+* ``path_rows``      -- every vertex of that canonical path, row by row: the
+  first and last column it visits on each grid row (Section II-E).
 * ``dist_rows``      -- the breakout matrix D_G by its definition
   (Section II-B-1), one fresh dynamic program per vertex.
 * ``base_row``       -- the two-row base case D_{G_h} by the steps of
@@ -57,6 +59,8 @@ def _bind(path: str):
     lib.oracle_lcs_last_row.argtypes = [p, i64, p, i64, p]
     lib.oracle_lcs_witness.restype = i64
     lib.oracle_lcs_witness.argtypes = [p, i64, p, i64, p, p]
+    lib.oracle_path_rows.restype = i64
+    lib.oracle_path_rows.argtypes = [p, i64, p, i64, p, p]
     lib.oracle_dist_rows.restype = ctypes.c_int
     lib.oracle_dist_rows.argtypes = [p, i64, i64, p, i64, p, i64, p]
     lib.oracle_base_row.restype = i64
@@ -113,6 +117,18 @@ def lcs_witness(a, b, lib=None):
     if L < 0:
         raise MemoryError("oracle_lcs_witness: table does not fit in host memory")
     return int(L), ai[:L].copy(), bi[:L].copy()
+
+
+def path_rows(a, b, lib=None):
+    """(col_in, col_out), int32[m + 1] each: on grid row r the canonical path
+    (the one lcs_witness's walk follows) enters at column col_in[r] and leaves
+    at col_out[r] (Section II-E: the vertices between the cross vertices)."""
+    a, b = _u8(a), _u8(b)
+    cin = np.zeros(a.size + 1, dtype=np.int32)
+    cout = np.zeros(a.size + 1, dtype=np.int32)
+    if (lib or _load()).oracle_path_rows(_ptr(a), a.size, _ptr(b), b.size, _ptr(cin), _ptr(cout)) < 0:
+        raise MemoryError("oracle_path_rows: table does not fit in host memory")
+    return cin, cout
 
 
 def dist_rows(a, r0: int, r1: int, b, verts=None, lib=None) -> np.ndarray:

@@ -58,3 +58,46 @@ def common_subsequences_of_length(a, b, k):
         if s not in out and is_subsequence(s, b):
             out.add(s)
     return out
+
+
+def max_paths(a, b):
+    """Every heaviest monotone path of the grid graph (Section II-A), enumerated
+    move by move: right, down, or the weight-1 diagonal where a[r] == b[c].
+    Each path is returned as its (col_in, col_out) per grid row r = 0..m.
+    For tiny strings only (the count of paths grows exponentially)."""
+    a, b = list(a), list(b)
+    m, n = len(a), len(b)
+    best, found = -1, []
+
+    def walk(r, c, w, rows):
+        nonlocal best, found
+        rows[r][0] = min(rows[r][0], c)
+        rows[r][1] = max(rows[r][1], c)
+        if r == m and c == n:
+            if w > best:
+                best, found = w, []
+            if w == best:
+                found.append(tuple((x, y) for x, y in rows))
+            return
+        if c < n:
+            walk(r, c + 1, w, [list(x) for x in rows])
+        if r < m:
+            nxt = [list(x) for x in rows]
+            walk(r + 1, c, w, nxt)
+            if c < n and a[r] == b[c]:
+                walk(r + 1, c + 1, w + 1, [list(x) for x in rows])
+
+    walk(0, 0, 0, [[n + 1, -1] for _ in range(m + 1)])
+    return best, found
+
+
+def leftmost_path_rows(a, b):
+    """(L, col_in, col_out) of the leftmost heaviest path: row by row the
+    smallest entry and exit columns over ALL heaviest paths.  Asserts that this
+    row-wise minimum is itself one of the heaviest paths (the leftmost one)."""
+    L, paths = max_paths(a, b)
+    m = len(list(a))
+    cin = [min(p[r][0] for p in paths) for r in range(m + 1)]
+    cout = [min(p[r][1] for p in paths) for r in range(m + 1)]
+    assert tuple(zip(cin, cout)) in set(paths), "row-wise minimum is not a heaviest path"
+    return max(L, 0), cin, cout

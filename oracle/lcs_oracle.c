@@ -228,3 +228,51 @@ int oracle_combine(const int32_t *DU, int64_t hU, const int32_t *DL, int64_t hL,
     }
     return 0;
 }
+
+/*
+ * Every vertex of the canonical path, row by row (Section II-E: the vertices
+ * between two cross vertices of a row, with the reading that a horizontal run
+ * ends where the path goes down or takes a match).  Builds the textbook table
+ * and walks back from (m, n) with the same LEFT > DIAG > UP preference as
+ * oracle_lcs_witness, all the way to (0, 0) (along row 0 or column 0 once one
+ * string is used up).  For every grid row r = 0..m, col_in[r] receives the
+ * smallest and col_out[r] the largest column the walk visits on that row.
+ * Returns the LCS length, or -1 if the table cannot be allocated.
+ */
+int64_t oracle_path_rows(const uint8_t *a, int64_t m, const uint8_t *b, int64_t n,
+                         int32_t *col_in, int32_t *col_out)
+{
+    size_t W = (size_t)n + 1;
+    int32_t *T = calloc(((size_t)m + 1) * W, sizeof(int32_t));
+    if (!T) return -1;
+    for (int64_t i = 1; i <= m; i++) {
+        for (int64_t j = 1; j <= n; j++) {
+            int32_t v;
+            if (a[i - 1] == b[j - 1]) v = T[(size_t)(i - 1) * W + (size_t)(j - 1)] + 1;
+            else {
+                int32_t up = T[(size_t)(i - 1) * W + (size_t)j];
+                int32_t left = T[(size_t)i * W + (size_t)(j - 1)];
+                v = up > left ? up : left;
+            }
+            T[(size_t)i * W + (size_t)j] = v;
+        }
+    }
+    for (int64_t r = 0; r <= m; r++) { col_in[r] = (int32_t)(n + 1); col_out[r] = -1; }
+    int64_t i = m, j = n;
+    for (;;) {
+        if (j < col_in[i]) col_in[i] = (int32_t)j;
+        if (j > col_out[i]) col_out[i] = (int32_t)j;
+        if (i == 0 && j == 0) break;
+        int32_t c = T[(size_t)i * W + (size_t)j];
+        if (j > 0 && T[(size_t)i * W + (size_t)(j - 1)] == c) {
+            j--;                                   /* LEFT */
+        } else if (i > 0 && j > 0 && a[i - 1] == b[j - 1]) {
+            i--; j--;                              /* DIAG: a match */
+        } else {
+            i--;                                   /* UP */
+        }
+    }
+    int64_t L = T[(size_t)m * W + (size_t)n];
+    free(T);
+    return L;
+}

@@ -1125,12 +1125,14 @@ extern "C" int32_t lcs_batch_submit(lcs_batch_t B, const lcs_pair_desc *pairs, i
 
     if (!(mode & LCS_BATCH_GRAPH)) return enqueue(s);
 
-    // graph: captured once per (count, buffers, tasks), replayed afterwards
+    // graph: captured once per (count, buffers, tasks), replayed afterwards.
+    // Every device pointer the captured kernels receive is part of the key.
     key = mix(key, (uint64_t)count);
     key = mix(key, (uint64_t)(uintptr_t)ws);
     key = mix(key, (uint64_t)(uintptr_t)symbols);
     key = mix(key, (uint64_t)(uintptr_t)lengths);
     key = mix(key, (uint64_t)(uintptr_t)a_idx);
+    key = mix(key, (uint64_t)(uintptr_t)b_idx);
     key = mix(key, (uint64_t)tbase);
     key = mix(key, (uint64_t)mode);
     if (!B->gexec || B->gkey != key) {

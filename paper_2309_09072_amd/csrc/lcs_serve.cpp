@@ -90,6 +90,7 @@ namespace {
 struct Request {
     int64_t tag;
     std::vector<uint8_t> a, b;
+    int32_t sigma;  // the request's own alphabet: its next-match tables and symbol check
     int32_t *ai, *bi;
     double t_submit;
     size_t foot;
@@ -98,7 +99,7 @@ struct Request {
 struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
-    lcs_plan_t plan = nullptr;
+    lcs_plan_t plan = nullptr;  // planned per admitted request (host memory only)
     uint8_t *pin_a = nullptr, *pin_b = nullptr;
     int32_t *pin_hdr = nullptr;  // err bits, length, end column
     bool busy = false;
@@ -153,10 +154,7 @@ extern "C" int32_t lcs_server_open(const lcs_server_desc *desc, void *arena, siz
     S->t0 = Clock::now();
     S->slots.resize(d.slots);
     for (Slot &s : S->slots) {
-        lcs_plan_desc pd{d.max_len, d.max_len, d.alphabet, d.base_rows, d.tile, 0};
-        size_t wsb = 0;
-        if (lcs_plan(&pd, &s.plan, &wsb) != LCS_OK ||
-            hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) != hipSuccess ||
+        if (hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) != hipSuccess ||
             hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess ||
             hipHostMalloc(reinterpret_cast<void **>(&s.pin_a), (size_t)d.max_len + 1, 0) != hipSuccess ||
             hipHostMalloc(reinterpret_cast<void **>(&s.pin_b), (size_t)d.max_len + 1, 0) != hipSuccess ||
@@ -172,7 +170,7 @@ extern "C" int32_t lcs_server_open(const lcs_server_desc *desc, void *arena, siz
 extern "C" int32_t lcs_server_footprint(lcs_server_t S, int32_t m, int32_t n, size_t *bytes) {
     if (!S || !bytes || m < 0 || n < 0) return LCS_E_INVAL;
     if (m > S->d.max_len || n > S->d.max_len) return LCS_E_TOO_BIG;
-    *bytes = footprint(m, n, S->d.alphabet, S->d.base_rows, S->d.tile);
+    *bytes = footprint(m, n, S->d.alphabet, S->d.base_rows, S->d.tile);  // largest alphabet
     return *bytes ? LCS_OK : LCS_E_TOO_BIG;
 }
 
@@ -183,7 +181,7 @@ extern "C" int32_t lcs_server_submit(lcs_server_t S, int64_t tag, const uint8_t 
     if ((a_idx == nullptr) != (b_idx == nullptr)) return LCS_E_INVAL;
     if (alphabet < 1 || alphabet > S->d.alphabet) return LCS_E_INVAL;
     if (m > S->d.max_len || n > S->d.max_len) return LCS_E_TOO_BIG;
-    const size_t foot = footprint(m, n, S->d.alphabet, S->d.base_rows, S->d.tile);
+    const size_t foot = footprint(m, n, alphabet, S->d.base_rows, S->d.tile);
     if (!foot) return LCS_E_TOO_BIG;
     if (foot > S->alloc.capacity()) return LCS_E_BUDGET;
     if ((int32_t)S->queue.size() >= S->d.max_queue) return LCS_E_AGAIN;
@@ -191,6 +189,7 @@ extern "C" int32_t lcs_server_submit(lcs_server_t S, int64_t tag, const uint8_t 
     r.tag = tag;
     r.a.assign(a, a + m);
     r.b.assign(b, b + n);
+    r.sigma = alphabet;
     r.ai = a_idx;
     r.bi = b_idx;
     r.t_submit = S->now();
@@ -206,6 +205,13 @@ static int32_t start(lcs_server_s *S, Slot &s) {
     uint8_t *base = S->arena + s.off;
     uint8_t *ad = base, *bd = base + align256(m), *ws = base + align256(m) + align256(n);
     const size_t wsb = r.foot - (size_t)(align256(m) + align256(n));
+    // a plan of the request's exact sizes and alphabet (host memory only)
+    if (s.plan) lcs_plan_destroy(s.plan);
+    s.plan = nullptr;
+    lcs_plan_desc pd{m, n, r.sigma, S->d.base_rows, S->d.tile, 0};
+    size_t need = 0;
+    if (lcs_plan(&pd, &s.plan, &need) != LCS_OK) return LCS_E_NOMEM;
+    if (need > wsb) return LCS_E_WORKSPACE;
     if (m) memcpy(s.pin_a, r.a.data(), m);
     if (n) memcpy(s.pin_b, r.b.data(), n);
     if (m && hipMemcpyAsync(ad, s.pin_a, m, hipMemcpyHostToDevice, s.stream) != hipSuccess) return LCS_E_HIP;

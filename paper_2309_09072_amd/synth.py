@@ -201,6 +201,7 @@ def serving_requests(count: int, rate: float, seed: int = SEED_BASE + 5,
             b = mutate(g, a, sigma, edit / 2, edit / 4, edit / 4)
             if b.size == 0:
                 b = uniform(g, 1, sigma)
+            b = b[:hi]  # insertions may carry a copy past the longest length
         else:
             n = int(round(np.exp(g.uniform(np.log(lo), np.log(hi)))))
             b = uniform(g, n, sigma)

@@ -156,3 +156,35 @@ def test_large_alphabets_every_mode(sigma):
     for mode in (L.BATCH_PERSISTENT, L.BATCH_STAGED, L.BATCH_PAIR_QUEUE):
         say("alphabet", sigma, "mode", mode)
         check(batch, *L.run_batch(batch, mode, 32, 16, 5))
+
+
+@pytest.mark.parametrize("mode", [L.BATCH_STAGED, L.BATCH_PERSISTENT, L.BATCH_PAIR_QUEUE])
+def test_graph_replay_follows_a_new_b_idx_buffer(mode):
+    """A graph replay with only the b_idx buffer changed writes the new buffer
+    (every device pointer the captured kernels take is part of the graph key)
+    and leaves the old one alone."""
+    import torch
+    batch = mixed_small(24, 81)
+    plan = L.Batch(batch.count, 300, 4, 32, 16, 5)
+    ws = L.alloc_workspace(plan.workspace_bytes)
+    sym = L.device_bytes(batch.symbols)
+    off = L.Batch.witness_offsets(batch.m, batch.n)
+    cap = max(int(off[-1]), 1)
+    lengths = torch.full((batch.count,), -99, dtype=torch.int32, device="cuda")
+    ai = torch.full((cap,), -1, dtype=torch.int32, device="cuda")
+    b_old = torch.full((cap,), -1, dtype=torch.int32, device="cuda")
+    b_new = torch.full((cap,), -1, dtype=torch.int32, device="cuda")
+    plan.submit(sym, batch.a_off, batch.b_off, batch.m, batch.n, ws, lengths, ai, b_old,
+                mode | L.BATCH_GRAPH)
+    torch.cuda.synchronize()
+    check(batch, lengths.cpu().numpy(), ai.cpu().numpy(), b_old.cpu().numpy(), off)
+    b_old.fill_(-7)
+    lengths.fill_(-99)
+    ai.fill_(-1)
+    torch.cuda.synchronize()
+    plan.submit(sym, batch.a_off, batch.b_off, batch.m, batch.n, ws, lengths, ai, b_new,
+                mode | L.BATCH_GRAPH)
+    torch.cuda.synchronize()
+    check(batch, lengths.cpu().numpy(), ai.cpu().numpy(), b_new.cpu().numpy(), off)
+    assert bool((b_old == -7).all()), "the replay wrote into the old b_idx buffer"
+    plan.close()

@@ -325,3 +325,33 @@ def test_wide_rows_across_16bit_limits():
                 bad = np.argwhere(got != want)
                 assert bad.size == 0, "n %d level %d strip %d vertex %d weight %d got %d want %d" % (
                     n, lv, s, verts[bad[0][0]], bad[0][1], got[tuple(bad[0])], want[tuple(bad[0])])
+
+
+@pytest.mark.parametrize("m,n", [(20000, 3000), (20000, 10000), (17000, 25000)])
+def test_tall_pairs_global_anchor_rows(m, n):
+    """Row strings longer than 16384: the top combine merges child strips of
+    16384 rows, whose anchor rows (2 * 16384 + 1 weights plus the D_U row) do
+    not fit one work-group's LDS, so the anchor search keeps them in global
+    memory; the three shapes reach its 1024-, 512- and 256-thread forms (at
+    most one, three, or more anchor rows per compute unit).  Length, witness,
+    sampled rows of the top matrix, and the top row against the textbook
+    table's last row."""
+    r = np.random.default_rng(m + n)
+    a = r.integers(0, 4, m).astype(np.uint8)
+    b = synth.fit_length(r, synth.mutate(r, a, 4, 0.1, 0.05, 0.05), n, 4) if n >= 10000 else \
+        r.integers(0, 4, n).astype(np.uint8)
+    say("tall pair", m, n)
+    Lg, plan, ws = check_against_oracle(a, b, 4, base_rows=64, tile=32)
+    levels = plan.levels()
+    assert levels[-1] == 1 and levels[-2] == 2
+    top, row0 = plan.dist(len(levels) - 1, 0, ws)
+    D0 = top[0].cpu().numpy()
+    row = oracle.lcs_last_row(a, b)
+    for k in list(range(0, n + 1, 61)) + [n]:
+        assert int(np.sum(D0 <= k)) - 1 == row[k], k
+    verts = [1, 31, 32, 33, n // 2, n - 33, n - 1]
+    got = top[verts].cpu().numpy()
+    want = oracle.dist_rows(a, 0, m, b, verts)
+    bad = np.argwhere(got != want)
+    assert bad.size == 0, "vertex %d weight %d got %d want %d" % (
+        verts[bad[0][0]], bad[0][1], got[tuple(bad[0])], want[tuple(bad[0])])

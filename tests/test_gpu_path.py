@@ -1,43 +1,20 @@
-"""Full path listing (lcs_path) against the vertices that the textbook DP's
-canonical backward walk (LEFT before DIAG before UP) visits."""
+"""Full path listing (lcs_path, Section II-E) against the oracle's path rows:
+the first and last column the canonical (leftmost) path visits on every grid
+row, from the textbook table's LEFT > DIAG > UP walk (pinned by brute force)."""
 import numpy as np
 import pytest
 import torch
 
+import oracle
 from paper_2309_09072_amd import lcs, synth
 
 pytestmark = pytest.mark.gpu
 
 
-def walk_rows(a, b):
-    """Per grid row r: (first, last) column the canonical walk visits."""
-    m, n = a.size, b.size
-    C = np.zeros((m + 1, n + 1), np.int32)
-    for i in range(1, m + 1):
-        eq = (b == a[i - 1])
-        for j in range(1, n + 1):
-            C[i, j] = C[i - 1, j - 1] + 1 if eq[j - 1] else max(C[i - 1, j], C[i, j - 1])
-    lo = np.full(m + 1, n + 1, np.int64)
-    hi = np.full(m + 1, -1, np.int64)
-    i, j = m, n
-    while True:
-        lo[i] = min(lo[i], j)
-        hi[i] = max(hi[i], j)
-        if i == 0 and j == 0:
-            break
-        if j > 0 and C[i, j - 1] == C[i, j]:
-            j -= 1
-        elif i > 0 and j > 0 and a[i - 1] == b[j - 1]:
-            i, j = i - 1, j - 1
-        else:
-            i -= 1
-    return lo, hi
-
-
 @pytest.mark.parametrize("m,n,sigma,seed", [(120, 150, 4, 1), (200, 90, 2, 2), (64, 64, 1, 3),
                                             (150, 150, 20, 4), (0, 40, 4, 5), (33, 0, 4, 6),
                                             (1, 70, 4, 7), (90, 1, 3, 8)])
-def test_path_matches_dp_walk(m, n, sigma, seed):
+def test_path_matches_oracle(m, n, sigma, seed):
     g = np.random.default_rng(synth.SEED_BASE + 130 + seed)
     a = synth.uniform(g, m, sigma)
     b = synth.mutate(g, a, sigma, 0.1, 0.05, 0.05)[:n] if seed % 2 else synth.uniform(g, n, sigma)
@@ -54,7 +31,7 @@ def test_path_matches_dp_walk(m, n, sigma, seed):
     plan.trace_device(ai, bi, ld)
     cin, cout = plan.path(ai, bi, ld, m)
     torch.cuda.synchronize()
-    lo, hi = walk_rows(a, b)
+    lo, hi = oracle.path_rows(a, b)
     assert cin.cpu().numpy().tolist() == lo.tolist()
     assert cout.cpu().numpy().tolist() == hi.tolist()
     plan.close()

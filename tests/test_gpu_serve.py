@@ -1,6 +1,7 @@
 """Serving on the GPU: results of requests admitted while others run are the
-oracle's, identical alone and in the mix (integers: tolerance 0); the arena
-budget is never exceeded; oversize requests are refused."""
+oracle's, identical alone and in the mix (integers: tolerance 0); the mix
+really overlaps on the device; the arena budget is never exceeded; oversize
+requests are refused; each request is built over its own alphabet."""
 import time
 
 import numpy as np
@@ -13,7 +14,14 @@ from paper_2309_09072_amd import synth
 pytestmark = pytest.mark.gpu
 
 
+def say(*a):
+    print(*a, flush=True)
+
+
 def serve_all(server, reqs, gap=0.0):
+    """Submit in arrival order (retrying while the host queue is full) and poll
+    until every request is done.  Returns the results by tag and the largest
+    number of requests seen running on the device at once."""
     import torch
     outs, results = {}, {}
     bufs = {}
@@ -23,6 +31,7 @@ def serve_all(server, reqs, gap=0.0):
                        torch.full((cap,), -1, dtype=torch.int32, device="cuda"))
     torch.cuda.synchronize()
     pending = list(reqs)
+    max_running = 0
     while pending or len(results) < len(reqs):
         if pending:
             r = pending[0]
@@ -34,34 +43,71 @@ def serve_all(server, reqs, gap=0.0):
             else:
                 assert st == -10        # queue full: poll and retry
         for tag, status, length, ts, tadm, tdone in server.poll():
-            assert status == 0, status
             ai, bi = outs[tag]
-            results[tag] = (length, ai[:length].cpu().numpy(), bi[:length].cpu().numpy(), ts, tadm, tdone)
+            results[tag] = (status, length, ai[:max(length, 0)].cpu().numpy(),
+                            bi[:max(length, 0)].cpu().numpy(), ts, tadm, tdone)
+        max_running = max(max_running, server.pending()[0])
         if gap:
             time.sleep(gap)
-    return results
+    return results, max_running
 
 
 def test_alone_and_mixed_equal_oracle():
-    import torch
-    reqs = synth.serving_requests(60, rate=1000.0, seed=11, lo=16, hi=900)
-    arena = L.alloc_workspace(256 << 20)
-    server = L.Server(arena, 900, 20, slots=6, max_queue=16, base_rows=32, tile=16)
-    mixed = serve_all(server, reqs)
+    """Requests shaped like the serving workload (lengths log-uniform in
+    128..8192, alphabet 4 or 20, 30% mutated copies), all submitted at once to
+    a server with 6 slots: they overlap on the device, each result is the
+    oracle's, and the same request served alone gives the identical result."""
+    reqs = synth.serving_requests(36, rate=0.0, seed=synth.SEED_BASE + 211)
+    say("requests", len(reqs), "cells", sum(int(r.a.size) * int(r.b.size) for r in reqs))
+    arena = L.alloc_workspace(24 << 30)
+    server = L.Server(arena, 8192, 20, slots=6, max_queue=8)
+    mixed, max_running = serve_all(server, reqs)
     running, waiting, used, peak = server.pending()
     assert running == 0 and waiting == 0 and used == 0
     assert 0 < peak <= arena.numel()
-    overlap = sum(1 for r in mixed.values() if r[4] < max(x[5] for x in mixed.values()))
+    # overlap on the device, from the server's own clocks: two requests were
+    # running together, and some request was admitted before a request
+    # admitted earlier had finished
+    assert max_running >= 2, max_running
+    order = sorted(mixed, key=lambda t: mixed[t][5])
+    joined = sum(1 for k in range(1, len(order))
+                 if any(mixed[order[k]][5] < mixed[order[i]][6] for i in range(k)))
+    assert joined >= len(order) // 2, joined
     for r in reqs:
-        L_, ai, bi = mixed[r.rid][:3]
+        st, L_, ai, bi = mixed[r.rid][:4]
+        assert st == 0, (r.rid, st)
         Lo, ao, bo = oracle.lcs_witness(r.a, r.b)
         assert L_ == Lo and np.array_equal(ai, ao) and np.array_equal(bi, bo), r.rid
     # the same requests one at a time through the same server
-    for r in reqs[:12]:
-        alone = serve_all(server, [r])
-        assert alone[r.rid][0] == mixed[r.rid][0]
-        assert np.array_equal(alone[r.rid][1], mixed[r.rid][1])
+    for r in reqs[:10]:
+        alone, _ = serve_all(server, [r])
+        assert alone[r.rid][:2] == mixed[r.rid][:2]
         assert np.array_equal(alone[r.rid][2], mixed[r.rid][2])
+        assert np.array_equal(alone[r.rid][3], mixed[r.rid][3])
+    server.close()
+
+
+def test_request_alphabet_is_checked():
+    """A request declared over 4 symbols is built with 4 next-match tables: a
+    symbol 5 in it is reported as LCS_E_SYMBOL even though the server allows
+    20, while its neighbours (alphabets 4 and 20) are unaffected."""
+    g = np.random.default_rng(7)
+    good4 = synth.Request(0, 0.0, synth.uniform(g, 300, 4), synth.uniform(g, 280, 4), 4)
+    bad = synth.Request(1, 0.0, synth.uniform(g, 200, 4), synth.uniform(g, 250, 4), 4)
+    bad.b[17] = 5
+    good20 = synth.Request(2, 0.0, synth.uniform(g, 260, 20), synth.uniform(g, 300, 20), 20)
+    arena = L.alloc_workspace(512 << 20)
+    server = L.Server(arena, 1024, 20, slots=3, max_queue=8)
+    res, _ = serve_all(server, [good4, bad, good20])
+    assert res[1][0] == -5
+    for r in (good4, good20):
+        Lo, ao, bo = oracle.lcs_witness(r.a, r.b)
+        assert res[r.rid][0] == 0 and res[r.rid][1] == Lo
+        assert np.array_equal(res[r.rid][2], ao) and np.array_equal(res[r.rid][3], bo)
+    # an alphabet above the server's is refused at submit
+    with pytest.raises(L.LcsError) as e:
+        server.submit(9, good4.a, good4.b, 21)
+    assert e.value.status == -1
     server.close()
 
 
@@ -76,8 +122,9 @@ def test_budget_and_oversize():
         r.sigma = min(r.sigma, 4)
         r.a = (r.a % 4).astype(np.uint8)
         r.b = (r.b % 4).astype(np.uint8)
-    res = serve_all(server, reqs)
+    res, _ = serve_all(server, reqs)
     assert server.pending()[3] <= arena.numel()
     for r in reqs:
-        assert res[r.rid][0] == oracle.lcs_length(r.a, r.b)
+        assert res[r.rid][0] == 0
+        assert res[r.rid][1] == oracle.lcs_length(r.a, r.b)
     server.close()

@@ -26,6 +26,12 @@ MUTANTS = {
     "dp_dropped_plus_one": ("cur[j] = prev[j - 1] + 1;", "cur[j] = prev[j - 1];"),
     # witness walk: DIAG tried before LEFT
     "walk_diag_first": ("if (CELL(i, j - 1) == c) {", "if (a[i - 1] != b[j - 1] && CELL(i, j - 1) == c) {"),
+    # path listing: UP tried before LEFT (a path that leaves rows too early)
+    "path_up_before_left": ("if (j > 0 && T[(size_t)i * W + (size_t)(j - 1)] == c) {",
+                            "if (j > 0 && (i == 0 || T[(size_t)(i - 1) * W + (size_t)j] != c) && T[(size_t)i * W + (size_t)(j - 1)] == c) {"),
+    # path listing: the exit column of a row recorded as its entry column
+    "path_exit_is_entry": ("if (j > col_out[i]) col_out[i] = (int32_t)j;",
+                           "if (j < col_out[i] || col_out[i] < 0) col_out[i] = (int32_t)j;"),
     # breakout definition: strict instead of >=
     "dist_strict": ("if (row[c] >= j) { d = i + c; break; }", "if (row[c] > j) { d = i + c; break; }"),
     # base case: the text's tail (from j_r + 2) instead of the example's (from j_r + 1)
@@ -92,6 +98,14 @@ def _pins(lib):
             fails.append("base row vs definition"); break
         if int(np.sum(DG[0] <= nn)) - 1 != brute.lcs_length(list(x), list(y)):
             fails.append("top row vs brute force"); break
+    for _ in range(40):
+        sig = int(r.integers(1, 4))
+        x = r.integers(0, sig, int(r.integers(0, 6))).astype(np.uint8)
+        y = r.integers(0, sig, int(r.integers(0, 6))).astype(np.uint8)
+        _, ci, co = brute.leftmost_path_rows(x, y)
+        oi, oo = oracle.path_rows(x, y, lib=lib)
+        if list(oi) != ci or list(oo) != co:
+            fails.append("path rows vs brute force"); break
     return fails
 
 

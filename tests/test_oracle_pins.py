@@ -98,6 +98,44 @@ def test_length_and_witness_vs_brute_force():
         assert list(ai) == bai and list(bi) == bbi
 
 
+def test_path_rows_vs_brute_force():
+    """Section II-E path listing: the oracle's per-row entry/exit columns are the
+    row-wise minimum over every heaviest path, enumerated move by move (which is
+    itself a heaviest path: the leftmost one), and its diagonal steps are the
+    brute-force canonical witness."""
+    r = np.random.default_rng(20)
+    for _ in range(250):
+        sig = int(r.integers(1, 4))
+        m, n = int(r.integers(0, 7)), int(r.integers(0, 7))
+        a = r.integers(0, sig, m).astype(np.uint8)
+        b = r.integers(0, sig, n).astype(np.uint8)
+        L, cin, cout = brute.leftmost_path_rows(a, b)
+        oi, oo = oracle.path_rows(a, b)
+        assert list(oi) == cin and list(oo) == cout, (a, b)
+        assert oi[0] == 0 and oo[m] == n
+        # diagonal steps (row r leaves at c, row r + 1 enters at c + 1) = the witness
+        diag = [(rr, int(oo[rr])) for rr in range(m) if oi[rr + 1] == oo[rr] + 1]
+        bl, ba, bb = brute.canonical_witness(list(a), list(b))
+        assert diag == list(zip(ba, bb)) and len(diag) == L == bl
+
+
+def test_path_rows_closed_forms():
+    """Unary alphabet: the leftmost path goes straight down to row m - n (m >= n)
+    and then diagonally; with m < n it goes diagonally first and then right
+    along row m.  Disjoint alphabets: straight down column 0, then along row m."""
+    for m, n in [(6, 3), (3, 6), (5, 5), (0, 4), (4, 0)]:
+        cin, cout = oracle.path_rows(np.zeros(m, np.uint8), np.zeros(n, np.uint8))
+        if m >= n:
+            want_in = [max(0, r - (m - n)) for r in range(m + 1)]
+            want_out = list(want_in)
+        else:
+            want_in = list(range(m + 1))
+            want_out = list(range(m)) + [n]
+        assert list(cin) == want_in and list(cout) == want_out, (m, n)
+    cin, cout = oracle.path_rows(np.zeros(5, np.uint8), np.ones(7, np.uint8))
+    assert list(cin) == [0] * 6 and list(cout) == [0] * 5 + [7]
+
+
 def test_dist_rows_vs_brute_force():
     """D(i, j) = smallest c with LCS(strip, b[i:c]) >= j, with LCS by enumeration."""
     r = np.random.default_rng(12)
