@@ -154,7 +154,7 @@ int32_t enqueue_build(const Layout &L, uint8_t *ws, const uint8_t *a, const uint
     hipError_t e = launch_clear(hdr, kHeaderWords, s);
     if (e != hipSuccess || L.lev.empty()) return hip_status(e);
     R.begin(LCS_PHASE_NEXTMATCH, 0, (int64_t)L.sigma * L.n + 4 * (int64_t)L.sigma * (L.n + 2));
-    e = launch_nextmatch(b, L.n, L.sigma, nm, s);
+    e = launch_nextmatch(b, L.n, L.sigma, nm, hdr, s);
     R.end();
     if (e != hipSuccess) return LCS_E_HIP;
     const LevelGeom &g0 = L.lev[0];

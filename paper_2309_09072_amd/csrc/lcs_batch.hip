@@ -203,9 +203,9 @@ __device__ __forceinline__ void exec_task(const BatchArgs &A, uint8_t *ws, int32
             if (threadIdx.x == 0) A.lengths[p] = 0;
             break;
         case ST_NM_SYM:
-            if (u == 0)
+            if (u == 0)  // (the same work-group then checks b's symbols into hdr[0])
                 for (int32_t i = threadIdx.x; i < kHeaderWords; i += kBlock) hdr[i] = 0;
-            nextmatch_block(b, P.n, u, nm + (size_t)u * (size_t)(P.n + 2), sm.nm);
+            nextmatch_block(b, P.n, u, A.sigma, nm + (size_t)u * (size_t)(P.n + 2), sm.nm, hdr);
             break;
         case ST_BASE_BLK:
             if (kAll && A.base_mode == kBaseTab16Mode)

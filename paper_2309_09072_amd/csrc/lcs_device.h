@@ -63,9 +63,10 @@ __device__ __forceinline__ int32_t wave_suffix_min(int32_t v) {
 // sigma tables serve all m rows.  Each thread scans a run of columns, a
 // block-wide suffix minimum (wave DPP scan + LDS across waves) carries the
 // first match of the runs to its right, then each run is written right to
-// left.  lds: kWaves int32.
-__device__ void nextmatch_block(const uint8_t *__restrict__ b, int32_t n, int32_t x,
-                                int32_t *__restrict__ nm, int32_t *lds) {
+// left.  The work-group of symbol 0 also checks every symbol of b against the
+// alphabet (a symbol >= sigma sets kErrSymbol in *err).  lds: kWaves int32.
+__device__ void nextmatch_block(const uint8_t *__restrict__ b, int32_t n, int32_t x, int32_t sigma,
+                                int32_t *__restrict__ nm, int32_t *lds, int32_t *err) {
     const int32_t INF = n + 1;
     const int32_t total = n + 2;
     const int32_t R = (total + kBlock - 1) / kBlock;
@@ -87,11 +88,16 @@ __device__ void nextmatch_block(const uint8_t *__restrict__ b, int32_t n, int32_
     int32_t carry = (lane < kWave - 1) ? nxt : INF;
     for (int w2 = w + 1; w2 < kWaves; ++w2) carry = imin(carry, lds[w2]);
     int32_t cur = carry;
+    bool bad = false;
     for (int32_t c = c1 - 1; c >= c0; --c) {
-        if (c < n && b[c] == x) cur = c + 1;
+        if (c < n) {
+            const int32_t y = b[c];
+            if (y == x) cur = c + 1;
+            bad |= y >= sigma;
+        }
         nm[c] = cur;
     }
-    __syncthreads();
+    if (__syncthreads_or(bad && x == 0) && threadIdx.x == 0) atomicOr(err, kErrSymbol);
 }
 
 // ---------------------------------------------------------------------------

@@ -10,10 +10,11 @@ __global__ void __launch_bounds__(kBlock) k_clear(int32_t *words, int32_t count)
     for (int32_t i = blockIdx.x * kBlock + threadIdx.x; i < count; i += gridDim.x * kBlock) words[i] = 0;
 }
 
-__global__ void __launch_bounds__(kBlock) k_nextmatch(const uint8_t *b, int32_t n, int32_t *nm) {
+__global__ void __launch_bounds__(kBlock) k_nextmatch(const uint8_t *b, int32_t n, int32_t sigma,
+                                                      int32_t *nm, int32_t *err) {
     __shared__ int32_t lds[kWaves];
     const int32_t x = blockIdx.x;
-    nextmatch_block(b, n, x, nm + (size_t)x * (size_t)(n + 2), lds);
+    nextmatch_block(b, n, x, sigma, nm + (size_t)x * (size_t)(n + 2), lds, err);
 }
 
 template <int H0, int kMode>
@@ -273,8 +274,9 @@ hipError_t launch_clear(int32_t *words, int32_t count, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_nextmatch(const uint8_t *b, int32_t n, int32_t sigma, int32_t *nm, hipStream_t s) {
-    hipLaunchKernelGGL(k_nextmatch, dim3(sigma), dim3(kBlock), 0, s, b, n, nm);
+hipError_t launch_nextmatch(const uint8_t *b, int32_t n, int32_t sigma, int32_t *nm, int32_t *err,
+                            hipStream_t s) {
+    hipLaunchKernelGGL(k_nextmatch, dim3(sigma), dim3(kBlock), 0, s, b, n, sigma, nm, err);
     return hipGetLastError();
 }
 

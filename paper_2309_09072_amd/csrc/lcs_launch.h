@@ -8,7 +8,8 @@
 namespace lcs {
 
 hipError_t launch_clear(int32_t *words, int32_t count, hipStream_t s);
-hipError_t launch_nextmatch(const uint8_t *b, int32_t n, int32_t sigma, int32_t *nm, hipStream_t s);
+hipError_t launch_nextmatch(const uint8_t *b, int32_t n, int32_t sigma, int32_t *nm, int32_t *err,
+                            hipStream_t s);
 hipError_t launch_base(int32_t h0, const uint8_t *a, int32_t n, int32_t sigma, const int32_t *nm,
                        int32_t *base0, int32_t *last, int32_t nstrips, int32_t hlast, int32_t *err,
                        hipStream_t s);

@@ -114,11 +114,12 @@ def test_bad_symbol_only_fails_its_pair():
     pairs = [(r.integers(0, 4, 100).astype(np.uint8), r.integers(0, 4, 90).astype(np.uint8))
              for _ in range(6)]
     pairs[3] = (np.array([0, 1, 7, 2], np.uint8), np.array([0, 1, 2], np.uint8))
+    pairs[4] = (np.array([0, 1, 3, 2], np.uint8), np.array([0, 5, 2], np.uint8))  # bad column symbol
     batch = synth.batch_from_pairs(pairs, 4)
-    for mode in (L.BATCH_PERSISTENT, L.BATCH_PAIR_QUEUE):
+    for mode in (L.BATCH_PERSISTENT, L.BATCH_PAIR_QUEUE, L.BATCH_STAGED, L.BATCH_PER_PAIR):
         lengths, ai, bi, off = L.run_batch(batch, mode, 16, 8, 2)
-        assert lengths[3] == -5
-        check(batch, lengths, ai, bi, off, skip=(3,))
+        assert lengths[3] == -5 and lengths[4] == -5, mode
+        check(batch, lengths, ai, bi, off, skip=(3, 4))
 
 
 def test_mixed_workload_sample():

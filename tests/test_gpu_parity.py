@@ -217,14 +217,28 @@ def test_edge_cases():
 
 
 def test_bad_symbol_reports_error():
-    a = np.array([0, 1, 2, 9, 1], np.uint8)
-    b = np.array([0, 1, 2, 1], np.uint8)
-    plan = L.Plan(5, 4, 4)
+    """A symbol outside the alphabet in either string is LCS_E_SYMBOL (row string:
+    base strips; column string: the next-match scan), also with the orientation
+    choice, which swaps the roles of the two strings."""
+    good_a = np.array([0, 1, 2, 3, 1], np.uint8)
+    good_b = np.array([0, 1, 2, 1], np.uint8)
+    bad_a = good_a.copy()
+    bad_a[3] = 9
+    bad_b = good_b.copy()
+    bad_b[2] = 4
+    for a, b in ((bad_a, good_b), (good_a, bad_b), (bad_a, bad_b)):
+        for orient in (False, True):
+            plan = L.Plan(5, 4, 4, orient=orient)
+            ws = L.alloc_workspace(plan.workspace_for(5, 4))
+            plan.build(L.device_bytes(a), L.device_bytes(b), ws)
+            with pytest.raises(L.LcsError) as e:
+                plan.length()
+            assert e.value.status == -5
+            plan.close()
+    plan = L.Plan(5, 4, 4)  # and a good pair in the same plan afterwards is fine
     ws = L.alloc_workspace(plan.workspace_for(5, 4))
-    plan.build(L.device_bytes(a), L.device_bytes(b), ws)
-    with pytest.raises(L.LcsError) as e:
-        plan.length()
-    assert e.value.status == -5
+    plan.build(L.device_bytes(good_a), L.device_bytes(good_b), ws)
+    assert plan.length() == oracle.lcs_length(good_a, good_b)
 
 
 def test_determinism_and_reuse():
