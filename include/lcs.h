@@ -126,6 +126,28 @@ int32_t lcs_dist_build(lcs_plan_t plan, const uint8_t *a, int32_t m, const uint8
                        void *workspace, size_t workspace_bytes, void *stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same as
+ * lcs_dist_build, with the workspace taken from a device array that the
+ * library holds itself, LCS_NOALLOC_WORKSPACE_BYTES long, one copy on each GPU
+ * it runs on (the current device's copy is used; the stream must belong to
+ * it), kept until the process ends.  It allocates nothing and calls no
+ * allocating routine.  Every call on a GPU shares that GPU's array: calls that
+ * overlap on one GPU race, and the build's matrices stay readable by
+ * lcs_length, lcs_trace, lcs_trace_device, lcs_semilocal, lcs_path and
+ * lcs_dist_view of this plan only until the next lcs_dist_build_noalloc on the
+ * same GPU (with any plan) overwrites them.  Everything that must start at
+ * zero is cleared by the build itself, with kernels (no memset).
+ * Errors: those of lcs_dist_build, and LCS_E_WORKSPACE when
+ * lcs_plan_workspace(plan, m, n) exceeds LCS_NOALLOC_WORKSPACE_BYTES (about
+ * 1450 x 1450 symbols with 64-row base strips); LCS_E_HIP if the array cannot
+ * be found on the current device.
+ */
+#define LCS_NOALLOC_WORKSPACE_BYTES ((size_t)64 << 20)
+int32_t lcs_dist_build_noalloc(lcs_plan_t plan, const uint8_t *a, int32_t m, const uint8_t *b,
+                               int32_t n, void *stream);
+
+/*
  * LCS length of the last build: the largest weight j whose breakout from top
  * vertex 0 of the whole grid is reachable (Sections II-B-1 and II-C).
  * Copies it to *length_host and SYNCHRONISES the stream.

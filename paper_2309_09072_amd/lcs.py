@@ -23,6 +23,7 @@ STATUS = {
     -9: "LCS_E_BUDGET", -10: "LCS_E_AGAIN",
 }
 BATCH_PERSISTENT, BATCH_PER_PAIR, BATCH_GRAPH, BATCH_STAGED, BATCH_PAIR_QUEUE = 0, 1, 2, 4, 8
+NOALLOC_WORKSPACE_BYTES = 64 << 20  # LCS_NOALLOC_WORKSPACE_BYTES of include/lcs.h
 
 
 class LcsError(RuntimeError):
@@ -87,6 +88,7 @@ PROTOTYPES = {
     "lcs_plan_workspace": (_I32, [_P, _I32, _I32, _PSZ]),
     "lcs_plan_destroy": (_I32, [_P]),
     "lcs_dist_build": (_I32, [_P, _P, _I32, _P, _I32, _P, _SZ, _P]),
+    "lcs_dist_build_noalloc": (_I32, [_P, _P, _I32, _P, _I32, _P]),
     "lcs_length": (_I32, [_P, _PI32, _P]),
     "lcs_length_device": (_I32, [_P, _P, _P]),
     "lcs_trace": (_I32, [_P, _P, _P, _I32, _PI32, _P]),
@@ -208,6 +210,14 @@ class Plan:
         check(load().lcs_dist_build(self._h, _dptr(a), int(a.numel()), _dptr(b), int(b.numel()),
                                     _dptr(ws), int(ws.numel()), stream_handle(stream)),
               "lcs_dist_build")
+
+    def build_noalloc(self, a, b, stream=None) -> None:
+        """lcs_dist_build_noalloc: the build on the library's own device array
+        (no workspace argument, nothing allocated)."""
+        self._keep = (a, b)
+        check(load().lcs_dist_build_noalloc(self._h, _dptr(a), int(a.numel()), _dptr(b),
+                                            int(b.numel()), stream_handle(stream)),
+              "lcs_dist_build_noalloc")
 
     def length(self, stream=None) -> int:
         out = ctypes.c_int32()

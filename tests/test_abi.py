@@ -104,3 +104,15 @@ def test_orient_flag_and_workspace_bound():
     import ctypes
     h, ws = ctypes.c_void_p(), ctypes.c_size_t()
     assert lcs.load().lcs_plan(ctypes.byref(desc), ctypes.byref(h), ctypes.byref(ws)) == -1
+
+
+def test_noalloc_build_rejects_pairs_beyond_its_array():
+    """The no-allocation build refuses a pair whose workspace exceeds the
+    library's own device array, before any device work (null strings are never
+    read)."""
+    lib = L.load()
+    p = L.Plan(4096, 4096, 4)
+    assert p.workspace_for(4096, 4096) > L.NOALLOC_WORKSPACE_BYTES
+    st = lib.lcs_dist_build_noalloc(p._h, None, 4096, None, 4096, None)
+    assert st == -3
+    assert p.workspace_for(1450, 1450) <= L.NOALLOC_WORKSPACE_BYTES
