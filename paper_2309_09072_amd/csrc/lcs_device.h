@@ -715,8 +715,8 @@ __device__ __forceinline__ BracketWindow bracket_window(const BracketSmemT<C> &s
                                                         const int32_t *__restrict__ U, int32_t ldU,
                                                         int32_t i0, int32_t ubase, int32_t v,
                                                         int32_t va, int32_t vb, int32_t jj,
-                                                        int32_t j, int32_t hU, int32_t hL,
-                                                        int32_t n) {
+                                                        int32_t js, int32_t j, int32_t hU,
+                                                        int32_t hL, int32_t n) {
     constexpr int32_t S = C::kJ;
     BracketWindow w;
     const int32_t ka = ldk(sm, va * S + jj);
@@ -729,8 +729,13 @@ __device__ __forceinline__ BracketWindow bracket_window(const BracketSmemT<C> &s
         w.xb = bracket_u<C, kLds>(sm, U, ldU, hU, i0, ubase, vb, kb, n);
     }
     w.lo = imax(ka - (v - va), imax(j - hL, 0));
+    // value bounds from the rows of the two brackets (rows of a breakout
+    // matrix interlace: D(i + d, j - d) <= D(i, j) <= D(i - d, j + d)), with
+    // the weights that lie inside this block's range
     w.vlo = (int32_t)sm.v[va * S + jj];
     w.vhi = (int32_t)sm.v[vb * S + jj];
+    if (jj >= vb - v) w.vlo = imax(w.vlo, (int32_t)sm.v[vb * S + jj - (vb - v)]);
+    if (jj + (v - va) < js) w.vhi = imin(w.vhi, (int32_t)sm.v[va * S + jj + (v - va)]);
     return w;
 }
 
@@ -797,11 +802,11 @@ __device__ __forceinline__ void bracket_pass1(BracketSmemT<C> &sm, const int32_t
         if ((e < nitems) && (jj < js)) {
             const int32_t j = j0 + jj;
             const BracketWindow w = bracket_window<C, kLds>(sm, U, ldU, i0, ubase, v, v - half,
-                                                         imin(v + half, len), jj, j, hU, hL, n);
+                                                         imin(v + half, len), jj, js, j, hU, hL, n);
             if (w.dead || w.lo > w.hi) {
                 bracket_store(sm, id[r], G + (size_t)(i0 + v) * H + j, n, INF, -1);
             } else if (finest && w.vlo == w.vhi) {
-                // D_G(ia, j) <= D_G(i, j) <= D_G(ib, j): the value is fixed
+                // the interlacing bounds meet: the value is fixed
                 bracket_store(sm, id[r], G + (size_t)(i0 + v) * H + j, n, w.vlo, 0);
             } else {
                 act[r] = true;
@@ -882,7 +887,7 @@ __device__ __forceinline__ void bracket_coarse(BracketSmemT<C> &sm, const int32_
         if (e < nitems && jj < js) {
             const int32_t v = half + t * st, j = j0 + jj;
             const BracketWindow w = bracket_window<C, kLds>(sm, U, ldU, i0, ubase, v, v - half,
-                                                         imin(v + half, len), jj, j, hU, hL, n);
+                                                         imin(v + half, len), jj, js, j, hU, hL, n);
             const int32_t k0 = w.lo + sub * kCoarseBatch;
             if (!w.dead && k0 <= w.hi) {
                 int32_t xs[kCoarseBatch], vs[kCoarseBatch];
@@ -905,7 +910,7 @@ __device__ __forceinline__ void bracket_coarse(BracketSmemT<C> &sm, const int32_
         const int32_t v = half + t * st, j = j0 + jj;
         const int32_t id = v * S + jj;
         const BracketWindow w = bracket_window<C, kLds>(sm, U, ldU, i0, ubase, v, v - half,
-                                                     imin(v + half, len), jj, j, hU, hL, n);
+                                                     imin(v + half, len), jj, js, j, hU, hL, n);
         const unsigned long long key = sm.key[e];
         sm.key[e] = ~0ull;  // ready for the next coarse level
         int32_t *g_out = G + (size_t)(i0 + v) * H + j;
@@ -1004,7 +1009,7 @@ __device__ __forceinline__ void bracket_levels(BracketSmemT<C> &sm, const int32_
                 const int32_t v = idq / S, jj = idq - v * S;
                 const int32_t j = j0 + jj;
                 const BracketWindow wq = bracket_window<C, kLds>(sm, U, ldU, i0, ubase, v, v - half,
-                                                              imin(v + half, len), jj, j, hU, hL, n);
+                                                              imin(v + half, len), jj, js, j, hU, hL, n);
                 const int32_t best0 = (int32_t)sm.v[idq];
                 int32_t best = best0, bk = -1;
                 constexpr int CB = C::kCoopB;
@@ -1037,7 +1042,7 @@ __device__ __forceinline__ void bracket_levels(BracketSmemT<C> &sm, const int32_
                 const int32_t v = idq / S, jj = idq - v * S;
                 const int32_t j = j0 + jj;
                 const BracketWindow wq = bracket_window<C, kLds>(sm, U, ldU, i0, ubase, v, v - half,
-                                                              imin(v + half, len), jj, j, hU, hL, n);
+                                                              imin(v + half, len), jj, js, j, hU, hL, n);
                 int32_t best = (int32_t)sm.v[idq], bk = ldk(sm, idq);
                 for (int32_t k0 = wq.lo + b1;; k0 += kPass2Batch) {
                     int32_t xs[kPass2Batch], vs[kPass2Batch];
