@@ -179,7 +179,10 @@ def alg_bytes(m: int, n: int, h0: int) -> int:
     return tot
 
 
-def bench_batched(reps: int, tune_shapes: bool = True):
+BATCH_MODES = ("staged_graph", "pair_queue_graph", "persistent_graph", "one_pair_per_launch")
+
+
+def bench_batched(reps: int, tune_shapes: bool = True, modes=BATCH_MODES):
     """Many pairs of uneven length: one launch per step across the pairs (staged),
     one persistent launch (pair queue, task queue), and one pair per launch."""
     import numpy as np
@@ -208,10 +211,13 @@ def bench_batched(reps: int, tune_shapes: bool = True):
     out = {"workload": batch.name, "pairs": batch.count, "cells": batch.cells, "seed": batch.seed,
            "slots": slots, "base_rows": h0, "tile": tile, "autotune": tuning,
            "workspace_GB": round(ws.numel() / 1e9, 2), "alg_bytes_per_batch": nbytes}
-    for name, mode in (("staged_graph", lcs.BATCH_STAGED | lcs.BATCH_GRAPH),
-                       ("pair_queue_graph", lcs.BATCH_PAIR_QUEUE | lcs.BATCH_GRAPH),
-                       ("persistent_graph", lcs.BATCH_PERSISTENT | lcs.BATCH_GRAPH),
-                       ("one_pair_per_launch", lcs.BATCH_PER_PAIR)):
+    mode_of = {"staged_graph": lcs.BATCH_STAGED | lcs.BATCH_GRAPH,
+               "staged": lcs.BATCH_STAGED,
+               "pair_queue_graph": lcs.BATCH_PAIR_QUEUE | lcs.BATCH_GRAPH,
+               "persistent_graph": lcs.BATCH_PERSISTENT | lcs.BATCH_GRAPH,
+               "one_pair_per_launch": lcs.BATCH_PER_PAIR}
+    for name in modes:
+        mode = mode_of[name]
         plan.submit(sym, batch.a_off, batch.b_off, batch.m, batch.n, ws, lengths, ai, bi, mode)
         torch.cuda.synchronize()
         # poison the outputs, so that a mode which wrote nothing cannot pass on the
@@ -235,17 +241,19 @@ def bench_batched(reps: int, tune_shapes: bool = True):
         out[name] = {"s_per_batch": round(dt, 4), "cells_per_s": batch.cells / dt,
                      "alg_GBps": round(nbytes / dt / 1e9, 1), "exact_match": exact}
         log("batched %s: %.3f s per batch, %.3g cells/s, exact=%s" % (name, dt, batch.cells / dt, exact))
-    best = min(("staged_graph", "pair_queue_graph", "persistent_graph"),
-               key=lambda k: out[k]["s_per_batch"])
-    ach = nbytes / out[best]["s_per_batch"] / 1e9
-    out["roofline"] = {"kernel": "whole batch, %s (all step kernels)" % best, "bound": "hbm",
-                       "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                       "frac": round(ach / HBM_PEAK_GBS, 4),
-                       "traffic": read_traffic(batch.name, "staged", batch_sources=True),
-                       "alg_bytes_per_batch": nbytes}
-    for k in ("staged_graph", "pair_queue_graph", "persistent_graph"):
-        out["speedup_%s_vs_per_pair" % k.replace("_graph", "")] = round(
-            out["one_pair_per_launch"]["s_per_batch"] / out[k]["s_per_batch"], 2)
+    one_launch = [k for k in out if k in ("staged_graph", "staged", "pair_queue_graph", "persistent_graph")]
+    if one_launch:
+        best = min(one_launch, key=lambda k: out[k]["s_per_batch"])
+        ach = nbytes / out[best]["s_per_batch"] / 1e9
+        out["roofline"] = {"kernel": "whole batch, %s (all step kernels)" % best, "bound": "hbm",
+                           "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": round(ach / HBM_PEAK_GBS, 4),
+                           "traffic": read_traffic(batch.name, "staged", batch_sources=True),
+                           "alg_bytes_per_batch": nbytes}
+        if "one_pair_per_launch" in out:
+            for k in one_launch:
+                out["speedup_%s_vs_per_pair" % k.replace("_graph", "")] = round(
+                    out["one_pair_per_launch"]["s_per_batch"] / out[k]["s_per_batch"], 2)
     del ws
     torch.cuda.empty_cache()
     return out, batch
@@ -591,6 +599,8 @@ def main():
     ap.add_argument("--only-batched", action="store_true",
                     help="run the batched workload alone (its own JSON line; for profiling)")
     ap.add_argument("--batch-reps", type=int, default=3)
+    ap.add_argument("--batch-modes", default=",".join(BATCH_MODES),
+                    help="comma-separated batch modes (staged = the staged mode without a graph)")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also launch one plain device copy of this many MiB (counter calibration)")
@@ -624,7 +634,8 @@ def main():
             log("calibration copy: %d bytes read, %d bytes written" % (nb, nb))
 
     if args.only_batched:
-        bres, _ = bench_batched(args.batch_reps, tune_shapes=False)
+        bres, _ = bench_batched(args.batch_reps, tune_shapes=False,
+                                modes=tuple(args.batch_modes.split(",")))
         calib()
         print(json.dumps({"metric": "batched LCS cells/s", "batched": bres}), flush=True)
         return
