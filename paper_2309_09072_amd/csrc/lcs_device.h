@@ -659,12 +659,12 @@ struct BracketCfg {
     static constexpr int kCoopB = CB;  // candidates per thread slice of the cooperative pass 2
 };
 using BracketCfg32 = BracketCfg<int32_t, 32, 64>;
-using BracketCfg16 = BracketCfg<uint16_t, 64, 98>;
+using BracketCfg16 = BracketCfg<uint16_t, 64, 100>;
 using BracketCfg16Mid = BracketCfg<uint16_t, 64, 128, 6>;  // 512+ rows: still 8 work-groups per CU
 using BracketCfg16Wide = BracketCfg<uint16_t, 64, 160>;  // tall strips: wider D_U window
 
 template <class C>
-struct BracketSmemT {
+struct __align__(16) BracketSmemT {
     using St = typename C::St;
     St k[(kMaxTile + 1) * C::kJ];
     St v[(kMaxTile + 1) * C::kJ];
@@ -739,18 +739,17 @@ __device__ __forceinline__ BracketWindow bracket_window(const BracketSmemT<C> &s
     return w;
 }
 
-// Final result of one output: LDS state for the finer levels and D_G.
+// Final result of one output: the LDS state that finer levels read; the block
+// writes all of its outputs to D_G at the end, row segment by row segment.
 template <class C>
-__device__ __forceinline__ void bracket_store(BracketSmemT<C> &sm, int32_t id,
-                                              int32_t *__restrict__ g, int32_t n, int32_t best,
-                                              int32_t bk) {
+__device__ __forceinline__ void bracket_store(BracketSmemT<C> &sm, int32_t id, int32_t n,
+                                              int32_t best, int32_t bk) {
     if (best > n) {
         best = n + 1;
         bk = -1;
     }
     stk(sm, id, bk);
     sm.v[id] = (typename C::St)best;
-    *g = best;
 }
 
 // D_U loads of one batch of tile vertex v (LDS parallelogram or global).
@@ -804,10 +803,10 @@ __device__ __forceinline__ void bracket_pass1(BracketSmemT<C> &sm, const int32_t
             const BracketWindow w = bracket_window<C, kLds>(sm, U, ldU, i0, ubase, v, v - half,
                                                          imin(v + half, len), jj, js, j, hU, hL, n);
             if (w.dead || w.lo > w.hi) {
-                bracket_store(sm, id[r], G + (size_t)(i0 + v) * H + j, n, INF, -1);
+                bracket_store(sm, id[r], n, INF, -1);
             } else if (finest && w.vlo == w.vhi) {
                 // the interlacing bounds meet: the value is fixed
-                bracket_store(sm, id[r], G + (size_t)(i0 + v) * H + j, n, w.vlo, 0);
+                bracket_store(sm, id[r], n, w.vlo, 0);
             } else {
                 act[r] = true;
                 vr[r] = v;
@@ -841,7 +840,7 @@ __device__ __forceinline__ void bracket_pass1(BracketSmemT<C> &sm, const int32_t
         bool queued = false;
         if (act[r]) {
             if (done) {
-                bracket_store(sm, id[r], G + (size_t)(i0 + vr[r]) * H + jv[r], n, best, bk);
+                bracket_store(sm, id[r], n, best, bk);
             } else {  // provisional state; pass 2 resumes at lo + B
                 stk(sm, id[r], bk);
                 sm.v[id[r]] = (typename C::St)imin(best, n + 1);
@@ -913,9 +912,8 @@ __device__ __forceinline__ void bracket_coarse(BracketSmemT<C> &sm, const int32_
                                                      imin(v + half, len), jj, js, j, hU, hL, n);
         const unsigned long long key = sm.key[e];
         sm.key[e] = ~0ull;  // ready for the next coarse level
-        int32_t *g_out = G + (size_t)(i0 + v) * H + j;
         if (w.dead || w.lo > w.hi) {
-            bracket_store(sm, id, g_out, n, INF, -1);
+            bracket_store(sm, id, n, INF, -1);
         } else {
             int32_t best = n + 2, bk = -1;
             if (key != ~0ull) {
@@ -927,7 +925,7 @@ __device__ __forceinline__ void bracket_coarse(BracketSmemT<C> &sm, const int32_
             const bool done = (kend >= w.hi) | (xl > w.xb) | (best == w.vlo) |
                               ((best <= n) & (xl - kend >= best - j));
             if (done) {
-                bracket_store(sm, id, g_out, n, best, bk);
+                bracket_store(sm, id, n, best, bk);
             } else {  // provisional state; pass 2 resumes at lo + g * kCoarseBatch
                 stk(sm, id, bk);
                 sm.v[id] = (typename C::St)imin(best, n + 1);
@@ -1033,7 +1031,7 @@ __device__ __forceinline__ void bracket_levels(BracketSmemT<C> &sm, const int32_
                     best = (int32_t)(key >> 32);
                     bk = (int32_t)(uint32_t)(key & 0xffffffffull);
                 }
-                bracket_store(sm, idq, G + (size_t)(i0 + v) * H + j0 + jj, n, best, bk);
+                bracket_store(sm, idq, n, best, bk);
             }
             __syncthreads();
         } else if (qn > 0) {
@@ -1051,9 +1049,43 @@ __device__ __forceinline__ void bracket_levels(BracketSmemT<C> &sm, const int32_
                     if (batch_reduce<kPass2Batch>(j, k0, 1, wq.hi, wq.xb, wq.vlo, n, xs, vs, best, bk))
                         break;
                 }
-                bracket_store(sm, idq, G + (size_t)(i0 + v) * H + j, n, best, bk);
+                bracket_store(sm, idq, n, best, bk);
             }
             __syncthreads();
+        }
+    }
+}
+
+// LDS copy of D_U for a tile: sm.u[v * kUW + c] = D_U(i0 + v, org - v + c)
+// for v = 0..len and c = 0..kUW-1, with k clamped into 0..hU and values
+// clamped to INF.  Four consecutive entries per thread: one address, four
+// loads, one LDS store.
+template <class C>
+__device__ __forceinline__ void bracket_copy_u(BracketSmemT<C> &sm, const int32_t *__restrict__ U,
+                                               int32_t ldU, int32_t hU, int32_t i0, int32_t len,
+                                               int32_t org, int32_t INF) {
+    constexpr int32_t UW = C::kUW;
+    static_assert(UW % 4 == 0, "the D_U window is copied four entries at a time");
+    constexpr int32_t Q = UW / 4;
+    for (int32_t e = threadIdx.x; e < (len + 1) * Q; e += kBlock) {
+        const int32_t v = e / Q, c = (e - v * Q) * 4;
+        const int32_t k0 = org - v + c;
+        const int32_t *__restrict__ row = U + (size_t)(i0 + v) * ldU;
+        uint32_t x[4];
+        if (k0 >= 0 && k0 + 3 <= hU) {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) x[t] = (uint32_t)row[k0 + t];
+        } else {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) x[t] = (uint32_t)row[imin(imax(k0 + t, 0), hU)];
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) x[t] = x[t] < (uint32_t)INF ? x[t] : (uint32_t)INF;
+        if constexpr (sizeof(typename C::St) == 2) {
+            *reinterpret_cast<uint2 *>(&sm.u[v * UW + c]) =
+                make_uint2(x[0] | (x[1] << 16), x[2] | (x[3] << 16));
+        } else {
+            *reinterpret_cast<uint4 *>(&sm.u[v * UW + c]) = make_uint4(x[0], x[1], x[2], x[3]);
         }
     }
 }
@@ -1084,13 +1116,7 @@ __device__ __forceinline__ void bracket_block(const int32_t *__restrict__ U, int
     // the tile-end loads.
     constexpr int32_t UW = C::kUW;
     const bool full = hU + len + 1 <= UW;
-    if (full) {
-        for (int32_t e = threadIdx.x; e < (len + 1) * UW; e += kBlock) {
-            const int32_t v = e / UW, c = e - v * UW;
-            const int32_t k = imin(imax(c - v, 0), hU);
-            sm.u[v * UW + c] = (typename C::St)umin(U[(size_t)(i0 + v) * ldU + k], INF);
-        }
-    }
+    if (full) bracket_copy_u<C>(sm, U, ldU, hU, i0, len, 0, INF);
     // Tile ends, in every wave: lane l holds k*(i0, j0 + l + 64 c) and
     // k*(i1, j0 + l + 64 c); wave 0 also stores them (and the ends' values)
     // in LDS.  Reachability from i0 is a prefix of the weights.
@@ -1139,13 +1165,8 @@ __device__ __forceinline__ void bracket_block(const int32_t *__restrict__ U, int
     }
     const bool lds_u = full || ((kbl >= 0) && (kbl - ka0 + len + 1 <= UW));
     const int32_t ubase = full ? 0 : ka0;
-    if (lds_u && !full) {  // copy the D_U parallelogram (all rows: an idle output reads row 0)
-        for (int32_t e = threadIdx.x; e < (len + 1) * UW; e += kBlock) {
-            const int32_t v = e / UW, c = e - v * UW;
-            const int32_t k = imin(imax(ka0 - v + c, 0), hU);
-            sm.u[v * UW + c] = (typename C::St)umin(U[(size_t)(i0 + v) * ldU + k], INF);
-        }
-    }
+    // the D_U parallelogram (all rows: an idle output reads row 0)
+    if (lds_u && !full) bracket_copy_u<C>(sm, U, ldU, hU, i0, len, ka0, INF);
     if ((jn > S) && threadIdx.x >= 1 && (int32_t)threadIdx.x < len)
         G[(size_t)(i0 + threadIdx.x) * H + j0 + S] = L[(size_t)sm.xlast[threadIdx.x] * ldL + (j0 + S - hU)];
     __syncthreads();
@@ -1153,6 +1174,12 @@ __device__ __forceinline__ void bracket_block(const int32_t *__restrict__ U, int
         bracket_levels<C, true, kCoop>(sm, U, hU, L, hL, G, n, i0, len, j0, js, ubase);
     else
         bracket_levels<C, false, kCoop>(sm, U, hU, L, hL, G, n, i0, len, j0, js, ubase);
+    // the block's outputs, tile vertices 1..len-1 x weights j0..j0+js-1, leave
+    // LDS as contiguous row segments
+    for (int32_t e = threadIdx.x; e < (len - 1) * S; e += kBlock) {
+        const int32_t t = 1 + e / S, jj = e - (t - 1) * S;
+        if (jj < js) G[(size_t)(i0 + t) * H + j0 + jj] = (int32_t)sm.v[t * S + jj];
+    }
     __syncthreads();
 }
 
