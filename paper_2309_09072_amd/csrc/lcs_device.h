@@ -435,7 +435,7 @@ __device__ __forceinline__ int32_t anchor_u(const int32_t *__restrict__ U, uint3
 }
 
 template <bool kLds, int NT, int CPT>
-__device__ void anchor_block_t(const int32_t *__restrict__ U, int32_t hU,
+__device__ __forceinline__ void anchor_block_t(const int32_t *__restrict__ U, int32_t hU,
                                const int32_t *__restrict__ L, int32_t hL, int32_t *__restrict__ G,
                                int32_t n, int32_t vtx, int32_t *__restrict__ Krow,
                                AnchorSmem<NT, CPT> &sm, int32_t *us, int32_t *ks) {
@@ -781,8 +781,6 @@ __device__ __forceinline__ void bracket_pass1(BracketSmemT<C> &sm, const int32_t
     const int32_t H = hU + hL + 1;
     const int32_t ldU = hU + 1, ldL = hL + 1;
     const int32_t lane = __lane_id();
-    // at the finest level only values are needed (no vertex brackets another)
-    const bool finest = (st == 2);
     int32_t id[R], vr[R], jv[R], lo[R], hi[R], xb[R], vlo[R];
     bool act[R];
 #pragma unroll
@@ -804,9 +802,6 @@ __device__ __forceinline__ void bracket_pass1(BracketSmemT<C> &sm, const int32_t
                                                          imin(v + half, len), jj, js, j, hU, hL, n);
             if (w.dead || w.lo > w.hi) {
                 bracket_store(sm, id[r], n, INF, -1);
-            } else if (finest && w.vlo == w.vhi) {
-                // the interlacing bounds meet: the value is fixed
-                bracket_store(sm, id[r], n, w.vlo, 0);
             } else {
                 act[r] = true;
                 vr[r] = v;
@@ -860,6 +855,100 @@ __device__ __forceinline__ void bracket_pass1(BracketSmemT<C> &sm, const int32_t
             }
         }
     }
+}
+
+// Finest bisection level (every other vertex; only values are needed).  Each
+// wave first tries the value bounds of its outputs, which meet for most of
+// them (the rows of the two neighbours interlace around each), and collects
+// the others in a wave-local list; it then searches the listed outputs one
+// per lane, B candidates each with all loads in flight, so no candidate is
+// loaded for an output whose value is already fixed and one round trip serves
+// all of the wave's searched outputs.  Unfinished outputs go to the level
+// queue for pass 2 (which resumes at lo + B).  The list lives in sm.key (128
+// entries per wave), which no other part of the block uses meanwhile; it is
+// set back to the all-ones state the coarse levels and pass 2 expect.
+template <class C, int B, bool kLds>
+__device__ __forceinline__ void bracket_finest(BracketSmemT<C> &sm, const int32_t *__restrict__ U,
+                                               int32_t hU, const int32_t *__restrict__ L,
+                                               int32_t hL, int32_t n, int32_t i0, int32_t len,
+                                               int32_t j0, int32_t js, int32_t nitems, int32_t par,
+                                               int32_t ubase) {
+    constexpr int32_t S = C::kJ;
+    constexpr int32_t kCap = 2 * kWave;  // list entries per wave
+    static_assert(sizeof(sm.key) >= (size_t)kWaves * kCap * sizeof(uint16_t), "list space");
+    const int32_t INF = n + 1;
+    const int32_t ldU = hU + 1, ldL = hL + 1;
+    const int32_t lane = __lane_id();
+    const int32_t wv = (int32_t)threadIdx.x / kWave;
+    uint16_t *list = reinterpret_cast<uint16_t *>(sm.key) + wv * kCap;
+    const int32_t rounds = (nitems + kBlock - 1) / kBlock;
+    int32_t cnt = 0;  // wave-uniform
+    for (int32_t r = 0; r < rounds; ++r) {
+        const int32_t e = r * kBlock + (int32_t)threadIdx.x;
+        const int32_t t = e / S, jj = e - t * S;
+        const int32_t v = 1 + 2 * t;
+        bool pend = false;
+        if (e < nitems && jj < js) {
+            const BracketWindow w = bracket_window<C, kLds>(sm, U, ldU, i0, ubase, v, v - 1,
+                                                         imin(v + 1, len), jj, js, j0 + jj, hU, hL, n);
+            if (w.dead || w.lo > w.hi)
+                bracket_store(sm, v * S + jj, n, INF, -1);
+            else if (w.vlo == w.vhi)  // the interlacing bounds meet: the value is fixed
+                bracket_store(sm, v * S + jj, n, w.vlo, 0);
+            else
+                pend = true;
+        }
+        const unsigned long long m = __ballot(pend);
+        if (pend) list[cnt + __popcll(m & ((1ull << lane) - 1ull))] = (uint16_t)(v * S + jj);
+        cnt += __popcll(m);
+        if (cnt <= kWave && r < rounds - 1) continue;
+        anchor_sync<kWave>();  // the list is written before any lane reads it
+        for (int32_t p0 = 0; p0 < cnt; p0 += kWave) {
+            const bool act = p0 + lane < cnt;
+            const int32_t id = act ? (int32_t)list[p0 + lane] : 0;
+            const int32_t vq = id / S, jq = id - vq * S;
+            int32_t vr = 0, jv = 0, lo = kLds ? ubase : 0, hi = lo, xb = n, vlo = -1;
+            if (act) {
+                const BracketWindow w = bracket_window<C, kLds>(sm, U, ldU, i0, ubase, vq, vq - 1,
+                                                             imin(vq + 1, len), jq, js, j0 + jq, hU,
+                                                             hL, n);
+                vr = vq;
+                jv = j0 + jq;
+                lo = w.lo;
+                hi = w.hi;
+                xb = w.xb;
+                vlo = w.vlo;
+            }
+            int32_t xs[B], vs[B];
+            bracket_load_u<C, B, kLds>(sm, U, ldU, hU, i0, ubase, vr, lo, hi, n, xs);
+            batch_load_l<true, B>(L, ldL, jv, lo, 1, hi, xs, vs);
+            int32_t best = n + 2, bk = -1;
+            const bool done = batch_reduce<B>(jv, lo, 1, hi, xb, vlo, n, xs, vs, best, bk);
+            bool queued = false;
+            if (act) {
+                if (done) {
+                    bracket_store(sm, id, n, best, bk);
+                } else {  // provisional state; pass 2 resumes at lo + B
+                    stk(sm, id, bk);
+                    sm.v[id] = (typename C::St)imin(best, n + 1);
+                    queued = true;
+                }
+            }
+            const unsigned long long mq = __ballot(queued);
+            if (mq) {
+                const int32_t leader = __ffsll((long long)mq) - 1;
+                int32_t qbase = 0;
+                if (lane == leader) qbase = atomicAdd(&sm.qn[par], __popcll(mq));
+                qbase = __shfl(qbase, leader, kWave);
+                if (queued) sm.q[qbase + __popcll(mq & ((1ull << lane) - 1ull))] = (typename C::St)id;
+            }
+        }
+        anchor_sync<kWave>();  // every lane has read the list before it is refilled
+        cnt = 0;
+    }
+    // the list space back to the all-ones (value, k) minima
+    if (lane < kCap * (int32_t)sizeof(uint16_t) / 8)
+        sm.key[wv * (kCap * (int32_t)sizeof(uint16_t) / 8) + lane] = ~0ull;
 }
 
 // Coarse bisection level (at most kCoarseItems outputs, wide windows): g
@@ -967,7 +1056,10 @@ __device__ __forceinline__ void bracket_levels(BracketSmemT<C> &sm, const int32_
         // first pass: coarse levels spread each window over g threads; the
         // fine levels (most outputs, narrow windows) take batches of 4
         int32_t b1;
-        if (nitems <= kCoarseItems) {
+        if (st == 2) {
+            b1 = 3;
+            bracket_finest<C, 3, kLds>(sm, U, hU, L, hL, n, i0, len, j0, js, nitems, par, ubase);
+        } else if (nitems <= kCoarseItems) {
             int32_t g = 2;
             while (2 * g * nitems <= kBlock) g <<= 1;
             b1 = g * kCoarseBatch;
