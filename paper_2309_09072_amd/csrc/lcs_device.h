@@ -1150,8 +1150,9 @@ __device__ __forceinline__ void bracket_levels(BracketSmemT<C> &sm, const int32_
 
 // LDS copy of D_U for a tile: sm.u[v * kUW + c] = D_U(i0 + v, org - v + c)
 // for v = 0..len and c = 0..kUW-1, with k clamped into 0..hU and values
-// clamped to INF.  Four consecutive entries per thread: one address, four
-// loads, one LDS store.
+// clamped to INF.  Four consecutive entries per thread and pass: one address,
+// four loads, one LDS store.  All passes' loads are issued before the first
+// LDS store, so the whole copy costs one memory round trip.
 template <class C>
 __device__ __forceinline__ void bracket_copy_u(BracketSmemT<C> &sm, const int32_t *__restrict__ U,
                                                int32_t ldU, int32_t hU, int32_t i0, int32_t len,
@@ -1159,25 +1160,37 @@ __device__ __forceinline__ void bracket_copy_u(BracketSmemT<C> &sm, const int32_
     constexpr int32_t UW = C::kUW;
     static_assert(UW % 4 == 0, "the D_U window is copied four entries at a time");
     constexpr int32_t Q = UW / 4;
-    for (int32_t e = threadIdx.x; e < (len + 1) * Q; e += kBlock) {
-        const int32_t v = e / Q, c = (e - v * Q) * 4;
+    constexpr int32_t kPasses = ((kMaxTile + 1) * Q + kBlock - 1) / kBlock;
+    const int32_t total = (len + 1) * Q;
+    uint32_t x[kPasses][4];
+#pragma unroll
+    for (int it = 0; it < kPasses; ++it) {
+        const int32_t e = (int32_t)threadIdx.x + it * kBlock;
+        const int32_t v = imin(e, total - 1) / Q, c = (imin(e, total - 1) - v * Q) * 4;
         const int32_t k0 = org - v + c;
         const int32_t *__restrict__ row = U + (size_t)(i0 + v) * ldU;
-        uint32_t x[4];
         if (k0 >= 0 && k0 + 3 <= hU) {
 #pragma unroll
-            for (int t = 0; t < 4; ++t) x[t] = (uint32_t)row[k0 + t];
+            for (int t = 0; t < 4; ++t) x[it][t] = (uint32_t)row[k0 + t];
         } else {
 #pragma unroll
-            for (int t = 0; t < 4; ++t) x[t] = (uint32_t)row[imin(imax(k0 + t, 0), hU)];
+            for (int t = 0; t < 4; ++t) x[it][t] = (uint32_t)row[imin(imax(k0 + t, 0), hU)];
         }
+    }
 #pragma unroll
-        for (int t = 0; t < 4; ++t) x[t] = x[t] < (uint32_t)INF ? x[t] : (uint32_t)INF;
-        if constexpr (sizeof(typename C::St) == 2) {
-            *reinterpret_cast<uint2 *>(&sm.u[v * UW + c]) =
-                make_uint2(x[0] | (x[1] << 16), x[2] | (x[3] << 16));
-        } else {
-            *reinterpret_cast<uint4 *>(&sm.u[v * UW + c]) = make_uint4(x[0], x[1], x[2], x[3]);
+    for (int it = 0; it < kPasses; ++it) {
+        const int32_t e = (int32_t)threadIdx.x + it * kBlock;
+        if (e < total) {
+            const int32_t v = e / Q, c = (e - v * Q) * 4;
+            uint32_t y[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) y[t] = x[it][t] < (uint32_t)INF ? x[it][t] : (uint32_t)INF;
+            if constexpr (sizeof(typename C::St) == 2) {
+                *reinterpret_cast<uint2 *>(&sm.u[v * UW + c]) =
+                    make_uint2(y[0] | (y[1] << 16), y[2] | (y[3] << 16));
+            } else {
+                *reinterpret_cast<uint4 *>(&sm.u[v * UW + c]) = make_uint4(y[0], y[1], y[2], y[3]);
+            }
         }
     }
 }
