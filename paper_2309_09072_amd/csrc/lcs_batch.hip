@@ -458,7 +458,8 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6))
 k_stage_anchor_lds(BatchArgs A, StageArgs S, int32_t hc) {
     extern __shared__ unsigned long long dyn[];
     __shared__ int32_t s_pu[2];
-    const int64_t t = blockIdx.x;
+    // neighbouring anchors on one XCD (see anchor_block_id in lcs_kernels.hip)
+    const int64_t t = xcd_block((int32_t)blockIdx.x, (int32_t)gridDim.x, imax(1, (int32_t)gridDim.x / 8));
     if (threadIdx.x == 0) {
         int32_t lo = 0, hi = S.npairs - 1;
         while (lo < hi) {
@@ -500,7 +501,8 @@ __global__ void __launch_bounds__(kBlock) k_stage_anchor_wave(BatchArgs A, Stage
                                                               int32_t bytes, int64_t items) {
     extern __shared__ unsigned long long dyn[];
     const int32_t wv = uniform((int32_t)threadIdx.x / kWave);  // the same on every lane of a wave
-    const int64_t t = (int64_t)blockIdx.x * kWaves + wv;
+    const int64_t t = (int64_t)xcd_block((int32_t)blockIdx.x, (int32_t)gridDim.x,
+                                         imax(1, (int32_t)gridDim.x / 8)) * kWaves + wv;
     if (t >= items) return;
     int32_t lo = 0, hi = S.npairs - 1;
     while (lo < hi) {

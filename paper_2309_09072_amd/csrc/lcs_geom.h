@@ -91,6 +91,20 @@ LCS_HD int32_t *parent_strip(const CombineArgs &c, int32_t p) {
     return (p < c.np - 1) ? c.pbase + (size_t)p * strip_elems(c.n, 2 * c.hc) : c.plast;
 }
 
+// Work-groups go to the chip's 8 XCDs (each with its own L2) round-robin by
+// linear id.  xcd_block maps the linear id b of N blocks to a logical block so
+// that each XCD runs groups of g consecutive logical blocks; blocks of an
+// incomplete last round keep their id.  With g = N / 8 every XCD gets one
+// contiguous range.
+LCS_HD int32_t xcd_block(int32_t b, int32_t N, int32_t g) {
+    constexpr int32_t X = 8;
+    if (g <= 1) return b;
+    const int32_t full = (N / (X * g)) * (X * g);
+    if (b >= full) return b;
+    const int32_t x = b % X, q = b / X;
+    return ((q / g) * X + x) * g + (q % g);
+}
+
 LCS_HD int32_t anchor_vertex(int32_t a, int32_t tile, int32_t n) {
     int64_t v = (int64_t)a * tile;
     return v < n ? (int32_t)v : n;

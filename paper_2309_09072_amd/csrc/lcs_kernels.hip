@@ -30,12 +30,23 @@ __global__ void __launch_bounds__(kBlock) k_base(const uint8_t *a, int32_t n, in
                                 err, reinterpret_cast<int32_t *>(smem), smem);
 }
 
+// Anchor searches of neighbouring vertices gather from nearly the same rows
+// and columns of D_L, and those gathers are one cache line each (the anchor
+// kernels move ~25x their algorithmic bytes).  The launch is remapped so that
+// each XCD runs one contiguous range of (pair, anchor) blocks: a line then
+// comes into one L2 and serves the neighbours there.
+__device__ __forceinline__ int32_t anchor_block_id() {
+    const int32_t N = (int32_t)(gridDim.x * gridDim.y);
+    return xcd_block((int32_t)(blockIdx.x + blockIdx.y * gridDim.x), N, imax(1, N / 8));
+}
+
 // Anchor search with the D_U row and the k* row of the vertex in LDS
 // (dynamic: the search's AnchorSmem, then hc + 1 and 2 hc + 1 int32).
 template <int NT, int CPT>
 __global__ void __launch_bounds__(NT) k_anchor_lds(CombineArgs c) {
     extern __shared__ unsigned long long dyn[];
-    const int32_t p = blockIdx.y, a = blockIdx.x;
+    const int32_t lb = anchor_block_id();
+    const int32_t p = lb / (int32_t)gridDim.x, a = lb - p * (int32_t)gridDim.x;
     const StripRef U = child_strip(c, 2 * p), L = child_strip(c, 2 * p + 1);
     int32_t *G = parent_strip(c, p);
     const int32_t vtx = anchor_vertex(a, c.tile, c.n);
@@ -59,7 +70,8 @@ template <int CPT>
 __global__ void __launch_bounds__(kBlock) k_anchor_wave(CombineArgs c, int32_t bytes) {
     extern __shared__ unsigned long long dyn[];
     const int32_t wv = (int32_t)threadIdx.x / kWave;
-    const int32_t p = blockIdx.y, a = (int32_t)blockIdx.x * kWaves + wv;
+    const int32_t lb = anchor_block_id();
+    const int32_t p = lb / (int32_t)gridDim.x, a = (lb - p * (int32_t)gridDim.x) * kWaves + wv;
     if (a >= c.nanch) return;
     const StripRef U = child_strip(c, 2 * p), L = child_strip(c, 2 * p + 1);
     int32_t *G = parent_strip(c, p);
@@ -81,7 +93,8 @@ __global__ void __launch_bounds__(kBlock) k_anchor_wave(CombineArgs c, int32_t b
 template <int NT, int CPT>
 __global__ void __launch_bounds__(NT) k_anchor(CombineArgs c) {
     __shared__ AnchorSmem<NT, CPT> sm;
-    const int32_t p = blockIdx.y, a = blockIdx.x;
+    const int32_t lb = anchor_block_id();
+    const int32_t p = lb / (int32_t)gridDim.x, a = lb - p * (int32_t)gridDim.x;
     const StripRef U = child_strip(c, 2 * p), L = child_strip(c, 2 * p + 1);
     int32_t *G = parent_strip(c, p);
     const int32_t vtx = anchor_vertex(a, c.tile, c.n);
