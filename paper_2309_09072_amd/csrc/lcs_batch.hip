@@ -365,7 +365,7 @@ __global__ void __launch_bounds__(kBlock) k_pair_queue(BatchArgs A, const int32_
 
 // One step of the staged mode: the items of every participating pair, as a
 // queue of work-groups.  Item t belongs to the pair j with
-// first[j] <= t < first[j + 1] (binary search).
+// first[j] <= t < first[j + 1] (stage_item below).
 struct StageArgs {
     int32_t kind, level, npairs;
     int32_t jchunk;         // weights per bracket task (the bracket shape's kJ)
@@ -373,27 +373,33 @@ struct StageArgs {
     const int64_t *first;   // their first item, plus the total at [npairs]
 };
 
+// The pair of item t and t's index among that pair's items, found by the whole
+// wave: each round loads 64 evenly spaced entries of first[] at once and keeps
+// the last one <= t (first[] never decreases and first[0] = 0 <= t), so 4096
+// pairs take two rounds of loads instead of a dozen dependent ones.  Every
+// lane returns the same pair; t must be the same on every lane.
+__device__ __forceinline__ int2 stage_item(const StageArgs &S, int64_t t) {
+    const int32_t lane = __lane_id();
+    int32_t lo = 0, cnt = S.npairs;
+    while (cnt > 1) {
+        const int32_t stride = (cnt + kWave - 1) / kWave;
+        const int32_t off = lane * stride;
+        const bool le = off < cnt && S.first[lo + off] <= t;
+        const int32_t l = 63 - __clzll((long long)__ballot(le));
+        lo = uniform(lo + l * stride);
+        cnt = uniform(imin(stride, cnt - l * stride));
+    }
+    return make_int2(uniform(S.pair[lo]), uniform((int32_t)(t - S.first[lo])));
+}
+
 // Instantiated per step kind, so each step gets its own register allocation
 // (a kernel that could run any step would carry the largest one everywhere).
 template <int H0, int KIND>
 __global__ void __launch_bounds__(kBlock) k_stage(BatchArgs A, StageArgs S) {
     __shared__ PersistentSmem sm;
-    __shared__ int32_t s_pu[2];
     const int64_t t = blockIdx.x;
-    if (threadIdx.x == 0) {
-        int32_t lo = 0, hi = S.npairs - 1;
-        while (lo < hi) {
-            const int32_t mid = (lo + hi + 1) >> 1;
-            if (S.first[mid] <= t)
-                lo = mid;
-            else
-                hi = mid - 1;
-        }
-        s_pu[0] = S.pair[lo];
-        s_pu[1] = (int32_t)(t - S.first[lo]);
-    }
-    __syncthreads();
-    const int32_t p = uniform(s_pu[0]), u = uniform(s_pu[1]);
+    const int2 pu = stage_item(S, t);
+    const int32_t p = pu.x, u = pu.y;
     exec_task<H0, false>(A, A.ws + A.pairs[p].ws_off, p, KIND, S.level, u, sm);
 }
 
@@ -403,23 +409,10 @@ template <int H0, int kMode>
 __global__ void __launch_bounds__(kBlock) k_stage_base(BatchArgs A, StageArgs S) {
     static_assert(kMode == kBaseTab16Mode, "the global-table form runs in k_stage");
     __shared__ __align__(16) uint8_t smem[base_smem_bytes<H0, kMode>()];  // table, then transposition
-    __shared__ int32_t s_pu[2];
     const int64_t t = blockIdx.x;
-    if (threadIdx.x == 0) {
-        int32_t lo = 0, hi = S.npairs - 1;
-        while (lo < hi) {
-            const int32_t mid = (lo + hi + 1) >> 1;
-            if (S.first[mid] <= t)
-                lo = mid;
-            else
-                hi = mid - 1;
-        }
-        s_pu[0] = S.pair[lo];
-        s_pu[1] = (int32_t)(t - S.first[lo]);
-    }
-    __syncthreads();
-    const PairRec &P = A.pairs[uniform(s_pu[0])];
-    base_task<H0, kMode>(A, A.ws + P.ws_off, P, uniform(s_pu[1]), reinterpret_cast<int32_t *>(smem), smem);
+    const int2 pu = stage_item(S, t);
+    const PairRec &P = A.pairs[pu.x];
+    base_task<H0, kMode>(A, A.ws + P.ws_off, P, pu.y, reinterpret_cast<int32_t *>(smem), smem);
 }
 
 // Staged bracket tasks (one tile x one weight chunk each) in the bracket shape
@@ -429,23 +422,10 @@ template <int H0, class C, bool kCoop = false>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8)))
 k_stage_bracket(BatchArgs A, StageArgs S) {
     __shared__ BracketSmemT<C> sm;
-    __shared__ int32_t s_pu[2];
     const int64_t t = blockIdx.x;
-    if (threadIdx.x == 0) {
-        int32_t lo = 0, hi = S.npairs - 1;
-        while (lo < hi) {
-            const int32_t mid = (lo + hi + 1) >> 1;
-            if (S.first[mid] <= t)
-                lo = mid;
-            else
-                hi = mid - 1;
-        }
-        s_pu[0] = S.pair[lo];
-        s_pu[1] = (int32_t)(t - S.first[lo]);
-    }
-    __syncthreads();
-    const PairRec &P = A.pairs[uniform(s_pu[0])];
-    bracket_task<C, kCoop>(A, A.ws + P.ws_off, P, S.level, uniform(s_pu[1]), sm);
+    const int2 pu = stage_item(S, t);
+    const PairRec &P = A.pairs[pu.x];
+    bracket_task<C, kCoop>(A, A.ws + P.ws_off, P, S.level, pu.y, sm);
 }
 
 // Staged anchor search with the vertex's D_U row and k* row in dynamic LDS
@@ -457,23 +437,10 @@ template <int H0>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6)))
 k_stage_anchor_lds(BatchArgs A, StageArgs S, int32_t hc) {
     extern __shared__ unsigned long long dyn[];
-    __shared__ int32_t s_pu[2];
     // neighbouring anchors on one XCD (see anchor_block_id in lcs_kernels.hip)
     const int64_t t = xcd_block((int32_t)blockIdx.x, (int32_t)gridDim.x, imax(1, (int32_t)gridDim.x / 8));
-    if (threadIdx.x == 0) {
-        int32_t lo = 0, hi = S.npairs - 1;
-        while (lo < hi) {
-            const int32_t mid = (lo + hi + 1) >> 1;
-            if (S.first[mid] <= t)
-                lo = mid;
-            else
-                hi = mid - 1;
-        }
-        s_pu[0] = S.pair[lo];
-        s_pu[1] = (int32_t)(t - S.first[lo]);
-    }
-    __syncthreads();
-    const int32_t p = uniform(s_pu[0]), u = uniform(s_pu[1]);
+    const int2 pu = stage_item(S, t);
+    const int32_t p = pu.x, u = pu.y;
     const PairRec &P = A.pairs[p];
     uint8_t *ws = A.ws + P.ws_off;
     const CombineArgs c = pair_combine_args(P, ws, S.level, A.tile);
@@ -504,15 +471,8 @@ __global__ void __launch_bounds__(kBlock) k_stage_anchor_wave(BatchArgs A, Stage
     const int64_t t = (int64_t)xcd_block((int32_t)blockIdx.x, (int32_t)gridDim.x,
                                          imax(1, (int32_t)gridDim.x / 8)) * kWaves + wv;
     if (t >= items) return;
-    int32_t lo = 0, hi = S.npairs - 1;
-    while (lo < hi) {
-        const int32_t mid = (lo + hi + 1) >> 1;
-        if (S.first[mid] <= t)
-            lo = mid;
-        else
-            hi = mid - 1;
-    }
-    const int32_t p = S.pair[lo], u = (int32_t)(t - S.first[lo]);
+    const int2 pu = stage_item(S, t);
+    const int32_t p = pu.x, u = pu.y;
     const PairRec &P = A.pairs[p];
     uint8_t *ws = A.ws + P.ws_off;
     const CombineArgs c = pair_combine_args(P, ws, S.level, A.tile);
