@@ -262,6 +262,268 @@ __device__ void base_strip_block(const uint8_t *__restrict__ arow, int32_t h, in
 }
 
 // ---------------------------------------------------------------------------
+// Base strips from a combed seaweed permutation.  The breakout rows of a
+// strip are a function of LCS(a[r0:r1], b[i:c]) over all i <= c, and that
+// whole family is encoded by one permutation of "seaweeds" (Tiskin's
+// semi-local LCS): h seaweeds enter on the left (row r, label -(r+1)) and n
+// on the top (column c, label c); in each cell the two arriving seaweeds
+// turn at a match, and at a mismatch they cross unless they crossed before,
+// which with these labels is exactly "the horizontal label is the larger".
+// Row by row, with x the horizontal label entering column c and y the
+// vertical one:
+//     match:     down <- x, right <- y
+//     mismatch:  down <- max(x, y), right <- min(x, y).
+// Let bot[q] be the label leaving the bottom of column q.  The column where
+// the j-th step of LCS(strip, b[i:c]) happens as c grows is the j-th
+// smallest q + 1 with q >= i and bot[q] < i (a seaweed that started left of
+// i and ends below column q), so
+//     D(i, 0) = i,  D(i, j) = j-th such q + 1, n + 1 past the last,
+// and there are h - #{right-side exits with label < i} of them.  From vertex
+// i - 1 to i the set loses the element i (if bot[i-1] < i-1) and gains
+// pos[i-1] + 1 (pos = where top seaweed i-1 ends, if below a column >= i).
+// The result equals the row-append recurrence's exactly (both are D); the
+// work is O(h n) combing plus O(h) per vertex instead of O(h^2) per vertex.
+//
+// Combing of one strip by one work-group of NT threads, kCombCols columns per
+// thread per tile: the horizontal label of row r passes every column of the
+// tile from left to right, so each row is a prefix scan over the threads of
+// the per-column maps x -> (match ? y : min(x, y)), which compose within the
+// family {x -> const v} u {x -> min(x, v)}; the tiles go left to right, the
+// labels leaving a tile on the right entering the next.  Writes bot[0..n),
+// pos[0..n) (n + 1 for a seaweed that leaves on the right) and right[0..h).
+constexpr int32_t kCombCols = 16;
+constexpr int32_t kCombMaxThreads = 1024;
+constexpr int32_t kCombMaxRows = 256;
+
+// (c, v) stands for x -> c ? v : min(x, v); b := b after a
+__device__ __forceinline__ void comb_fn_after(int32_t ac, int32_t av, int32_t &bc, int32_t &bv) {
+    bv = bc ? bv : imin(av, bv);
+    bc |= ac;
+}
+
+// Inclusive scan of the maps over the lanes of a wave (lane l: lanes 0..l
+// composed in order).  Within each row of 16 lanes DPP row_shr:1,2,4,8 pulls
+// the maps of lower lanes (masked by lane id, as in wave_suffix_min); the row
+// totals of lanes 15, 31, 47 are folded in with readlane.
+__device__ __forceinline__ void wave_fn_scan(int32_t &c, int32_t &v) {
+    const int lane = __lane_id();
+    const int rl = lane & 15;
+    int32_t tc, tv;
+    tc = __builtin_amdgcn_mov_dpp(c, 0x111, 0xF, 0xF, false);  // row_shr:1
+    tv = __builtin_amdgcn_mov_dpp(v, 0x111, 0xF, 0xF, false);
+    if (rl >= 1) comb_fn_after(tc, tv, c, v);
+    tc = __builtin_amdgcn_mov_dpp(c, 0x112, 0xF, 0xF, false);  // row_shr:2
+    tv = __builtin_amdgcn_mov_dpp(v, 0x112, 0xF, 0xF, false);
+    if (rl >= 2) comb_fn_after(tc, tv, c, v);
+    tc = __builtin_amdgcn_mov_dpp(c, 0x114, 0xF, 0xF, false);  // row_shr:4
+    tv = __builtin_amdgcn_mov_dpp(v, 0x114, 0xF, 0xF, false);
+    if (rl >= 4) comb_fn_after(tc, tv, c, v);
+    tc = __builtin_amdgcn_mov_dpp(c, 0x118, 0xF, 0xF, false);  // row_shr:8
+    tv = __builtin_amdgcn_mov_dpp(v, 0x118, 0xF, 0xF, false);
+    if (rl >= 8) comb_fn_after(tc, tv, c, v);
+    int32_t pc = __builtin_amdgcn_readlane(c, 15), pv = __builtin_amdgcn_readlane(v, 15);
+    const int32_t r1c = __builtin_amdgcn_readlane(c, 31), r1v = __builtin_amdgcn_readlane(v, 31);
+    const int32_t r2c = __builtin_amdgcn_readlane(c, 47), r2v = __builtin_amdgcn_readlane(v, 47);
+    int32_t qc = r1c, qv = r1v;
+    comb_fn_after(pc, pv, qc, qv);  // rows 0..1
+    int32_t sc = r2c, sv = r2v;
+    comb_fn_after(qc, qv, sc, sv);  // rows 0..2
+    if (lane >= 48) {
+        comb_fn_after(sc, sv, c, v);
+    } else if (lane >= 32) {
+        comb_fn_after(qc, qv, c, v);
+    } else if (lane >= 16) {
+        comb_fn_after(pc, pv, c, v);
+    }
+}
+
+// lds: 3 * h + 4 * (NT / kWave) int32
+template <int NT>
+__device__ void comb_strip_block(const uint8_t *__restrict__ arow, int32_t h,
+                                 const uint8_t *__restrict__ b, int32_t n, int32_t sigma,
+                                 int32_t *__restrict__ bot, int32_t *__restrict__ pos,
+                                 int32_t *__restrict__ right, int32_t *lds, int32_t *err) {
+    constexpr int32_t C = kCombCols;
+    constexpr int32_t NW = NT / kWave;
+    const int32_t tid = threadIdx.x;
+    const int32_t nthr = (int32_t)blockDim.x;  // <= NT, a multiple of kWave
+    const int32_t w = tid / kWave;
+    const int lane = __lane_id();
+    int32_t *hin = lds, *hout = lds + h;                 // labels entering / leaving a tile, per row
+    int32_t *xs = lds + 2 * h;                           // the strip's row symbols
+    int32_t *wsc = lds + 3 * h, *wsv = wsc + 2 * NW;     // wave totals, two buffers
+    bool bad = false;
+    for (int32_t r = tid; r < h; r += nthr) {
+        hin[r] = -(r + 1);
+        xs[r] = arow[r];
+        bad |= xs[r] >= sigma;
+    }
+    const int32_t T = nthr * C;
+    for (int32_t c0 = 0; c0 < n; c0 += T) {
+        int32_t v[C], bs[C];
+        const int32_t cb = c0 + tid * C;
+#pragma unroll
+        for (int e = 0; e < C; ++e) {
+            const int32_t c = cb + e;
+            v[e] = (c < n) ? c : 0x7fffffff;   // a padding column maps x -> x
+            bs[e] = (c < n) ? (int32_t)b[c] : 0x100;
+        }
+        __syncthreads();  // hin of this tile written
+        int32_t buf = 0;
+        for (int32_t r = 0; r < h; ++r) {
+            const int32_t x = xs[r];
+            int32_t fc = 0, fv = 0x7fffffff;
+#pragma unroll
+            for (int e = 0; e < C; ++e) {
+                const bool m = bs[e] == x;
+                fv = m ? v[e] : imin(fv, v[e]);
+                fc |= (int32_t)m;
+            }
+            wave_fn_scan(fc, fv);
+            if (lane == kWave - 1) {
+                wsc[buf * NW + w] = fc;
+                wsv[buf * NW + w] = fv;
+            }
+            __syncthreads();
+            int32_t pc = 0, pv = 0x7fffffff;
+            for (int32_t w2 = 0; w2 < w; ++w2) {  // p := wave w2 after p
+                const int32_t bc = wsc[buf * NW + w2];
+                pv = bc ? wsv[buf * NW + w2] : imin(pv, wsv[buf * NW + w2]);
+                pc |= bc;
+            }
+            const int32_t xin = hin[r];
+            const int32_t xw = pc ? pv : imin(xin, pv);      // label entering wave w
+            const int32_t xl = fc ? fv : imin(xw, fv);       // label leaving this thread
+            // label entering this thread: the left neighbour's (wave_shr:1), lane 0: xw
+            int32_t hh = __builtin_amdgcn_update_dpp(xw, xl, 0x138, 0xF, 0xF, false);
+#pragma unroll
+            for (int e = 0; e < C; ++e) {
+                const int32_t y = v[e];
+                const bool m = bs[e] == x;
+                v[e] = m ? hh : imax(hh, y);
+                hh = m ? y : imin(hh, y);
+            }
+            if (tid == nthr - 1) hout[r] = hh;
+            buf ^= 1;
+        }
+#pragma unroll
+        for (int e = 0; e < C; ++e) {
+            const int32_t c = cb + e;
+            if (c < n) {
+                bot[c] = v[e];
+                if (v[e] >= 0) pos[v[e]] = c;
+            }
+        }
+        __syncthreads();  // hout complete, every read of hin done
+        int32_t *t = hin;
+        hin = hout;
+        hout = t;
+    }
+    __syncthreads();
+    for (int32_t r = tid; r < h; r += nthr) {
+        const int32_t lab = hin[r];
+        right[r] = lab;
+        if (lab >= 0) pos[lab] = n + 1;
+    }
+    if (__syncthreads_or(bad) && tid == 0) atomicOr(err, kErrSymbol);
+}
+
+// Breakout rows of vertices i0 .. i1-1 of one base strip (h rows) from its
+// combing, by one wave; vertex n + 1 is the all-unreachable sentinel row.
+// The wave keeps the sorted set {q + 1 : q >= i, bot[q] < i} (at most h
+// values, E per lane, element 64 e + lane in register e) and moves from
+// vertex to vertex by dropping the element i and inserting pos[i-1] + 1.
+// The first vertex's set comes from a scan of bot[i0..].  lst: 64 E int32 of
+// LDS for this wave alone.  out: the strip matrix, row length h + 1.
+template <int E>
+__device__ void dgen_wave(const int32_t *__restrict__ bot, const int32_t *__restrict__ pos,
+                          const int32_t *__restrict__ right, int32_t h, int32_t n, int32_t i0,
+                          int32_t i1, int32_t *__restrict__ out, int32_t *lst) {
+    const int32_t INF = n + 1;
+    const int32_t hp1 = h + 1;
+    const int lane = __lane_id();
+    const int32_t iend = imin(i1, n + 1);  // rows with a vertex
+    int32_t L[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) L[e] = INF;
+    if (i0 < iend) {
+        int32_t below = 0;  // right-side exits with label < i0
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int32_t r = e * kWave + lane;
+            below += __popcll(__ballot(r < h && right[r] < i0));
+        }
+        const int32_t K = h - below;
+        int32_t found = 0;
+        const unsigned long long lt = (1ull << lane) - 1ull;
+        for (int32_t q0 = i0; found < K && q0 < n; q0 += 4 * kWave) {
+            int32_t bv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int32_t q = q0 + u * kWave + lane;
+                bv[u] = (q < n) ? bot[q] : 0x7fffffff;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const bool hit = bv[u] < i0;
+                const unsigned long long mk = __ballot(hit);
+                const int32_t slot = found + __popcll(mk & lt);
+                if (hit && slot < E * kWave) lst[slot] = q0 + u * kWave + lane + 1;
+                found += __popcll(mk);
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        const int32_t cnt = imin(imin(found, K), E * kWave);
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int32_t j = e * kWave + lane;
+            if (j < cnt) L[e] = lst[j];
+        }
+    }
+    int32_t pv = INF;  // pos[i - 1 ..] for the next 64 vertices, one per lane
+    for (int32_t i = i0; i < iend; ++i) {
+        if (i > i0) {
+            const int32_t k = (i - 1 - i0) & (kWave - 1);
+            if (k == 0) {
+                const int32_t q = i - 1 + lane;
+                pv = (q < n) ? pos[q] : INF;
+            }
+            const int32_t t = __builtin_amdgcn_readlane(pv, k);
+            if (__builtin_amdgcn_readlane(L[0], 0) == i) {  // drop element i
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    const int32_t nx = (e + 1 < E) ? __builtin_amdgcn_readlane(L[e + 1 < E ? e + 1 : e], 0) : INF;
+                    L[e] = __builtin_amdgcn_update_dpp(nx, L[e], 0x130, 0xF, 0xF, false);  // wave_shl:1
+                }
+            }
+            if (t >= i && t < n) {  // insert t + 1
+                const int32_t val = t + 1;
+                int32_t pr[E];
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    const int32_t pe = (e > 0) ? __builtin_amdgcn_readlane(L[e > 0 ? e - 1 : 0], kWave - 1) : -1;
+                    pr[e] = __builtin_amdgcn_update_dpp(pe, L[e], 0x138, 0xF, 0xF, false);  // wave_shr:1
+                }
+#pragma unroll
+                for (int e = 0; e < E; ++e) L[e] = (L[e] < val) ? L[e] : ((pr[e] < val) ? val : pr[e]);
+            }
+        }
+        int32_t *row = out + (size_t)i * (size_t)hp1;
+        if (lane == 0) row[0] = i;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int32_t j = e * kWave + lane;
+            if (j < h) row[1 + j] = L[e];
+        }
+    }
+    if (i1 == n + 2) {
+        int32_t *row = out + (size_t)(n + 1) * (size_t)hp1;
+        for (int32_t j = lane; j <= h; j += kWave) row[j] = INF;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Candidate scan of the combine equation for one output (vertex row at offset urow of
 // D_U, weight j): candidates k = k0, k0+step, ... in increasing order, value
 // D_L(D_U(i, k), j - k).  Every k with max(0, j-hL) <= k <= min(j, hU) is a

@@ -30,6 +30,41 @@ __global__ void __launch_bounds__(kBlock) k_base(const uint8_t *a, int32_t n, in
                                 err, reinterpret_cast<int32_t *>(smem), smem);
 }
 
+// Seaweed combing of every base strip, one work-group (NT threads, fewer
+// for narrow strings) per strip; region comb holds comb_stride int32 per strip.
+template <int NT>
+__global__ void __launch_bounds__(NT) k_comb(const uint8_t *a, const uint8_t *b, int32_t n,
+                                             int32_t sigma, int32_t h0, int32_t nstrips,
+                                             int32_t hlast, int32_t *comb, int32_t cstride,
+                                             int32_t *err) {
+    __shared__ int32_t lds[3 * kCombMaxRows + 4 * (NT / kWave)];
+    const int32_t s = blockIdx.x;
+    const int32_t h = (s == nstrips - 1) ? hlast : h0;
+    int32_t *cs = comb + (size_t)s * (size_t)cstride;
+    comb_strip_block<NT>(a + (size_t)s * h0, h, b, n, sigma, cs, cs + n, cs + 2 * (size_t)n, lds, err);
+}
+
+// Breakout rows of every base strip from its combing: one wave per run of
+// `chunk` consecutive vertices of one strip (runs of a strip on one XCD).
+template <int E>
+__global__ void __launch_bounds__(kBlock) k_dgen(const int32_t *comb, int32_t cstride, int32_t n,
+                                                 int32_t h0, int32_t nstrips, int32_t hlast,
+                                                 int32_t *base0, int32_t *last, int32_t chunk,
+                                                 int32_t nchunks) {
+    __shared__ int32_t lst[kWaves][E * kWave];
+    const int32_t wv = __builtin_amdgcn_readfirstlane((int32_t)threadIdx.x / kWave);
+    const int64_t g = (int64_t)xcd_block((int32_t)blockIdx.x, (int32_t)gridDim.x,
+                                         imax(1, (int32_t)gridDim.x / 8)) * kWaves + wv;
+    if (g >= (int64_t)nstrips * nchunks) return;
+    const int32_t s = (int32_t)(g / nchunks), ck = (int32_t)(g - (int64_t)s * nchunks);
+    const bool is_last = (s == nstrips - 1);
+    const int32_t h = is_last ? hlast : h0;
+    int32_t *out = is_last ? last : base0 + (size_t)s * strip_elems(n, h0);
+    const int32_t *cs = comb + (size_t)s * (size_t)cstride;
+    const int32_t i0 = ck * chunk;
+    dgen_wave<E>(cs, cs + n, cs + 2 * (size_t)n, h, n, i0, imin(i0 + chunk, n + 2), out, lst[wv]);
+}
+
 // Anchor searches of neighbouring vertices gather from nearly the same rows
 // and columns of D_L, and those gathers are one cache line each (the anchor
 // kernels move ~25x their algorithmic bytes).  The launch is remapped so that
@@ -318,6 +353,34 @@ hipError_t launch_base(int32_t h0, const uint8_t *a, int32_t n, int32_t sigma, c
         case 64: launch_base_h<64>(grid, s, a, n, sigma, nm, base0, last, nstrips, hlast, err); break;
         default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_base_comb(int32_t h0, const uint8_t *a, const uint8_t *b, int32_t n,
+                            int32_t sigma, int32_t *base0, int32_t *last, int32_t nstrips,
+                            int32_t hlast, int32_t *comb, int32_t comb_stride, int32_t *err,
+                            hipStream_t s) {
+    if (h0 < 1 || h0 > kCombMaxRows) return hipErrorInvalidValue;
+    int32_t thr = (n + kCombCols - 1) / kCombCols;
+    thr = imin(kCombMaxThreads, imax(kWave, (thr + kWave - 1) / kWave * kWave));
+    hipLaunchKernelGGL((k_comb<kCombMaxThreads>), dim3(nstrips), dim3(thr), 0, s, a, b, n, sigma,
+                       h0, nstrips, hlast, comb, comb_stride, err);
+    // runs short enough that the waves fill the chip, long enough to amortise
+    // the scan for the first vertex of each run
+    int32_t chunk = 256;
+    while (chunk > 32 && (int64_t)nstrips * ((n + 2 + chunk - 1) / chunk) < 16384) chunk /= 2;
+    const int32_t nchunks = (n + 2 + chunk - 1) / chunk;
+    const int64_t waves = (int64_t)nstrips * nchunks;
+    const dim3 grid((uint32_t)((waves + kWaves - 1) / kWaves));
+    if (h0 <= kWave)
+        hipLaunchKernelGGL((k_dgen<1>), grid, dim3(kBlock), 0, s, comb, comb_stride, n, h0, nstrips,
+                           hlast, base0, last, chunk, nchunks);
+    else if (h0 <= 2 * kWave)
+        hipLaunchKernelGGL((k_dgen<2>), grid, dim3(kBlock), 0, s, comb, comb_stride, n, h0, nstrips,
+                           hlast, base0, last, chunk, nchunks);
+    else
+        hipLaunchKernelGGL((k_dgen<4>), grid, dim3(kBlock), 0, s, comb, comb_stride, n, h0, nstrips,
+                           hlast, base0, last, chunk, nchunks);
     return hipGetLastError();
 }
 

@@ -22,6 +22,8 @@ struct Layout {
     std::vector<int64_t> anch_off;   // per level: anchor argmin rows of its combines
     int64_t off_hdr = 0, off_nm = 0, total = 0;
     int64_t off_rev = -1;  // reversed strings of an oriented build (rows, then columns)
+    int64_t off_comb = 0;  // per base strip: the combed seaweeds (bot[n], pos[n], right[h0])
+    int32_t comb_stride = 0;  // int32 per base strip in that region
     int32_t nanch = 0;
 };
 
@@ -56,6 +58,9 @@ inline bool make_layout(int32_t m, int32_t n, int32_t sigma, int32_t h0, int32_t
                        (int64_t)strip_elems(n, g.hlast));
         off = align256(off + g.bytes);
         L.lev.push_back(g);
+        L.comb_stride = (2 * n + h0 + 63) & ~63;
+        L.off_comb = off;
+        off = align256(off + 4 * (int64_t)g.nstrips * L.comb_stride);
         while (L.lev.back().nstrips > 1) {
             const LevelGeom pv = L.lev.back();
             LevelGeom q{};
