@@ -468,6 +468,10 @@ def bench_pair(workload: str, steps: int, warmup: int, base_rows: int, tile: int
     stream = torch.cuda.current_stream()
     ad, bd = lcs.device_bytes(pair.a), lcs.device_bytes(pair.b)
     tuning = None
+    if base_rows == 0:  # the library's choice for this size
+        probe = lcs.Plan(m, n, pair.sigma, 0, max(tile, 4))
+        base_rows = probe.base_rows
+        probe.close()
     if tile == 0:  # the autotuner picks the tile for this base-strip height
         from paper_2309_09072_amd import tune
         tr = tune.tune_pair(ad, bd, pair.sigma, base_rows=base_rows, use_cache=False)
@@ -588,7 +592,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(WORKLOADS))
-    ap.add_argument("--base-rows", type=int, default=64)
+    ap.add_argument("--base-rows", type=int, default=0,
+                    help="rows per base strip; 0: the library's choice for the size")
     ap.add_argument("--tile", type=int, default=0,
                     help="vertices between anchor searches; 0: chosen by the autotuner")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)

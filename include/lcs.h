@@ -70,7 +70,11 @@ typedef struct lcs_plan_desc {
     int32_t max_n;     /* largest column-string length, >= 0 */
     int32_t alphabet;  /* number of symbol codes, 1..256 */
     int32_t base_rows; /* rows per base strip (Section II-B-3 generalised to
-                          base_rows rows): 16, 32 or 64; 0 selects 64 */
+                          base_rows rows): 16, 32, 64, 128 or 256; 0 selects
+                          by the sizes built (rows = max_m and columns = max_n,
+                          or the shorter and longer of the two with
+                          LCS_PLAN_ORIENT): 256 from 8192 rows or from 4096
+                          rows with 8192 columns, 128 from 4096 rows, else 64 */
     int32_t tile;      /* vertices per search tile of the combine: power of two
                           in 4..32; 0 selects the default (32) */
     uint32_t flags;    /* 0 or an OR of LCS_PLAN_PROFILE, LCS_PLAN_ORIENT */
@@ -101,6 +105,10 @@ int32_t lcs_plan(const lcs_plan_desc *desc, lcs_plan_t *out, size_t *workspace_b
 
 /* Workspace size for one pair of exact sizes (m, n) <= the plan's maxima. */
 int32_t lcs_plan_workspace(lcs_plan_t plan, int32_t m, int32_t n, size_t *workspace_bytes);
+
+/* The plan's descriptor with its defaults resolved (base_rows and tile as the
+ * builds use them) written to *out.  Errors: LCS_E_INVAL (null pointer). */
+int32_t lcs_plan_describe(lcs_plan_t plan, lcs_plan_desc *out);
 
 /* Release a plan (host memory only; the workspace stays the caller's). */
 int32_t lcs_plan_destroy(lcs_plan_t plan);

@@ -5,6 +5,7 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 #include <vector>
 
@@ -113,6 +114,13 @@ bool valid_shape(int32_t base_rows, int32_t tile) {
     if (base_rows != 16 && base_rows != 32 && base_rows != 64) return false;
     if (tile < 4 || tile > 32 || (tile & (tile - 1))) return false;
     return true;
+}
+
+// single-pair plans also take base strips of 128 and 256 rows (their base
+// strips are combed; the batch and serving paths append rows, up to 64)
+static bool valid_pair_shape(int32_t base_rows, int32_t tile) {
+    if (base_rows == 128 || base_rows == 256) return valid_shape(64, tile);
+    return valid_shape(base_rows, tile);
 }
 
 int32_t resolve(int32_t v, int32_t dflt) { return v == 0 ? dflt : v; }
@@ -225,12 +233,24 @@ extern "C" int32_t lcs_plan(const lcs_plan_desc *desc, lcs_plan_t *out, size_t *
     if (!desc || !out || !workspace_bytes) return LCS_E_INVAL;
     *out = nullptr;
     lcs_plan_desc d = *desc;
-    d.base_rows = resolve(d.base_rows, kDefaultBaseRows);
+    if (d.base_rows == 0) {
+        // Taller base strips replace combine levels; the combing of a strip is
+        // one work-group, so they pay once there are rows for many strips and
+        // columns enough to keep each busy (measured on MI355X: 64 rows up to
+        // 2048 x 2048, 128 at 4096 x 4096, 256 from 8192 x 8192 and at
+        // 4096 x 16384).
+        const bool orient = (d.flags & LCS_PLAN_ORIENT) != 0;
+        const int32_t rows = orient ? std::min(d.max_m, d.max_n) : d.max_m;
+        const int32_t cols = orient ? std::max(d.max_m, d.max_n) : d.max_n;
+        d.base_rows = (rows >= 8192 || (rows >= 4096 && cols >= 8192)) ? 256
+                      : rows >= 4096                                    ? 128
+                                                                        : kDefaultBaseRows;
+    }
     d.tile = resolve(d.tile, kDefaultTile);
     if (d.max_m < 0 || d.max_n < 0 || d.alphabet < 1 || d.alphabet > 256 ||
         (d.flags & ~(LCS_PLAN_PROFILE | LCS_PLAN_ORIENT)) != 0)
         return LCS_E_INVAL;
-    if (!valid_shape(d.base_rows, d.tile)) return LCS_E_INVAL;
+    if (!valid_pair_shape(d.base_rows, d.tile)) return LCS_E_INVAL;
     if (d.max_n > 0x7ffffff0 || d.max_m > 0x7ffffff0) return LCS_E_TOO_BIG;
     Layout L;
     if (!make_layout(d.max_m, d.max_n, d.alphabet, d.base_rows, d.tile, L)) return LCS_E_TOO_BIG;
@@ -250,6 +270,12 @@ extern "C" int32_t lcs_plan(const lcs_plan_desc *desc, lcs_plan_t *out, size_t *
     p->rec.on = (d.flags & LCS_PLAN_PROFILE) != 0;
     *workspace_bytes = (size_t)total;
     *out = p;
+    return LCS_OK;
+}
+
+extern "C" int32_t lcs_plan_describe(lcs_plan_t p, lcs_plan_desc *out) {
+    if (!p || !out) return LCS_E_INVAL;
+    *out = p->d;
     return LCS_OK;
 }
 

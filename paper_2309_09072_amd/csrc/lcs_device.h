@@ -284,14 +284,13 @@ __device__ void base_strip_block(const uint8_t *__restrict__ arow, int32_t h, in
 // The result equals the row-append recurrence's exactly (both are D); the
 // work is O(h n) combing plus O(h) per vertex instead of O(h^2) per vertex.
 //
-// Combing of one strip by one work-group of NT threads, kCombCols columns per
-// thread per tile: the horizontal label of row r passes every column of the
+// Combing of one strip by one work-group of NT threads, C columns per thread
+// per tile: the horizontal label of row r passes every column of the
 // tile from left to right, so each row is a prefix scan over the threads of
 // the per-column maps x -> (match ? y : min(x, y)), which compose within the
 // family {x -> const v} u {x -> min(x, v)}; the tiles go left to right, the
 // labels leaving a tile on the right entering the next.  Writes bot[0..n),
 // pos[0..n) (n + 1 for a seaweed that leaves on the right) and right[0..h).
-constexpr int32_t kCombCols = 16;
 constexpr int32_t kCombMaxThreads = 1024;
 constexpr int32_t kCombMaxRows = 256;
 
@@ -303,11 +302,11 @@ __device__ __forceinline__ void comb_fn_after(int32_t ac, int32_t av, int32_t &b
 
 // Inclusive scan of the maps over the lanes of a wave (lane l: lanes 0..l
 // composed in order).  Within each row of 16 lanes DPP row_shr:1,2,4,8 pulls
-// the maps of lower lanes (masked by lane id, as in wave_suffix_min); the row
-// totals of lanes 15, 31, 47 are folded in with readlane.
-__device__ __forceinline__ void wave_fn_scan(int32_t &c, int32_t &v) {
-    const int lane = __lane_id();
-    const int rl = lane & 15;
+// the maps of lower lanes (masked by lane id, as in wave_suffix_min; alone,
+// row_fn_scan); the row totals of lanes 15, 31, 47 are folded in with
+// readlane.
+__device__ __forceinline__ void row_fn_scan(int32_t &c, int32_t &v) {
+    const int rl = __lane_id() & 15;
     int32_t tc, tv;
     tc = __builtin_amdgcn_mov_dpp(c, 0x111, 0xF, 0xF, false);  // row_shr:1
     tv = __builtin_amdgcn_mov_dpp(v, 0x111, 0xF, 0xF, false);
@@ -321,6 +320,10 @@ __device__ __forceinline__ void wave_fn_scan(int32_t &c, int32_t &v) {
     tc = __builtin_amdgcn_mov_dpp(c, 0x118, 0xF, 0xF, false);  // row_shr:8
     tv = __builtin_amdgcn_mov_dpp(v, 0x118, 0xF, 0xF, false);
     if (rl >= 8) comb_fn_after(tc, tv, c, v);
+}
+__device__ __forceinline__ void wave_fn_scan(int32_t &c, int32_t &v) {
+    const int lane = __lane_id();
+    row_fn_scan(c, v);
     int32_t pc = __builtin_amdgcn_readlane(c, 15), pv = __builtin_amdgcn_readlane(v, 15);
     const int32_t r1c = __builtin_amdgcn_readlane(c, 31), r1v = __builtin_amdgcn_readlane(v, 31);
     const int32_t r2c = __builtin_amdgcn_readlane(c, 47), r2v = __builtin_amdgcn_readlane(v, 47);
@@ -338,16 +341,16 @@ __device__ __forceinline__ void wave_fn_scan(int32_t &c, int32_t &v) {
 }
 
 // lds: 3 * h + 4 * (NT / kWave) int32
-template <int NT>
+template <int NT, int C>
 __device__ void comb_strip_block(const uint8_t *__restrict__ arow, int32_t h,
                                  const uint8_t *__restrict__ b, int32_t n, int32_t sigma,
                                  int32_t *__restrict__ bot, int32_t *__restrict__ pos,
                                  int32_t *__restrict__ right, int32_t *lds, int32_t *err) {
-    constexpr int32_t C = kCombCols;
     constexpr int32_t NW = NT / kWave;
+    static_assert(NW <= 16, "the wave totals are scanned by one row of 16 lanes");
     const int32_t tid = threadIdx.x;
     const int32_t nthr = (int32_t)blockDim.x;  // <= NT, a multiple of kWave
-    const int32_t w = tid / kWave;
+    const int32_t w = __builtin_amdgcn_readfirstlane(tid / kWave);
     const int lane = __lane_id();
     int32_t *hin = lds, *hout = lds + h;                 // labels entering / leaving a tile, per row
     int32_t *xs = lds + 2 * h;                           // the strip's row symbols
@@ -385,11 +388,17 @@ __device__ void comb_strip_block(const uint8_t *__restrict__ arow, int32_t h,
                 wsv[buf * NW + w] = fv;
             }
             __syncthreads();
+            // the waves before w, composed: lanes 0..NW-1 scan the wave totals
             int32_t pc = 0, pv = 0x7fffffff;
-            for (int32_t w2 = 0; w2 < w; ++w2) {  // p := wave w2 after p
-                const int32_t bc = wsc[buf * NW + w2];
-                pv = bc ? wsv[buf * NW + w2] : imin(pv, wsv[buf * NW + w2]);
-                pc |= bc;
+            if (w > 0) {
+                int32_t tc = 0, tv = 0x7fffffff;
+                if (lane < NW) {
+                    tc = wsc[buf * NW + lane];
+                    tv = wsv[buf * NW + lane];
+                }
+                row_fn_scan(tc, tv);
+                pc = __builtin_amdgcn_readlane(tc, w - 1);
+                pv = __builtin_amdgcn_readlane(tv, w - 1);
             }
             const int32_t xin = hin[r];
             const int32_t xw = pc ? pv : imin(xin, pv);      // label entering wave w
@@ -1692,8 +1701,13 @@ __device__ void trace_leaf_block(const uint8_t *__restrict__ arow, int32_t h, in
         // bit w - 1 of the mask is set, and the matched rows are written out
         // by their lanes afterwards, with D_r(s, w) read from LDS.
         static_assert(H0 <= kWave, "one lane per column");
-        // the row matches of one source lie about H0 * sigma columns past it
-        const int32_t W = imin(imin(n + 2 - s, tabcap / imax(sigma, 1)), 8 * H0);
+        // Only weights up to w0 and columns up to e = D_h(s, w0) matter (as in
+        // trace_leaf_tall below): lookups from columns past e are skipped, so
+        // the table window [s, e] serves every lookup when it fits.
+        const int32_t w0c = imin(imax(node.y, 0), h);
+        const int32_t eend = imin(imax(node.z, s), n + 1);
+        const int32_t pmax = imin(eend, n);
+        const int32_t W = imin(imin(n + 2 - s, tabcap / imax(sigma, 1)), eend - s + 1);
         for (int32_t x = 0; x < sigma; ++x) {
             const int32_t *src = nm + (size_t)x * (n + 2) + s;
             int32_t *dst = tab + x * W;
@@ -1716,16 +1730,17 @@ __device__ void trace_leaf_block(const uint8_t *__restrict__ arow, int32_t h, in
             // D_r(s, j - 1): lane l - 1's value by a whole-wave DPP shift
             // (wave_shr:1); lane 0 keeps `s`, column 0
             const int32_t p = __builtin_amdgcn_update_dpp(s, d, 0x138, 0xF, 0xF, false);
+            const bool live = (j <= w0c) && (x < sigma) && (p <= pmax);
             int32_t cd = INF;
-            if (x < sigma && p <= n) cd = (p - s < W) ? tab[x * W + (p - s)] : nm[(size_t)x * (n + 2) + p];
+            if (live) cd = (p - s < W) ? tab[x * W + (p - s)] : nm[(size_t)x * (n + 2) + p];
             const int32_t dn = umin(d, cd);
-            const bool hit = (j <= h) && (x < sigma) && (p <= n) && (cd == dn);
+            const bool hit = live && (cd == dn);
             const unsigned long long mk = __ballot(hit);
             if (tid == r) {
                 mlo = (uint32_t)mk;
                 mhi = (uint32_t)(mk >> 32);
             }
-            d = (j <= h) ? dn : INF;
+            d = (j <= w0c) ? dn : INF;
             if (j <= h) lds[(r + 1) * S + j] = d;
         }
         // walk: uniform over the wave; lane w - 1 notes the row that matched
@@ -1783,6 +1798,139 @@ __device__ void trace_leaf_block(const uint8_t *__restrict__ arow, int32_t h, in
         if (w != 0 || e != s) atomicOr(err, kErrTrace);
     }
     __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Midpoint trace inside a base strip of up to 64 E rows (E = 2 or 4), by one
+// wave: the row appends of the one-wave form above with E columns per lane
+// (column j = 64 e + lane + 1 in register e), restricted to the weights
+// 1..w0 of the node.  Column j of D_{r+1}(s, .) depends only on columns j - 1
+// and j of D_r(s, .), and the walk reads no weight above w0, so every lookup
+// index is at most e = D_h(s, w0) and a table window [s, e] serves all of
+// them when it fits in LDS (lookups past the window read the global table).
+// Pass 1 keeps each row's match masks in LDS; the walk back picks the row
+// where each weight matched; pass 2 appends the rows again and each lane
+// keeps D_r(s, j) of the row r where weight j matched (that column - 1 is the
+// match in b).  Lookups from columns past e are skipped (see below), so with
+// the window [s, e] in LDS no lookup goes to the global table.  LDS: tab (tabcap int32), masks (h E u64), mrow and xs (64 E
+// int32 each).
+template <int E>
+__device__ __forceinline__ void leaf_row(int32_t (&d)[E], int32_t x, int32_t s, int32_t n,
+                                         int32_t sigma, int32_t wmax, int32_t pmax, const int32_t *tab,
+                                         int32_t W, const int32_t *__restrict__ nm,
+                                         unsigned long long (&mk)[E]) {
+    const int lane = __lane_id();
+    const int32_t INF = n + 1;
+    int32_t p[E];  // D_r(s, j - 1): the next lower column, across lanes and registers
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int32_t carry = (e == 0) ? s : __builtin_amdgcn_readlane(d[e > 0 ? e - 1 : 0], kWave - 1);
+        p[e] = __builtin_amdgcn_update_dpp(carry, d[e], 0x138, 0xF, 0xF, false);  // wave_shr:1
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int32_t j = e * kWave + lane + 1;
+        const bool live = j <= wmax && x < sigma && p[e] <= pmax;
+        int32_t cd = INF;
+        if (live) cd = (p[e] - s < W) ? tab[x * W + (p[e] - s)] : nm[(size_t)x * (n + 2) + p[e]];
+        const int32_t dn = umin(d[e], cd);
+        mk[e] = __ballot(live && cd == dn);
+        d[e] = (j <= wmax) ? dn : INF;
+    }
+}
+
+template <int E>
+__device__ void trace_leaf_tall(const uint8_t *__restrict__ arow, int32_t h, int32_t n,
+                                int32_t sigma, const int32_t *__restrict__ nm, int4 node,
+                                int32_t row0, int32_t *__restrict__ a_idx,
+                                int32_t *__restrict__ b_idx, int32_t wcap, int32_t *err,
+                                int32_t *tab, int32_t tabcap, unsigned long long *masks,
+                                int32_t *mrow, int32_t *xs) {
+    const int32_t INF = n + 1;
+    const int32_t s = umin(node.x, n);
+    const int lane = __lane_id();
+    const int32_t w0 = imin(imax(node.y, 0), h);
+    const int32_t off = imax(node.w, 0);
+    const int32_t eend = imin(imax(node.z, s), n + 1);
+    // Values above e = D_h(s, w0) are never on the path, and a value <= e never
+    // comes from one above e (next-match columns only grow), so lookups from
+    // columns past e are skipped: those entries become n + 1 and every entry
+    // <= e, and every match bit of a weight <= w0 at a column <= e, is unchanged.
+    const int32_t pmax = imin(eend, n);
+    const int32_t W = imin(imin(eend - s + 1, n + 2 - s), tabcap / imax(sigma, 1));
+    for (int32_t x = 0; x < sigma; ++x) {
+        const int32_t *src = nm + (size_t)x * (n + 2) + s;
+        int32_t *dst = tab + x * W;
+        for (int32_t c0 = 0; c0 < W; c0 += 8 * kWave) {
+            int32_t v[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) v[t] = src[imin(c0 + t * kWave + lane, W - 1)];
+#pragma unroll
+            for (int t = 0; t < 8; ++t)
+                if (c0 + t * kWave + lane < W) dst[c0 + t * kWave + lane] = v[t];
+        }
+    }
+    for (int32_t r = lane; r < E * kWave; r += kWave) {
+        xs[r] = (r < h) ? (int32_t)arow[r] : 0;
+        mrow[r] = 0;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    int32_t d[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) d[e] = INF;
+    for (int32_t r = 0; r < h; ++r) {
+        unsigned long long mk[E];
+        leaf_row<E>(d, xs[r], s, n, sigma, w0, pmax, tab, W, nm, mk);
+        if (lane == 0) {
+#pragma unroll
+            for (int e = 0; e < E; ++e) masks[r * E + e] = mk[e];
+        }
+    }
+    int32_t dend = s;
+    if (w0 >= 1) {
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+            if (e == ((w0 - 1) >> 6)) dend = __builtin_amdgcn_readlane(d[e], (w0 - 1) & (kWave - 1));
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    int32_t w = w0;
+    for (int32_t r = h; r >= 1 && w >= 1; --r) {
+        const unsigned long long mk = masks[(r - 1) * E + ((w - 1) >> 6)];
+        if ((mk >> ((w - 1) & (kWave - 1))) & 1ull) {
+            if (lane == 0) mrow[w - 1] = r;
+            --w;
+        }
+    }
+    if (lane == 0 && (w != 0 || dend != node.z)) atomicOr(err, kErrTrace);
+    if (w != 0 || w0 == 0) return;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    int32_t mr[E], cap[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int32_t j = e * kWave + lane + 1;
+        mr[e] = (j <= w0) ? mrow[j - 1] : 0;
+        cap[e] = INF;
+        d[e] = INF;
+    }
+    const int32_t rlast = mrow[w0 - 1];  // weights match in increasing rows
+    for (int32_t r = 0; r < rlast; ++r) {
+        unsigned long long mk[E];
+        leaf_row<E>(d, xs[r], s, n, sigma, w0, pmax, tab, W, nm, mk);
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+            if (mr[e] == r + 1) cap[e] = d[e];
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int32_t j = e * kWave + lane + 1;
+        if (j <= w0 && mr[e] >= 1 && off + j <= wcap) {
+            a_idx[off + j - 1] = row0 + mr[e] - 1;
+            b_idx[off + j - 1] = cap[e] - 1;
+        }
+    }
 }
 
 }  // namespace lcs

@@ -32,7 +32,7 @@ __global__ void __launch_bounds__(kBlock) k_base(const uint8_t *a, int32_t n, in
 
 // Seaweed combing of every base strip, one work-group (NT threads, fewer
 // for narrow strings) per strip; region comb holds comb_stride int32 per strip.
-template <int NT>
+template <int NT, int C>
 __global__ void __launch_bounds__(NT) k_comb(const uint8_t *a, const uint8_t *b, int32_t n,
                                              int32_t sigma, int32_t h0, int32_t nstrips,
                                              int32_t hlast, int32_t *comb, int32_t cstride,
@@ -41,7 +41,8 @@ __global__ void __launch_bounds__(NT) k_comb(const uint8_t *a, const uint8_t *b,
     const int32_t s = blockIdx.x;
     const int32_t h = (s == nstrips - 1) ? hlast : h0;
     int32_t *cs = comb + (size_t)s * (size_t)cstride;
-    comb_strip_block<NT>(a + (size_t)s * h0, h, b, n, sigma, cs, cs + n, cs + 2 * (size_t)n, lds, err);
+    comb_strip_block<NT, C>(a + (size_t)s * h0, h, b, n, sigma, cs, cs + n, cs + 2 * (size_t)n, lds,
+                            err);
 }
 
 // Breakout rows of every base strip from its combing: one wave per run of
@@ -278,6 +279,23 @@ __global__ void __launch_bounds__(kWave) k_trace_leaf(const uint8_t *a, int32_t 
                                wcap, err, lds, tab, kLeafTab);
 }
 
+// Base strips of 128 or 256 rows (E = 2, 4): one wave per strip.
+constexpr int32_t kLeafTabTall = 16384;
+template <int E>
+__global__ void __launch_bounds__(kWave) k_trace_leaf_tall(const uint8_t *a, int32_t n, int32_t sigma,
+                                                            const int32_t *nm, int32_t h0,
+                                                            int32_t nstrips, int32_t hlast,
+                                                            const int4 *nodes, int32_t *a_idx,
+                                                            int32_t *b_idx, int32_t wcap, int32_t *err) {
+    __shared__ int32_t tab[kLeafTabTall];
+    __shared__ unsigned long long masks[E * kWave * E];
+    __shared__ int32_t mrow[E * kWave], xs[E * kWave];
+    const int32_t s = blockIdx.x;
+    const int32_t h = (s == nstrips - 1) ? hlast : h0;
+    trace_leaf_tall<E>(a + (size_t)s * h0, h, n, sigma, nm, nodes[s], s * h0, a_idx, b_idx, wcap,
+                       err, tab, kLeafTabTall, masks, mrow, xs);
+}
+
 __global__ void __launch_bounds__(kBlock) k_semilocal(const int32_t *top, int32_t m, int32_t n,
                                                       const int32_t *qi, const int32_t *qk,
                                                       int32_t count, int32_t *out) {
@@ -361,10 +379,20 @@ hipError_t launch_base_comb(int32_t h0, const uint8_t *a, const uint8_t *b, int3
                             int32_t hlast, int32_t *comb, int32_t comb_stride, int32_t *err,
                             hipStream_t s) {
     if (h0 < 1 || h0 > kCombMaxRows) return hipErrorInvalidValue;
-    int32_t thr = (n + kCombCols - 1) / kCombCols;
+    // the fewest columns per thread that cover the string in one tile (a
+    // shorter dependent chain per row), at most 16 (then several tiles)
+    const int32_t C = (n <= 4 * kCombMaxThreads) ? 4 : (n <= 8 * kCombMaxThreads) ? 8 : 16;
+    int32_t thr = (n + C - 1) / C;
     thr = imin(kCombMaxThreads, imax(kWave, (thr + kWave - 1) / kWave * kWave));
-    hipLaunchKernelGGL((k_comb<kCombMaxThreads>), dim3(nstrips), dim3(thr), 0, s, a, b, n, sigma,
-                       h0, nstrips, hlast, comb, comb_stride, err);
+    if (C == 4)
+        hipLaunchKernelGGL((k_comb<kCombMaxThreads, 4>), dim3(nstrips), dim3(thr), 0, s, a, b, n, sigma,
+                           h0, nstrips, hlast, comb, comb_stride, err);
+    else if (C == 8)
+        hipLaunchKernelGGL((k_comb<kCombMaxThreads, 8>), dim3(nstrips), dim3(thr), 0, s, a, b, n, sigma,
+                           h0, nstrips, hlast, comb, comb_stride, err);
+    else
+        hipLaunchKernelGGL((k_comb<kCombMaxThreads, 16>), dim3(nstrips), dim3(thr), 0, s, a, b, n, sigma,
+                           h0, nstrips, hlast, comb, comb_stride, err);
     // runs short enough that the waves fill the chip, long enough to amortise
     // the scan for the first vertex of each run
     int32_t chunk = 256;
@@ -531,6 +559,14 @@ hipError_t launch_trace_leaf(int32_t h0, const uint8_t *a, int32_t n, int32_t si
         case 64:
             hipLaunchKernelGGL(k_trace_leaf<64>, dim3(nstrips), dim3(kWave), 0, s, a, n, sigma, nm,
                                nstrips, hlast, nodes, a_idx, b_idx, wcap, err);
+            break;
+        case 128:
+            hipLaunchKernelGGL(k_trace_leaf_tall<2>, dim3(nstrips), dim3(kWave), 0, s, a, n, sigma, nm,
+                               h0, nstrips, hlast, nodes, a_idx, b_idx, wcap, err);
+            break;
+        case 256:
+            hipLaunchKernelGGL(k_trace_leaf_tall<4>, dim3(nstrips), dim3(kWave), 0, s, a, n, sigma, nm,
+                               h0, nstrips, hlast, nodes, a_idx, b_idx, wcap, err);
             break;
         default:
             return hipErrorInvalidValue;

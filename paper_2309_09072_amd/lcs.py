@@ -86,6 +86,7 @@ PROTOTYPES = {
     "lcs_status_string": (ctypes.c_char_p, [_I32]),
     "lcs_plan": (_I32, [ctypes.POINTER(PlanDesc), ctypes.POINTER(_P), _PSZ]),
     "lcs_plan_workspace": (_I32, [_P, _I32, _I32, _PSZ]),
+    "lcs_plan_describe": (_I32, [_P, ctypes.POINTER(PlanDesc)]),
     "lcs_plan_destroy": (_I32, [_P]),
     "lcs_dist_build": (_I32, [_P, _P, _I32, _P, _I32, _P, _SZ, _P]),
     "lcs_dist_build_noalloc": (_I32, [_P, _P, _I32, _P, _I32, _P]),
@@ -198,6 +199,10 @@ class Plan:
         self._h = h
         self.workspace_bytes = int(ws.value)
         self._keep = None
+        res = PlanDesc()
+        check(lib.lcs_plan_describe(h, ctypes.byref(res)), "lcs_plan_describe")
+        self.base_rows = int(res.base_rows)  # as resolved by the library
+        self.tile = int(res.tile)
 
     def workspace_for(self, m: int, n: int) -> int:
         ws = ctypes.c_size_t()

@@ -1,7 +1,8 @@
 """Autotuner for the tile shapes of the strip recursion.
 
 Two shape parameters change the speed but never the result (every choice is
-exact): ``base_rows`` (rows per base strip, 16/32/64) and ``tile`` (vertices
+exact): ``base_rows`` (rows per base strip: 16 to 256 for single pairs, 16/32/64
+for batches) and ``tile`` (vertices
 between two anchor searches of a combine, a power of two 4..32).  The tuner
 times each candidate on the GPU through the C ABI (one pair: the whole build
 plus the witness trace; a batch: one submit of a sample of its pairs), keeps
@@ -18,16 +19,18 @@ import time
 from dataclasses import dataclass, field
 from typing import Callable, Dict, List, Optional, Sequence, Tuple
 
-BASE_ROWS = (16, 32, 64)
+BASE_ROWS = (16, 32, 64)                  # batches (row-append base strips)
+PAIR_BASE_ROWS = (16, 32, 64, 128, 256)   # single pairs (combed base strips)
 TILES = (8, 16, 32)
 DEFAULT = (64, 32)
 
 Config = Tuple[int, int]  # (base_rows, tile)
 
 
-def candidates(base_rows: Optional[int] = None, tiles: Sequence[int] = TILES) -> List[Config]:
-    """Candidate (base_rows, tile) pairs; base_rows fixed when given."""
-    hs = (int(base_rows),) if base_rows else BASE_ROWS
+def candidates(base_rows: Optional[int] = None, tiles: Sequence[int] = TILES,
+               rows: Sequence[int] = BASE_ROWS) -> List[Config]:
+    """Candidate (base_rows, tile) pairs; base_rows fixed when given, else from `rows`."""
+    hs = (int(base_rows),) if base_rows else tuple(rows)
     return [(h, int(t)) for h in hs for t in tiles]
 
 
@@ -127,7 +130,7 @@ def tune_pair(a, b, alphabet: int, base_rows: Optional[int] = None,
     trace, HIP events on the current stream); the mean step time decides.
     `timer` replaces the GPU timing (host tests of the selection logic)."""
     m, n = int(a.numel()), int(b.numel())
-    cands = candidates(base_rows, tiles)
+    cands = candidates(base_rows, tiles, PAIR_BASE_ROWS)
     if timer is None:
         timer = _pair_timer(a, b, alphabet, reps, cands)
         key = cache_key(device_name(), "pair", m, n, alphabet, base_rows)

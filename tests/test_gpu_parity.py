@@ -66,10 +66,13 @@ def check_against_oracle(a, b, sigma, **kw):
 # ----------------------------------------------------------------- small, full D
 
 
-@pytest.mark.parametrize("base_rows,tile", [(16, 4), (16, 8), (32, 16), (64, 32), (16, 32)])
+@pytest.mark.parametrize("base_rows,tile", [(16, 4), (16, 8), (32, 16), (64, 32), (16, 32), (128, 8),
+                                            (256, 32)])
 def test_levels_cell_for_cell(base_rows, tile):
     r = np.random.default_rng(100 + base_rows + tile)
     shapes = [(200, 150, 4), (129, 203, 2), (97, 64, 20), (65, 257, 4), (16, 31, 1), (250, 9, 3)]
+    if base_rows >= 128:  # several strips of the tall shapes, a short last one
+        shapes += [(700, 333, 4), (530, 260, 20), (257, 1100, 2)]
     for m, n, sig in shapes:
         a = r.integers(0, sig, m).astype(np.uint8)
         b = r.integers(0, sig, n).astype(np.uint8)
@@ -90,12 +93,14 @@ def _base_rows_check(a, b, plan, ws, verts):
 
 
 def test_base_table_window_and_fallback():
-    """Base strips of a small alphabet read a window of the next-match tables
-    from LDS; entries past the window are recomputed from the global tables.
-    Case 1: i.i.d. strings (every work-group exact from its window).  Case 2:
-    symbol 3 is absent from b's first 4000 columns, so strips holding it
-    reach past the window of every vertex block left of ~1950 and take the
-    fallback; blocks further right see the whole table."""
+    """Matches that jump far ahead.  Case 1: i.i.d. strings.  Case 2: symbol 3
+    is absent from b's first 4000 columns.  Single pairs (combed base
+    strips): for the vertices left of ~4000 the later breakouts of strips
+    holding symbol 3 lie thousands of columns away, so the row generation's
+    first-vertex scans run long.  Batches (row-append base strips): those
+    strips reach past the LDS window of the next-match tables for every
+    vertex block left of ~1950 and take the fallback to the global tables;
+    blocks further right see the whole table."""
     r = np.random.default_rng(4242)
     n = 5000
     verts = sorted(set(list(range(0, n + 1, 37)) + [1, 255, 256, 257, 1950, 2954, 2955, n - 1, n]))
@@ -103,10 +108,20 @@ def test_base_table_window_and_fallback():
     b1 = r.integers(0, 4, n).astype(np.uint8)
     b2 = np.concatenate([r.integers(0, 3, 4000), r.integers(0, 4, n - 4000)]).astype(np.uint8)
     for a, b in ((a1, b1), (a1, b2)):
-        for h0 in (16, 64):
+        for h0 in (16, 64, 256):
             say("base window", h0, int(b[:4000].max()))
             Lg, plan, ws = check_against_oracle(a, b, 4, base_rows=h0)
             _base_rows_check(a, b, plan, ws, verts)
+    batch = synth.batch_from_pairs([(a1, b1), (a1, b2)], 4, 4242, "window")
+    for h0 in (16, 64):
+        say("batch base window", h0)
+        lengths, ai, bi, off = L.run_batch(batch, L.BATCH_STAGED, h0, 32, 0)
+        for p in range(batch.count):
+            a, b = batch.pair(p)
+            Lo, ao, bo = oracle.lcs_witness(a, b)
+            assert lengths[p] == Lo, "pair %d: %d vs oracle %d" % (p, lengths[p], Lo)
+            assert np.array_equal(ai[off[p]:off[p] + Lo], ao), "pair %d a_idx" % p
+            assert np.array_equal(bi[off[p]:off[p] + Lo], bo), "pair %d b_idx" % p
 
 
 def test_base_strips_alphabet_20():
@@ -123,7 +138,7 @@ def test_base_strips_alphabet_20():
     p3 = synth.pair_mutated(192, 192, 20, 77, 0.10, 0.05, 0.05)
     b3 = np.concatenate([p3.b, r.integers(0, 20, n - p3.b.size)]).astype(np.uint8)
     for a, b in ((a1, b1), (a1, b2), (p3.a, b3)):
-        for h0 in (16, 32, 64):
+        for h0 in (16, 32, 64, 128, 256):
             say("alphabet 20 base", h0, b.size)
             Lg, plan, ws = check_against_oracle(a, b, 20, base_rows=h0)
             _base_rows_check(a, b, plan, ws, verts)
@@ -184,7 +199,7 @@ def test_random_shapes_length_and_witness():
         n = int(r.integers(0, 3000))
         if case % 5 == 0:
             m = int(r.integers(0, 70))
-        base_rows = int(r.choice([16, 32, 64]))
+        base_rows = int(r.choice([16, 32, 64, 128, 256]))
         tile = int(r.choice([4, 8, 16, 32]))
         a = r.integers(0, sig, m).astype(np.uint8)
         if case % 3 == 0 and m > 0:

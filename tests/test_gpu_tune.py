@@ -15,7 +15,7 @@ def test_tune_pair_exact_and_cached(tmp_path):
     b = synth.uniform(g, 1300, 4)
     ad, bd = lcs.device_bytes(a), lcs.device_bytes(b)
     r = tune.tune_pair(ad, bd, 4, reps=1, cache_path=path)
-    assert not r.cached and set(r.ms) == set(tune.candidates())
+    assert not r.cached and set(r.ms) == set(tune.candidates(rows=tune.PAIR_BASE_ROWS))
     assert all(t > 0 for t in r.ms.values())
     h, t = r.best
     length, ai, bi = lcs.lcs(a, b, 4, base_rows=h, tile=t)

@@ -18,11 +18,13 @@ def test_candidates():
     c = tune.candidates()
     assert len(c) == len(tune.BASE_ROWS) * len(tune.TILES) and tune.DEFAULT in c
     assert tune.candidates(64) == [(64, t) for t in tune.TILES]
+    cp = tune.candidates(rows=tune.PAIR_BASE_ROWS)
+    assert len(cp) == len(tune.PAIR_BASE_ROWS) * len(tune.TILES) and (256, 32) in cp
 
 
 def test_every_candidate_is_a_valid_plan():
     from paper_2309_09072_amd import lcs
-    for h, t in tune.candidates():
+    for h, t in tune.candidates(rows=tune.PAIR_BASE_ROWS):
         p = lcs.Plan(300, 500, 4, h, t)
         assert p.workspace_for(300, 500) > 0
         p.close()
@@ -49,7 +51,7 @@ def test_tune_with_fake_timer_and_cache(tmp_path):
     b = torch.zeros(2000, dtype=torch.uint8)
     r = tune.tune_pair(a, b, 4, timer=timer, cache_path=path)
     assert r.best == (32, 32) and not r.cached
-    assert sorted(calls) == sorted(tune.candidates())
+    assert sorted(calls) == sorted(tune.candidates(rows=tune.PAIR_BASE_ROWS))
     data = json.load(open(path))
     (key, entry), = data.items()
     assert key == "host|pair|m1024|n2048|s4|hany"
