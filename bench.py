@@ -182,7 +182,7 @@ def alg_bytes(m: int, n: int, h0: int) -> int:
 BATCH_MODES = ("staged_graph", "pair_queue_graph", "persistent_graph", "one_pair_per_launch")
 
 
-def bench_batched(reps: int, tune_shapes: bool = True, modes=BATCH_MODES):
+def bench_batched(reps: int, tune_shapes: bool = True, modes=BATCH_MODES, base_rows: int = 0):
     """Many pairs of uneven length: one launch per step across the pairs (staged),
     one persistent launch (pair queue, task queue), and one pair per launch."""
     import numpy as np
@@ -193,23 +193,31 @@ def bench_batched(reps: int, tune_shapes: bool = True, modes=BATCH_MODES):
     maxlen = int(max(batch.m.max(), batch.n.max()))
     slots = 512
     tuning = None
-    h0, tile = 64, 32
+    h0, tile = (base_rows or 64), 32
     if tune_shapes:  # the autotuner picks the shapes on a sample of the batch (staged mode)
         from paper_2309_09072_amd import tune
-        tr = tune.tune_batch(batch, lcs.BATCH_STAGED | lcs.BATCH_GRAPH, slots=slots, use_cache=False)
+        tr = tune.tune_batch(batch, lcs.BATCH_STAGED | lcs.BATCH_GRAPH, base_rows=base_rows or None,
+                             slots=slots, use_cache=False)
         h0, tile = tr.best
         tuning = tr.as_json()
         log("batch autotuner: base_rows %d tile %d (%s)" % (h0, tile, tuning["ms"]))
     plan = lcs.Batch(batch.count, maxlen, batch.sigma, h0, tile, slots=slots)
-    ws = lcs.alloc_workspace(plan.workspace_bytes)
+    # the persistent and pair-queue modes append rows: base strips of at most 64 rows
+    h0_rows = min(h0, 64)
+    plan_rows = plan if h0 <= 64 else lcs.Batch(batch.count, maxlen, batch.sigma, h0_rows, tile,
+                                                  slots=slots)
+    ws = lcs.alloc_workspace(max(plan.workspace_bytes, plan_rows.workspace_bytes))
     sym = lcs.device_bytes(batch.symbols)
     off = lcs.Batch.witness_offsets(batch.m, batch.n)
     lengths = torch.zeros(batch.count, dtype=torch.int32, device="cuda")
     ai = torch.zeros(int(off[-1]), dtype=torch.int32, device="cuda")
     bi = torch.zeros(int(off[-1]), dtype=torch.int32, device="cuda")
     nbytes = sum(alg_bytes(int(batch.m[p]), int(batch.n[p]), h0) for p in range(batch.count))
+    nbytes_rows = nbytes if h0 <= 64 else sum(alg_bytes(int(batch.m[p]), int(batch.n[p]), h0_rows)
+                                              for p in range(batch.count))
     out = {"workload": batch.name, "pairs": batch.count, "cells": batch.cells, "seed": batch.seed,
-           "slots": slots, "base_rows": h0, "tile": tile, "autotune": tuning,
+           "slots": slots, "base_rows": h0, "base_rows_persistent_modes": h0_rows, "tile": tile,
+           "autotune": tuning,
            "workspace_GB": round(ws.numel() / 1e9, 2), "alg_bytes_per_batch": nbytes}
     mode_of = {"staged_graph": lcs.BATCH_STAGED | lcs.BATCH_GRAPH,
                "staged": lcs.BATCH_STAGED,
@@ -218,7 +226,9 @@ def bench_batched(reps: int, tune_shapes: bool = True, modes=BATCH_MODES):
                "one_pair_per_launch": lcs.BATCH_PER_PAIR}
     for name in modes:
         mode = mode_of[name]
-        plan.submit(sym, batch.a_off, batch.b_off, batch.m, batch.n, ws, lengths, ai, bi, mode)
+        combed = bool(mode & (lcs.BATCH_STAGED | lcs.BATCH_PER_PAIR))
+        pl, nb = (plan, nbytes) if combed else (plan_rows, nbytes_rows)
+        pl.submit(sym, batch.a_off, batch.b_off, batch.m, batch.n, ws, lengths, ai, bi, mode)
         torch.cuda.synchronize()
         # poison the outputs, so that a mode which wrote nothing cannot pass on the
         # previous mode's results
@@ -228,32 +238,37 @@ def bench_batched(reps: int, tune_shapes: bool = True, modes=BATCH_MODES):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(reps):
-            plan.submit(sym, batch.a_off, batch.b_off, batch.m, batch.n, ws, lengths, ai, bi, mode)
+            pl.submit(sym, batch.a_off, batch.b_off, batch.m, batch.n, ws, lengths, ai, bi, mode)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / reps
         if not (mode & (lcs.BATCH_PER_PAIR | lcs.BATCH_STAGED | lcs.BATCH_PAIR_QUEUE)):
-            plan.status(ws)
+            pl.status(ws)
         L = lengths.cpu().numpy()
         A, B = ai.cpu().numpy(), bi.cpu().numpy()
         items = [(batch.pair(p)[0], batch.pair(p)[1], int(L[p]), A[off[p]:off[p] + max(L[p], 0)],
                   B[off[p]:off[p] + max(L[p], 0)]) for p in range(batch.count)]
         exact = oracle_check_many(items)
         out[name] = {"s_per_batch": round(dt, 4), "cells_per_s": batch.cells / dt,
-                     "alg_GBps": round(nbytes / dt / 1e9, 1), "exact_match": exact}
+                     "alg_GBps": round(nb / dt / 1e9, 1), "exact_match": exact,
+                     "base_rows": pl.desc.base_rows}
         log("batched %s: %.3f s per batch, %.3g cells/s, exact=%s" % (name, dt, batch.cells / dt, exact))
     one_launch = [k for k in out if k in ("staged_graph", "staged", "pair_queue_graph", "persistent_graph")]
     if one_launch:
         best = min(one_launch, key=lambda k: out[k]["s_per_batch"])
-        ach = nbytes / out[best]["s_per_batch"] / 1e9
+        nbest = nbytes if best.startswith("staged") else nbytes_rows
+        ach = nbest / out[best]["s_per_batch"] / 1e9
         out["roofline"] = {"kernel": "whole batch, %s (all step kernels)" % best, "bound": "hbm",
                            "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": round(ach / HBM_PEAK_GBS, 4),
                            "traffic": read_traffic(batch.name, "staged", batch_sources=True),
-                           "alg_bytes_per_batch": nbytes}
+                           "alg_bytes_per_batch": nbest}
         if "one_pair_per_launch" in out:
             for k in one_launch:
                 out["speedup_%s_vs_per_pair" % k.replace("_graph", "")] = round(
                     out["one_pair_per_launch"]["s_per_batch"] / out[k]["s_per_batch"], 2)
+    if plan_rows is not plan:
+        plan_rows.close()
+    plan.close()
     del ws
     torch.cuda.empty_cache()
     return out, batch
@@ -601,6 +616,9 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the 4096 x 4096 pair, the batched (4096 pairs), serving and "
                          "paper-shape workloads")
+    ap.add_argument("--batch-base-rows", type=int, default=0,
+                    help="rows per base strip of the batch; 0: the autotuner's choice "
+                         "(64 with --only-batched)")
     ap.add_argument("--only-batched", action="store_true",
                     help="run the batched workload alone (its own JSON line; for profiling)")
     ap.add_argument("--batch-reps", type=int, default=3)
@@ -640,7 +658,7 @@ def main():
 
     if args.only_batched:
         bres, _ = bench_batched(args.batch_reps, tune_shapes=False,
-                                modes=tuple(args.batch_modes.split(",")))
+                                modes=tuple(args.batch_modes.split(",")), base_rows=args.batch_base_rows)
         calib()
         print(json.dumps({"metric": "batched LCS cells/s", "batched": bres}), flush=True)
         return

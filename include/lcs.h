@@ -12,8 +12,10 @@
  * where the symbols match (Section II-A, Fig. 1).  For a horizontal strip of
  * rows, the breakout matrix D(i, j) holds the leftmost bottom-row column that a
  * path of weight j can reach from top-row column i (Section II-B-1).  Strips of
- * base_rows rows are built from per-symbol next-match tables (the base case of
- * Section II-B-3), adjacent strips are merged with the combine equation of
+ * base_rows rows are built by appending rows with per-symbol next-match tables
+ * (the base case of Section II-B-3) or, with identical results, from a combed
+ * seaweed permutation of the strip (single pairs and staged batches); adjacent
+ * strips are merged with the combine equation of
  * Section II-B-1 up to the whole grid, the length is read off the top matrix,
  * and the witness comes from the cross vertices found by a recursive midpoint
  * search (Sections II-C to II-E).
@@ -115,8 +117,10 @@ int32_t lcs_plan_destroy(lcs_plan_t plan);
 
 /*
  * Build every breakout matrix of the strip recursion for the pair (a, b):
- * the per-symbol next-match tables (Section II-B-3 base case), the base strips
- * of base_rows rows, then the combine equation of Section II-B-1 level by
+ * the per-symbol next-match tables (Section II-B-3 base case; the trace reads
+ * them), the base strips of base_rows rows (from each strip's seaweed
+ * combing: the breakout rows that appending the rows one at a time with those
+ * tables gives), then the combine equation of Section II-B-1 level by
  * level up to the whole grid, whose argmin search follows the monotone-matrix
  * property of Section II-B-1 (Alg. 1 and Alg. 2 for every tile-th vertex,
  * bracketed searches in between), and finally the LCS length.
@@ -294,7 +298,9 @@ typedef struct lcs_batch_desc {
     int32_t max_pairs; /* most pairs per submit */
     int32_t max_len;   /* largest m and largest n of any pair */
     int32_t alphabet;  /* 1..256 */
-    int32_t base_rows; /* as in lcs_plan_desc */
+    int32_t base_rows; /* 16, 32 or 64 (0 selects 64); 128 or 256 with
+                          LCS_BATCH_STAGED or LCS_BATCH_PER_PAIR only
+                          (lcs_batch_submit returns LCS_E_INVAL otherwise) */
     int32_t tile;      /* as in lcs_plan_desc */
     int32_t slots;     /* pairs whose matrices may be resident at once (0 = all);
                           pair p reuses slot p mod slots after pair p - slots
@@ -361,7 +367,7 @@ typedef struct lcs_server_s *lcs_server_t;
 typedef struct lcs_server_desc {
     int32_t max_len;   /* largest m and n of a request */
     int32_t alphabet;  /* largest alphabet of a request, 1..256 */
-    int32_t base_rows; /* as in lcs_plan_desc */
+    int32_t base_rows; /* 16, 32 or 64; 0 selects 64 */
     int32_t tile;      /* as in lcs_plan_desc */
     int32_t slots;     /* requests that may run on the device at once (1..64) */
     int32_t max_queue; /* waiting requests held on the host */

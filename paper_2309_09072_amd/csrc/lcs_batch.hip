@@ -69,6 +69,7 @@ struct BatchArgs {
     const Seg *segs;     // persistent mode: the global task order
     int64_t nseg;
     int32_t base_mode;   // table form of the base-strip tasks (kBase*Mode)
+    int32_t base_rows;   // rows per base strip
 };
 
 constexpr uint32_t kSpinLimit = 1u << 22;  // ~ seconds: a dependency bug ends as an error, not a hang
@@ -369,6 +370,7 @@ __global__ void __launch_bounds__(kBlock) k_pair_queue(BatchArgs A, const int32_
 struct StageArgs {
     int32_t kind, level, npairs;
     int32_t jchunk;         // weights per bracket task (the bracket shape's kJ)
+    int32_t cols;           // longest column string of the plan
     const int32_t *pair;    // participating pairs
     const int64_t *first;   // their first item, plus the total at [npairs]
 };
@@ -492,6 +494,69 @@ __global__ void __launch_bounds__(kBlock) k_stage_anchor_wave(BatchArgs A, Stage
     }
 }
 
+// Staged seaweed combing: one work-group per (pair, base strip), blockDim set
+// by the plan's longest string (C columns per thread, as in the single-pair
+// path).
+template <int C>
+__global__ void __launch_bounds__(kCombMaxThreads) k_stage_comb(BatchArgs A, StageArgs S) {
+    __shared__ int32_t lds[3 * kCombMaxRows + 4 * (kCombMaxThreads / kWave)];
+    const int2 pu = stage_item(S, blockIdx.x);
+    const PairRec &P = A.pairs[pu.x];
+    uint8_t *ws = A.ws + P.ws_off;
+    const LevelGeom &g = P.lev[0];
+    const int32_t s = pu.y;
+    const int32_t h = (s == g.nstrips - 1) ? g.hlast : P.h0;
+    int32_t *cs = reinterpret_cast<int32_t *>(ws + P.off_comb) + (size_t)s * (size_t)P.comb_stride;
+    comb_strip_block<kCombMaxThreads, C>(A.symbols + P.a_off + (size_t)s * P.h0, h, A.symbols + P.b_off,
+                                         P.n, A.sigma, cs, cs + P.n, cs + 2 * (size_t)P.n, lds,
+                                         reinterpret_cast<int32_t *>(ws + P.off_hdr));
+}
+
+// Staged breakout-row generation: one wave per (pair, strip, run of
+// kStageRun vertices), four per work-group (runs of one strip on one XCD).
+constexpr int32_t kStageRun = 64;
+template <int E>
+__global__ void __launch_bounds__(kBlock) k_stage_dgen(BatchArgs A, StageArgs S, int64_t items) {
+    __shared__ int32_t lst[kWaves][E * kWave];
+    const int32_t wv = uniform((int32_t)threadIdx.x / kWave);
+    const int64_t t = (int64_t)xcd_block((int32_t)blockIdx.x, (int32_t)gridDim.x,
+                                         imax(1, (int32_t)gridDim.x / 8)) * kWaves + wv;
+    if (t >= items) return;
+    const int2 pu = stage_item(S, t);
+    const PairRec &P = A.pairs[pu.x];
+    uint8_t *ws = A.ws + P.ws_off;
+    const LevelGeom &g = P.lev[0];
+    const int32_t nrun = (P.n + 2 + kStageRun - 1) / kStageRun;
+    const int32_t s = pu.y / nrun, ck = pu.y - s * nrun;
+    const bool last = (s == g.nstrips - 1);
+    const int32_t h = last ? g.hlast : P.h0;
+    int32_t *out = reinterpret_cast<int32_t *>(ws + (last ? g.last_off : g.base)) +
+                   (last ? 0 : (size_t)s * strip_elems(P.n, P.h0));
+    const int32_t *cs = reinterpret_cast<const int32_t *>(ws + P.off_comb) + (size_t)s * (size_t)P.comb_stride;
+    const int32_t i0 = ck * kStageRun;
+    dgen_wave<E>(cs, cs + P.n, cs + 2 * (size_t)P.n, h, P.n, i0, imin(i0 + kStageRun, P.n + 2), out,
+                 lst[wv]);
+}
+
+// Staged trace inside base strips of 128 or 256 rows: one wave per strip.
+template <int E>
+__global__ void __launch_bounds__(kWave) k_stage_leaf_tall(BatchArgs A, StageArgs S) {
+    __shared__ int32_t tab[kLeafTabTall];
+    __shared__ unsigned long long masks[E * kWave * E];
+    __shared__ int32_t mrow[E * kWave], xs[E * kWave];
+    const int2 pu = stage_item(S, blockIdx.x);
+    const PairRec &P = A.pairs[pu.x];
+    uint8_t *ws = A.ws + P.ws_off;
+    const LevelGeom &g = P.lev[0];
+    const int32_t u = pu.y;
+    const int32_t h = (u == g.nstrips - 1) ? g.hlast : P.h0;
+    const int4 *nodes = reinterpret_cast<const int4 *>(ws + P.node_off[0]);
+    trace_leaf_tall<E>(A.symbols + P.a_off + (size_t)u * P.h0, h, P.n, A.sigma,
+                       reinterpret_cast<const int32_t *>(ws + P.off_nm), nodes[u], u * P.h0,
+                       A.a_idx + P.wit_off, A.b_idx + P.wit_off, P.m < P.n ? P.m : P.n,
+                       reinterpret_cast<int32_t *>(ws + P.off_hdr), tab, kLeafTabTall, masks, mrow, xs);
+}
+
 // dynamic LDS a staged anchor search may take: what one work-group of gfx950
 // can hold (160 KB) minus room for the kernel's static LDS
 constexpr size_t kStageMaxLds = 159 * 1024;
@@ -517,7 +582,7 @@ static hipError_t opt_in_stage_lds() {
 template <int H0>
 static hipError_t launch_stage(const BatchArgs &A, const StageArgs &S, dim3 grid, hipStream_t st) {
     if (S.kind == ST_ANCHOR && S.level >= 1 && S.level < kMaxLev) {
-        const int32_t hc = H0 << (S.level - 1);
+        const int32_t hc = A.base_rows << (S.level - 1);
         const int32_t hs = 2 * hc + 1;
         if (hs <= 512) {  // short rows: one search per wave
             const int32_t per_wave = (int32_t)(((hs <= 256 ? sizeof(AnchorSmem<kWave, 4>)
@@ -555,9 +620,9 @@ static hipError_t launch_stage(const BatchArgs &A, const StageArgs &S, dim3 grid
         case ST_ANCHOR: hipLaunchKernelGGL((k_stage<H0, ST_ANCHOR>), grid, dim3(kBlock), 0, st, A, S); break;
         case ST_BRACKET_CH:
             // the single-pair path's shape for the level's child strip height
-            if (S.jchunk == BracketCfg16::kJ && S.level >= 1 && (H0 << (S.level - 1)) >= kWideWindowMinH)
+            if (S.jchunk == BracketCfg16::kJ && S.level >= 1 && (A.base_rows << (S.level - 1)) >= kWideWindowMinH)
                 hipLaunchKernelGGL((k_stage_bracket<H0, BracketCfg16Wide, true>), grid, dim3(kBlock), 0, st, A, S);
-            else if (S.jchunk == BracketCfg16::kJ && S.level >= 1 && (H0 << (S.level - 1)) >= kCoopPass2MinH)
+            else if (S.jchunk == BracketCfg16::kJ && S.level >= 1 && (A.base_rows << (S.level - 1)) >= kCoopPass2MinH)
                 hipLaunchKernelGGL((k_stage_bracket<H0, BracketCfg16Mid, true>), grid, dim3(kBlock), 0, st, A, S);
             else if (S.jchunk == BracketCfg16::kJ)
                 hipLaunchKernelGGL((k_stage_bracket<H0, BracketCfg16>), grid, dim3(kBlock), 0, st, A, S);
@@ -567,6 +632,35 @@ static hipError_t launch_stage(const BatchArgs &A, const StageArgs &S, dim3 grid
         case ST_LENGTH: hipLaunchKernelGGL((k_stage<H0, ST_LENGTH>), grid, dim3(kBlock), 0, st, A, S); break;
         case ST_SPLIT: hipLaunchKernelGGL((k_stage<H0, ST_SPLIT>), grid, dim3(kBlock), 0, st, A, S); break;
         case ST_LEAF: hipLaunchKernelGGL((k_stage<H0, ST_LEAF>), grid, dim3(kBlock), 0, st, A, S); break;
+        case ST_COMB: {
+            const int32_t C = (S.cols <= 4 * kCombMaxThreads) ? 4 : (S.cols <= 8 * kCombMaxThreads) ? 8 : 16;
+            int32_t thr = (S.cols + C - 1) / C;
+            thr = imin(kCombMaxThreads, imax(kWave, (thr + kWave - 1) / kWave * kWave));
+            if (C == 4)
+                hipLaunchKernelGGL((k_stage_comb<4>), grid, dim3(thr), 0, st, A, S);
+            else if (C == 8)
+                hipLaunchKernelGGL((k_stage_comb<8>), grid, dim3(thr), 0, st, A, S);
+            else
+                hipLaunchKernelGGL((k_stage_comb<16>), grid, dim3(thr), 0, st, A, S);
+            break;
+        }
+        case ST_DGEN: {
+            const int64_t items = grid.x;
+            const dim3 g((unsigned)((items + kWaves - 1) / kWaves));
+            if (A.base_rows <= kWave)
+                hipLaunchKernelGGL((k_stage_dgen<1>), g, dim3(kBlock), 0, st, A, S, items);
+            else if (A.base_rows <= 2 * kWave)
+                hipLaunchKernelGGL((k_stage_dgen<2>), g, dim3(kBlock), 0, st, A, S, items);
+            else
+                hipLaunchKernelGGL((k_stage_dgen<4>), g, dim3(kBlock), 0, st, A, S, items);
+            break;
+        }
+        case ST_LEAF_TALL:
+            if (A.base_rows <= 2 * kWave)
+                hipLaunchKernelGGL((k_stage_leaf_tall<2>), grid, dim3(kWave), 0, st, A, S);
+            else
+                hipLaunchKernelGGL((k_stage_leaf_tall<4>), grid, dim3(kWave), 0, st, A, S);
+            break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -629,7 +723,9 @@ static int32_t plan_sizes(const lcs_batch_desc *desc, lcs_batch_s *b) {
     if (d.max_pairs < 1 || d.max_len < 1 || d.alphabet < 1 || d.alphabet > 256 || d.flags != 0 ||
         d.slots < 0)
         return LCS_E_INVAL;
-    if (!valid_shape(d.base_rows, d.tile)) return LCS_E_INVAL;
+    // 128- and 256-row base strips: staged and per-pair modes only (checked at submit)
+    const bool tall = d.base_rows == 128 || d.base_rows == 256;
+    if (!valid_shape(tall ? 64 : d.base_rows, d.tile)) return LCS_E_INVAL;
     if (d.slots == 0 || d.slots > d.max_pairs) d.slots = d.max_pairs;
     Layout L;
     if (!make_layout(d.max_len, d.max_len, d.alphabet, d.base_rows, d.tile, L)) return LCS_E_TOO_BIG;
@@ -762,6 +858,9 @@ static bool make_pair(const lcs_batch_s *B, const lcs_pair_desc &pd, int32_t p, 
     R.sigma = B->d.alphabet;
     R.nvb = vertex_blocks_of(pd.n, kBlock);
     R.jchunk = stage_jchunk(B->d.max_len);
+    R.h0 = B->d.base_rows;
+    R.comb_stride = L.comb_stride;
+    R.off_comb = L.off_comb;
     int32_t c = kCtrHead;
     for (int32_t l = 0; l < R.nlev; ++l) {
         R.lev[l] = L.lev[l];
@@ -853,6 +952,8 @@ extern "C" int32_t lcs_batch_submit(lcs_batch_t B, const lcs_pair_desc *pairs, i
             (kinds & (kinds - 1)) != 0)  // at most one of them
             return LCS_E_INVAL;
     }
+    // the persistent and pair-queue kernels append rows: base strips of at most 64 rows
+    if (B->d.base_rows > kWave && !(mode & (LCS_BATCH_STAGED | LCS_BATCH_PER_PAIR))) return LCS_E_INVAL;
     if ((size_t)B->total > workspace_bytes) return LCS_E_WORKSPACE;
     if (reinterpret_cast<uintptr_t>(workspace) & 255) return LCS_E_INVAL;
     int64_t wit = 0;
@@ -964,8 +1065,11 @@ extern "C" int32_t lcs_batch_submit(lcs_batch_t B, const lcs_pair_desc *pairs, i
             const int32_t sjc = stage_jchunk(B->d.max_len);
             add_stage(ST_EMPTY, 0, [](const PairRec &R) -> int64_t { return R.nlev == 0 ? 1 : 0; });
             add_stage(ST_NM_SYM, 0, [sig](const PairRec &R) -> int64_t { return R.nlev ? sig : 0; });
-            add_stage(ST_BASE_BLK, 0, [](const PairRec &R) -> int64_t {
-                return R.nlev ? (int64_t)R.lev[0].nstrips * ((R.n + 2 + kBlock - 1) / kBlock) : 0;
+            // base strips by combing: one work-group per strip, one wave per
+            // run of kStageRun vertices
+            add_stage(ST_COMB, 0, [](const PairRec &R) -> int64_t { return R.nlev ? R.lev[0].nstrips : 0; });
+            add_stage(ST_DGEN, 0, [](const PairRec &R) -> int64_t {
+                return R.nlev ? (int64_t)R.lev[0].nstrips * ((R.n + 2 + kStageRun - 1) / kStageRun) : 0;
             });
             for (int32_t l = 1; l <= lmax; ++l) {
                 add_stage(ST_ANCHOR, l, [l](const PairRec &R) -> int64_t {
@@ -983,7 +1087,8 @@ extern "C" int32_t lcs_batch_submit(lcs_batch_t B, const lcs_pair_desc *pairs, i
                 add_stage(ST_SPLIT, l, [l](const PairRec &R) -> int64_t {
                     return R.nlev > l ? R.lev[l].nstrips : 0;
                 });
-            add_stage(ST_LEAF, 0, [](const PairRec &R) -> int64_t { return R.nlev ? R.lev[0].nstrips : 0; });
+            add_stage(B->d.base_rows > kWave ? ST_LEAF_TALL : ST_LEAF, 0,
+                      [](const PairRec &R) -> int64_t { return R.nlev ? R.lev[0].nstrips : 0; });
         }
         if (soff > B->stage_bytes) return LCS_E_TOO_BIG;
     }
@@ -1013,6 +1118,7 @@ extern "C" int32_t lcs_batch_submit(lcs_batch_t B, const lcs_pair_desc *pairs, i
     A.tile = B->d.tile;
     A.segs = reinterpret_cast<const Seg *>(ws + B->off_stage);
     A.nseg = nseg;
+    A.base_rows = B->d.base_rows;
     switch (B->d.base_rows) {
         case 16: A.base_mode = base_tab_mode<16>(B->d.max_len, B->d.alphabet); break;
         case 32: A.base_mode = base_tab_mode<32>(B->d.max_len, B->d.alphabet); break;
@@ -1038,6 +1144,7 @@ extern "C" int32_t lcs_batch_submit(lcs_batch_t B, const lcs_pair_desc *pairs, i
                 S.level = sl.level;
                 S.npairs = sl.npairs;
                 S.jchunk = stage_jchunk(B->d.max_len);
+                S.cols = B->d.max_len;
                 S.pair = reinterpret_cast<const int32_t *>(ws + B->off_stage + sl.pair_off);
                 S.first = reinterpret_cast<const int64_t *>(ws + B->off_stage + sl.first_off);
                 if (sl.items >= (int64_t)1 << 31) return LCS_E_TOO_BIG;
@@ -1158,6 +1265,7 @@ extern "C" int32_t lcs_batch_status(lcs_batch_t B, void *workspace, void *stream
 extern "C" int32_t lcs_batch_selftest(const lcs_batch_desc *desc, const lcs_pair_desc *pairs,
                                       int32_t count) {
     if (!desc || (count > 0 && !pairs) || count < 0) return LCS_E_INVAL;
+    if (desc->base_rows > kWave) return LCS_E_INVAL;  // the persistent schedule appends rows (<= 64)
     lcs_batch_s b;
     const int32_t rc = plan_sizes(desc, &b);
     if (rc != LCS_OK) return rc;

@@ -1839,6 +1839,7 @@ __device__ __forceinline__ void leaf_row(int32_t (&d)[E], int32_t x, int32_t s, 
     }
 }
 
+constexpr int32_t kLeafTabTall = 16384;  // next-match entries a tall leaf keeps in LDS
 template <int E>
 __device__ void trace_leaf_tall(const uint8_t *__restrict__ arow, int32_t h, int32_t n,
                                 int32_t sigma, const int32_t *__restrict__ nm, int4 node,

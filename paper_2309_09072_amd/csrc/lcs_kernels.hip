@@ -280,7 +280,6 @@ __global__ void __launch_bounds__(kWave) k_trace_leaf(const uint8_t *a, int32_t 
 }
 
 // Base strips of 128 or 256 rows (E = 2, 4): one wave per strip.
-constexpr int32_t kLeafTabTall = 16384;
 template <int E>
 __global__ void __launch_bounds__(kWave) k_trace_leaf_tall(const uint8_t *a, int32_t n, int32_t sigma,
                                                             const int32_t *nm, int32_t h0,

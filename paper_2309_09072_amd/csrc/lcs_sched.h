@@ -34,6 +34,10 @@ enum Stage : int32_t {
     ST_NM_SYM = 16,      // next-match table of one symbol (u = symbol)
     ST_BASE_BLK = 17,    // u = strip * vertex_blocks + block
     ST_BRACKET_CH = 18,  // u = (q * tiles + tile) * chunks + chunk
+    // staged mode only (the persistent schedule never lists them):
+    ST_COMB = 19,        // seaweed combing of one base strip (u = strip)
+    ST_DGEN = 20,        // breakout rows of one run of vertices of one strip
+    ST_LEAF_TALL = 21,   // trace inside one base strip of 128 or 256 rows
 };
 
 struct PairRec {
@@ -54,6 +58,9 @@ struct PairRec {
     int32_t sigma;   // next-match tasks (one per symbol)
     int32_t nvb;     // 256-vertex blocks of a base strip
     int32_t jchunk;  // weights per bracket task
+    int32_t h0;      // rows per base strip
+    int32_t comb_stride;  // int32 per base strip in the combing region
+    int64_t off_comb;     // the combing region (bot, pos, right per strip)
 };
 
 // One stage of one pair in the global order, cut into chunks of at most

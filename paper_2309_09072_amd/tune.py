@@ -19,8 +19,8 @@ import time
 from dataclasses import dataclass, field
 from typing import Callable, Dict, List, Optional, Sequence, Tuple
 
-BASE_ROWS = (16, 32, 64)                  # batches (row-append base strips)
-PAIR_BASE_ROWS = (16, 32, 64, 128, 256)   # single pairs (combed base strips)
+BASE_ROWS = (16, 32, 64)                  # persistent batches (row-append base strips)
+PAIR_BASE_ROWS = (16, 32, 64, 128, 256)   # single pairs, staged batches (combed base strips)
 TILES = (8, 16, 32)
 DEFAULT = (64, 32)
 
@@ -183,7 +183,12 @@ def tune_batch(batch, mode: int, base_rows: Optional[int] = None, tiles: Sequenc
     """Best (base_rows, tile) for a synth.Batch run in `mode`, timed on its
     first `sample` pairs (wall time of one submit, after a warm-up)."""
     import numpy as np
-    cands = candidates(base_rows, tiles)
+
+    from . import lcs
+    # the staged and per-pair modes comb their base strips (up to 256 rows);
+    # the persistent ones append rows (up to 64)
+    rows = PAIR_BASE_ROWS if mode & (lcs.BATCH_STAGED | lcs.BATCH_PER_PAIR) else BASE_ROWS
+    cands = candidates(base_rows, tiles, rows)
     k = min(int(sample), batch.count)
     mm = int(np.median(batch.m[:k])) if k else 0
     nn = int(np.median(batch.n[:k])) if k else 0

@@ -51,13 +51,25 @@ def test_persistent_matches_oracle(base_rows, tile, slots):
     check(batch, *res)
 
 
-@pytest.mark.parametrize("base_rows,tile,slots", [(16, 8, 2), (32, 32, 0), (64, 16, 1)])
+@pytest.mark.parametrize("base_rows,tile,slots", [(16, 8, 2), (32, 32, 0), (64, 16, 1), (128, 16, 3),
+                                                  (256, 32, 0)])
 def test_staged_matches_oracle(base_rows, tile, slots):
-    """Staged launches; small slot areas force the pairs into several waves."""
-    batch = mixed_small(60, 50 + base_rows)
+    """Staged launches; small slot areas force the pairs into several waves.
+    Base strips of 128 and 256 rows (staged mode only) get pairs long enough
+    for several strips and combine levels."""
+    batch = mixed_small(60, 50 + base_rows, maxlen=300 if base_rows <= 64 else 1100)
     say("staged", base_rows, tile, slots)
     res = L.run_batch(batch, L.BATCH_STAGED, base_rows, tile, slots)
     check(batch, *res)
+
+
+def test_tall_base_strips_staged_or_per_pair_only():
+    batch = mixed_small(4, 7)
+    for mode in (L.BATCH_PERSISTENT, L.BATCH_PAIR_QUEUE):
+        with pytest.raises(L.LcsError) as e:
+            L.run_batch(batch, mode, 128, 32, 0)
+        assert e.value.status == -1
+    check(batch, *L.run_batch(batch, L.BATCH_PER_PAIR, 256, 32, 0))
 
 
 @pytest.mark.parametrize("base_rows,tile,slots", [(16, 8, 3), (32, 32, 0), (64, 16, 1)])
