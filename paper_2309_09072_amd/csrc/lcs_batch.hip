@@ -538,7 +538,7 @@ __global__ void __launch_bounds__(kBlock) k_stage_dgen(BatchArgs A, StageArgs S,
                  lst[wv]);
 }
 
-// Staged trace inside base strips of 128 or 256 rows: one wave per strip.
+// Staged trace inside base strips of 128 to 512 rows: one wave per strip.
 template <int E>
 __global__ void __launch_bounds__(kWave) k_stage_leaf_tall(BatchArgs A, StageArgs S) {
     __shared__ int32_t tab[kLeafTabTall];
@@ -651,15 +651,19 @@ static hipError_t launch_stage(const BatchArgs &A, const StageArgs &S, dim3 grid
                 hipLaunchKernelGGL((k_stage_dgen<1>), g, dim3(kBlock), 0, st, A, S, items);
             else if (A.base_rows <= 2 * kWave)
                 hipLaunchKernelGGL((k_stage_dgen<2>), g, dim3(kBlock), 0, st, A, S, items);
-            else
+            else if (A.base_rows <= 4 * kWave)
                 hipLaunchKernelGGL((k_stage_dgen<4>), g, dim3(kBlock), 0, st, A, S, items);
+            else
+                hipLaunchKernelGGL((k_stage_dgen<8>), g, dim3(kBlock), 0, st, A, S, items);
             break;
         }
         case ST_LEAF_TALL:
             if (A.base_rows <= 2 * kWave)
                 hipLaunchKernelGGL((k_stage_leaf_tall<2>), grid, dim3(kWave), 0, st, A, S);
-            else
+            else if (A.base_rows <= 4 * kWave)
                 hipLaunchKernelGGL((k_stage_leaf_tall<4>), grid, dim3(kWave), 0, st, A, S);
+            else
+                hipLaunchKernelGGL((k_stage_leaf_tall<8>), grid, dim3(kWave), 0, st, A, S);
             break;
         default: return hipErrorInvalidValue;
     }
@@ -723,8 +727,8 @@ static int32_t plan_sizes(const lcs_batch_desc *desc, lcs_batch_s *b) {
     if (d.max_pairs < 1 || d.max_len < 1 || d.alphabet < 1 || d.alphabet > 256 || d.flags != 0 ||
         d.slots < 0)
         return LCS_E_INVAL;
-    // 128- and 256-row base strips: staged and per-pair modes only (checked at submit)
-    const bool tall = d.base_rows == 128 || d.base_rows == 256;
+    // 128- to 512-row base strips: staged and per-pair modes only (checked at submit)
+    const bool tall = d.base_rows == 128 || d.base_rows == 256 || d.base_rows == 512;
     if (!valid_shape(tall ? 64 : d.base_rows, d.tile)) return LCS_E_INVAL;
     if (d.slots == 0 || d.slots > d.max_pairs) d.slots = d.max_pairs;
     Layout L;

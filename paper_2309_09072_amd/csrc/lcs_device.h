@@ -292,7 +292,7 @@ __device__ void base_strip_block(const uint8_t *__restrict__ arow, int32_t h, in
 // labels leaving a tile on the right entering the next.  Writes bot[0..n),
 // pos[0..n) (n + 1 for a seaweed that leaves on the right) and right[0..h).
 constexpr int32_t kCombMaxThreads = 1024;
-constexpr int32_t kCombMaxRows = 256;
+constexpr int32_t kCombMaxRows = 512;
 
 // (c, v) stands for x -> c ? v : min(x, v); b := b after a
 __device__ __forceinline__ void comb_fn_after(int32_t ac, int32_t av, int32_t &bc, int32_t &bv) {
@@ -1801,7 +1801,7 @@ __device__ void trace_leaf_block(const uint8_t *__restrict__ arow, int32_t h, in
 }
 
 // ---------------------------------------------------------------------------
-// Midpoint trace inside a base strip of up to 64 E rows (E = 2 or 4), by one
+// Midpoint trace inside a base strip of up to 64 E rows (E = 2, 4 or 8), by one
 // wave: the row appends of the one-wave form above with E columns per lane
 // (column j = 64 e + lane + 1 in register e), restricted to the weights
 // 1..w0 of the node.  Column j of D_{r+1}(s, .) depends only on columns j - 1

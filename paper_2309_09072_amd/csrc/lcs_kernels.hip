@@ -279,7 +279,7 @@ __global__ void __launch_bounds__(kWave) k_trace_leaf(const uint8_t *a, int32_t 
                                wcap, err, lds, tab, kLeafTab);
 }
 
-// Base strips of 128 or 256 rows (E = 2, 4): one wave per strip.
+// Base strips of 128 to 512 rows (E = 2, 4, 8): one wave per strip.
 template <int E>
 __global__ void __launch_bounds__(kWave) k_trace_leaf_tall(const uint8_t *a, int32_t n, int32_t sigma,
                                                             const int32_t *nm, int32_t h0,
@@ -405,8 +405,11 @@ hipError_t launch_base_comb(int32_t h0, const uint8_t *a, const uint8_t *b, int3
     else if (h0 <= 2 * kWave)
         hipLaunchKernelGGL((k_dgen<2>), grid, dim3(kBlock), 0, s, comb, comb_stride, n, h0, nstrips,
                            hlast, base0, last, chunk, nchunks);
-    else
+    else if (h0 <= 4 * kWave)
         hipLaunchKernelGGL((k_dgen<4>), grid, dim3(kBlock), 0, s, comb, comb_stride, n, h0, nstrips,
+                           hlast, base0, last, chunk, nchunks);
+    else
+        hipLaunchKernelGGL((k_dgen<8>), grid, dim3(kBlock), 0, s, comb, comb_stride, n, h0, nstrips,
                            hlast, base0, last, chunk, nchunks);
     return hipGetLastError();
 }
@@ -565,6 +568,10 @@ hipError_t launch_trace_leaf(int32_t h0, const uint8_t *a, int32_t n, int32_t si
             break;
         case 256:
             hipLaunchKernelGGL(k_trace_leaf_tall<4>, dim3(nstrips), dim3(kWave), 0, s, a, n, sigma, nm,
+                               h0, nstrips, hlast, nodes, a_idx, b_idx, wcap, err);
+            break;
+        case 512:
+            hipLaunchKernelGGL(k_trace_leaf_tall<8>, dim3(nstrips), dim3(kWave), 0, s, a, n, sigma, nm,
                                h0, nstrips, hlast, nodes, a_idx, b_idx, wcap, err);
             break;
         default:

@@ -37,7 +37,7 @@ enum Stage : int32_t {
     // staged mode only (the persistent schedule never lists them):
     ST_COMB = 19,        // seaweed combing of one base strip (u = strip)
     ST_DGEN = 20,        // breakout rows of one run of vertices of one strip
-    ST_LEAF_TALL = 21,   // trace inside one base strip of 128 or 256 rows
+    ST_LEAF_TALL = 21,   // trace inside one base strip of 128 to 512 rows
 };
 
 struct PairRec {

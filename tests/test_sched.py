@@ -42,7 +42,7 @@ def test_mixed_workload_shapes():
 def test_rejects_bad_descriptors():
     assert L.batch_selftest([10], [10], 0) == -1
     assert L.batch_selftest([10], [10], 4, 48) == -1
-    # 128- and 256-row base strips are for single pairs only
+    # base strips of more than 64 rows are for the combing modes only
     assert L.batch_selftest([10], [10], 4, 128) == -1
     assert L.batch_selftest([10], [10], 4, 256) == -1
     assert L.batch_selftest([100], [10], 4, max_len=50) == -2
