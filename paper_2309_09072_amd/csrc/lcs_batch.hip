@@ -538,12 +538,14 @@ __global__ void __launch_bounds__(kBlock) k_stage_dgen(BatchArgs A, StageArgs S,
                  lst[wv]);
 }
 
-// Staged trace inside base strips of 128 to 512 rows: one wave per strip.
-template <int E>
-__global__ void __launch_bounds__(kWave) k_stage_leaf_tall(BatchArgs A, StageArgs S) {
+// Staged trace inside base strips of 128 to 512 rows: K waves per strip.
+template <int Ew, int K>
+__global__ void __launch_bounds__(K * kWave) k_stage_leaf_tall(BatchArgs A, StageArgs S) {
+    constexpr int E = Ew * K;
     __shared__ int32_t tab[kLeafTabTall];
     __shared__ unsigned long long masks[E * kWave * E];
     __shared__ int32_t mrow[E * kWave], xs[E * kWave];
+    __shared__ int32_t ring[(K - 1) * E * kWave], sync[K + 2];
     const int2 pu = stage_item(S, blockIdx.x);
     const PairRec &P = A.pairs[pu.x];
     uint8_t *ws = A.ws + P.ws_off;
@@ -551,10 +553,11 @@ __global__ void __launch_bounds__(kWave) k_stage_leaf_tall(BatchArgs A, StageArg
     const int32_t u = pu.y;
     const int32_t h = (u == g.nstrips - 1) ? g.hlast : P.h0;
     const int4 *nodes = reinterpret_cast<const int4 *>(ws + P.node_off[0]);
-    trace_leaf_tall<E>(A.symbols + P.a_off + (size_t)u * P.h0, h, P.n, A.sigma,
-                       reinterpret_cast<const int32_t *>(ws + P.off_nm), nodes[u], u * P.h0,
-                       A.a_idx + P.wit_off, A.b_idx + P.wit_off, P.m < P.n ? P.m : P.n,
-                       reinterpret_cast<int32_t *>(ws + P.off_hdr), tab, kLeafTabTall, masks, mrow, xs);
+    trace_leaf_pipe<Ew, K>(A.symbols + P.a_off + (size_t)u * P.h0, h, P.n, A.sigma,
+                           reinterpret_cast<const int32_t *>(ws + P.off_nm), nodes[u], u * P.h0,
+                           A.a_idx + P.wit_off, A.b_idx + P.wit_off, P.m < P.n ? P.m : P.n,
+                           reinterpret_cast<int32_t *>(ws + P.off_hdr), tab, kLeafTabTall, masks, mrow,
+                           xs, ring, sync);
 }
 
 // dynamic LDS a staged anchor search may take: what one work-group of gfx950
@@ -659,11 +662,11 @@ static hipError_t launch_stage(const BatchArgs &A, const StageArgs &S, dim3 grid
         }
         case ST_LEAF_TALL:
             if (A.base_rows <= 2 * kWave)
-                hipLaunchKernelGGL((k_stage_leaf_tall<2>), grid, dim3(kWave), 0, st, A, S);
+                hipLaunchKernelGGL((k_stage_leaf_tall<1, 2>), grid, dim3(2 * kWave), 0, st, A, S);
             else if (A.base_rows <= 4 * kWave)
-                hipLaunchKernelGGL((k_stage_leaf_tall<4>), grid, dim3(kWave), 0, st, A, S);
+                hipLaunchKernelGGL((k_stage_leaf_tall<1, 4>), grid, dim3(4 * kWave), 0, st, A, S);
             else
-                hipLaunchKernelGGL((k_stage_leaf_tall<8>), grid, dim3(kWave), 0, st, A, S);
+                hipLaunchKernelGGL((k_stage_leaf_tall<2, 4>), grid, dim3(4 * kWave), 0, st, A, S);
             break;
         default: return hipErrorInvalidValue;
     }

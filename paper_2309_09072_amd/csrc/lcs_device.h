@@ -1669,6 +1669,24 @@ __device__ void trace_split_block(const int32_t *__restrict__ U, int32_t hU,
 }
 
 // ---------------------------------------------------------------------------
+// nm_x[p] for a live lane, n + 1 otherwise: from the LDS window [s, s + W)
+// (W >= 1), from the global table past it.  The LDS read is unconditional and
+// the global one sits behind a wave-uniform branch: as the two arms of one
+// select, the compiler merges them into a single flat load, which waits on
+// both memory counters in every row of the dependent chain.
+__device__ __forceinline__ int32_t leaf_lookup(bool live, int32_t x, int32_t p, int32_t s, int32_t n,
+                                               const int32_t *tab, int32_t W,
+                                               const int32_t *__restrict__ nm) {
+    const int32_t q = imin(imax(p - s, 0), W - 1);
+    int32_t cd = tab[(live ? x : 0) * W + q];  // inside the window for every lane
+    if (!live) cd = n + 1;
+    const bool far = live && p - s >= W;
+    if (__ballot(far) != 0ull) {
+        if (far) cd = nm[(size_t)x * (n + 2) + p];
+    }
+    return cd;
+}
+
 // Midpoint trace inside a base strip of h <= H0 rows.  The breakout rows of
 // the single source s after each appended row, D_r(s, .) for r = 0..h, are
 // recomputed into LDS; the walk then goes back from (h, w, e): at row r the
@@ -1702,7 +1720,7 @@ __device__ void trace_leaf_block(const uint8_t *__restrict__ arow, int32_t h, in
         // by their lanes afterwards, with D_r(s, w) read from LDS.
         static_assert(H0 <= kWave, "one lane per column");
         // Only weights up to w0 and columns up to e = D_h(s, w0) matter (as in
-        // trace_leaf_tall below): lookups from columns past e are skipped, so
+        // trace_leaf_pipe below): lookups from columns past e are skipped, so
         // the table window [s, e] serves every lookup when it fits.
         const int32_t w0c = imin(imax(node.y, 0), h);
         const int32_t eend = imin(imax(node.z, s), n + 1);
@@ -1731,8 +1749,7 @@ __device__ void trace_leaf_block(const uint8_t *__restrict__ arow, int32_t h, in
             // (wave_shr:1); lane 0 keeps `s`, column 0
             const int32_t p = __builtin_amdgcn_update_dpp(s, d, 0x138, 0xF, 0xF, false);
             const bool live = (j <= w0c) && (x < sigma) && (p <= pmax);
-            int32_t cd = INF;
-            if (live) cd = (p - s < W) ? tab[x * W + (p - s)] : nm[(size_t)x * (n + 2) + p];
+            const int32_t cd = leaf_lookup(live, x, p, s, n, tab, W, nm);
             const int32_t dn = umin(d, cd);
             const bool hit = live && (cd == dn);
             const unsigned long long mk = __ballot(hit);
@@ -1801,55 +1818,71 @@ __device__ void trace_leaf_block(const uint8_t *__restrict__ arow, int32_t h, in
 }
 
 // ---------------------------------------------------------------------------
-// Midpoint trace inside a base strip of up to 64 E rows (E = 2, 4 or 8), by one
-// wave: the row appends of the one-wave form above with E columns per lane
-// (column j = 64 e + lane + 1 in register e), restricted to the weights
-// 1..w0 of the node.  Column j of D_{r+1}(s, .) depends only on columns j - 1
-// and j of D_r(s, .), and the walk reads no weight above w0, so every lookup
-// index is at most e = D_h(s, w0) and a table window [s, e] serves all of
-// them when it fits in LDS (lookups past the window read the global table).
-// Pass 1 keeps each row's match masks in LDS; the walk back picks the row
-// where each weight matched; pass 2 appends the rows again and each lane
-// keeps D_r(s, j) of the row r where weight j matched (that column - 1 is the
-// match in b).  Lookups from columns past e are skipped (see below), so with
-// the window [s, e] in LDS no lookup goes to the global table.  LDS: tab (tabcap int32), masks (h E u64), mrow and xs (64 E
-// int32 each).
-template <int E>
-__device__ __forceinline__ void leaf_row(int32_t (&d)[E], int32_t x, int32_t s, int32_t n,
-                                         int32_t sigma, int32_t wmax, int32_t pmax, const int32_t *tab,
-                                         int32_t W, const int32_t *__restrict__ nm,
-                                         unsigned long long (&mk)[E]) {
+// Midpoint trace inside a base strip of up to 64 E rows (E = Ew K = 2, 4 or 8
+// registers of columns), by K waves: the row appends of the one-wave form
+// above with column j = 64 e + lane + 1 in register e (wave k holds registers
+// Ew k .. Ew k + Ew - 1), restricted to the weights 1..w0 of the node.
+// Column j of D_{r+1}(s, .) depends only on columns j - 1 and j of D_r(s, .),
+// and the walk reads no weight above w0, so every lookup index is at most
+// e = D_h(s, w0) and a table window [s, e] serves all of them when it fits in
+// LDS (lookups past the window read the global table).  Pass 1 keeps each
+// row's match masks in LDS; the walk back picks the row where each weight
+// matched; pass 2 appends the rows again and each lane keeps D_r(s, j) of the
+// row r where weight j matched (that column - 1 is the match in b).
+// The waves run as a pipeline: appending row r in wave k needs D_r(s, .) of
+// the column just left of its own, which wave k - 1 holds.  Wave k - 1 stores
+// that value for every row in an LDS ring and publishes its progress every
+// kLeafLag rows; wave k runs at least kLeafLag rows behind it (a bounded
+// wait: past kSpinLimit polls the trace reports kErrTrace).  Pass 2 reads the
+// values pass 1 stored (they are the same), with no waiting.
+// LDS: tab (tabcap int32), masks (h E u64), mrow and xs (64 E int32 each),
+// ring ((K - 1) 64 E int32), sync (K + 2 int32).
+constexpr int32_t kLeafTabTall = 16384;  // next-match entries a tall leaf keeps in LDS
+constexpr int32_t kLeafLag = 8;
+constexpr uint32_t kLeafSpinLimit = 1u << 22;
+
+// One row append for this wave's Ew registers; carry = D_r(s, jbase), the
+// column left of the wave's first (s for the first wave).
+template <int Ew>
+__device__ __forceinline__ void leaf_row(int32_t (&d)[Ew], int32_t carry, int32_t jbase, int32_t x,
+                                         int32_t s, int32_t n, int32_t sigma, int32_t wmax,
+                                         int32_t pmax, const int32_t *tab, int32_t W,
+                                         const int32_t *__restrict__ nm, unsigned long long (&mk)[Ew]) {
     const int lane = __lane_id();
     const int32_t INF = n + 1;
-    int32_t p[E];  // D_r(s, j - 1): the next lower column, across lanes and registers
+    int32_t p[Ew];  // D_r(s, j - 1): the next lower column, across lanes and registers
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const int32_t carry = (e == 0) ? s : __builtin_amdgcn_readlane(d[e > 0 ? e - 1 : 0], kWave - 1);
-        p[e] = __builtin_amdgcn_update_dpp(carry, d[e], 0x138, 0xF, 0xF, false);  // wave_shr:1
+    for (int e = 0; e < Ew; ++e) {
+        const int32_t c = (e == 0) ? carry : __builtin_amdgcn_readlane(d[e > 0 ? e - 1 : 0], kWave - 1);
+        p[e] = __builtin_amdgcn_update_dpp(c, d[e], 0x138, 0xF, 0xF, false);  // wave_shr:1
     }
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const int32_t j = e * kWave + lane + 1;
+    for (int e = 0; e < Ew; ++e) {
+        const int32_t j = jbase + e * kWave + lane + 1;
         const bool live = j <= wmax && x < sigma && p[e] <= pmax;
-        int32_t cd = INF;
-        if (live) cd = (p[e] - s < W) ? tab[x * W + (p[e] - s)] : nm[(size_t)x * (n + 2) + p[e]];
+        const int32_t cd = leaf_lookup(live, x, p[e], s, n, tab, W, nm);
         const int32_t dn = umin(d[e], cd);
         mk[e] = __ballot(live && cd == dn);
         d[e] = (j <= wmax) ? dn : INF;
     }
 }
 
-constexpr int32_t kLeafTabTall = 16384;  // next-match entries a tall leaf keeps in LDS
-template <int E>
-__device__ void trace_leaf_tall(const uint8_t *__restrict__ arow, int32_t h, int32_t n,
+template <int Ew, int K>
+__device__ void trace_leaf_pipe(const uint8_t *__restrict__ arow, int32_t h, int32_t n,
                                 int32_t sigma, const int32_t *__restrict__ nm, int4 node,
                                 int32_t row0, int32_t *__restrict__ a_idx,
                                 int32_t *__restrict__ b_idx, int32_t wcap, int32_t *err,
                                 int32_t *tab, int32_t tabcap, unsigned long long *masks,
-                                int32_t *mrow, int32_t *xs) {
+                                int32_t *mrow, int32_t *xs, int32_t *ring, int32_t *sync) {
+    constexpr int32_t E = Ew * K;
+    constexpr int32_t RH = E * kWave;  // ring entries per wave boundary (>= h)
+    constexpr int32_t NT = K * kWave;
     const int32_t INF = n + 1;
     const int32_t s = umin(node.x, n);
     const int lane = __lane_id();
+    const int32_t tid = threadIdx.x;
+    const int32_t wv = __builtin_amdgcn_readfirstlane(tid / kWave);
+    const int32_t jbase = wv * Ew * kWave;  // this wave: columns jbase + 1 .. jbase + 64 Ew
     const int32_t w0 = imin(imax(node.y, 0), h);
     const int32_t off = imax(node.w, 0);
     const int32_t eend = imin(imax(node.z, s), n + 1);
@@ -1862,71 +1895,143 @@ __device__ void trace_leaf_tall(const uint8_t *__restrict__ arow, int32_t h, int
     for (int32_t x = 0; x < sigma; ++x) {
         const int32_t *src = nm + (size_t)x * (n + 2) + s;
         int32_t *dst = tab + x * W;
-        for (int32_t c0 = 0; c0 < W; c0 += 8 * kWave) {
+        for (int32_t c0 = 0; c0 < W; c0 += 8 * NT) {
             int32_t v[8];
 #pragma unroll
-            for (int t = 0; t < 8; ++t) v[t] = src[imin(c0 + t * kWave + lane, W - 1)];
+            for (int t = 0; t < 8; ++t) v[t] = src[imin(c0 + t * NT + tid, W - 1)];
 #pragma unroll
             for (int t = 0; t < 8; ++t)
-                if (c0 + t * kWave + lane < W) dst[c0 + t * kWave + lane] = v[t];
+                if (c0 + t * NT + tid < W) dst[c0 + t * NT + tid] = v[t];
         }
     }
-    for (int32_t r = lane; r < E * kWave; r += kWave) {
+    for (int32_t r = tid; r < E * kWave; r += NT) {
         xs[r] = (r < h) ? (int32_t)arow[r] : 0;
         mrow[r] = 0;
     }
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    int32_t d[E];
+    if (tid < K) sync[tid] = 0;
+    __syncthreads();
+    int32_t d[Ew];
 #pragma unroll
-    for (int e = 0; e < E; ++e) d[e] = INF;
-    for (int32_t r = 0; r < h; ++r) {
-        unsigned long long mk[E];
-        leaf_row<E>(d, xs[r], s, n, sigma, w0, pmax, tab, W, nm, mk);
+    for (int e = 0; e < Ew; ++e) d[e] = INF;
+    bool stall = false;
+    int32_t avail = 0, cbase = 0, win = 0;  // lane l of win: ring row cbase + l of the wave to the left
+    // rows go in runs of 64: lane l holds the run's row symbol l, and gathers
+    // the row's match masks and the value for the ring, written out per run
+    // (the ring every kLeafLag rows), so one LDS round trip is left per row
+    for (int32_t rb = 0; rb < h; rb += kWave) {
+        const int32_t xr = xs[rb + lane];
+        const int32_t rn = imin(kWave, h - rb);
+        uint32_t mlo[Ew], mhi[Ew];
+        int32_t rv = INF;
+        for (int32_t rr = 0; rr < rn; ++rr) {
+            const int32_t r = rb + rr;
+            if (wv < K - 1) {  // D_r(s, last column) for the wave to the right
+                const int32_t last = __builtin_amdgcn_readlane(d[Ew - 1], kWave - 1);
+                if (lane == rr) rv = last;
+                if ((r + 1) % kLeafLag == 0 || r + 1 == h) {
+                    if (lane <= rr) ring[wv * RH + rb + lane] = rv;
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                    if (lane == 0)
+                        __hip_atomic_store(sync + wv, r + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                }
+            }
+            int32_t carry = s;
+            if (wv > 0) {
+                if (r >= avail) {
+                    const int32_t want = imin(r + kLeafLag, h);
+                    int32_t got = __builtin_amdgcn_readfirstlane(
+                        __hip_atomic_load(sync + wv - 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
+                    uint32_t spins = 0;
+                    while (got < want) {
+                        __builtin_amdgcn_s_sleep(1);
+                        if (++spins > kLeafSpinLimit) {
+                            stall = true;
+                            got = h;
+                            break;
+                        }
+                        got = __builtin_amdgcn_readfirstlane(
+                            __hip_atomic_load(sync + wv - 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+                    avail = got;
+                    cbase = r;
+                    win = (r + lane < h) ? ring[(wv - 1) * RH + r + lane] : INF;
+                } else if (r >= cbase + kWave) {
+                    cbase = r;
+                    win = (r + lane < h) ? ring[(wv - 1) * RH + r + lane] : INF;
+                }
+                carry = __builtin_amdgcn_readlane(win, r - cbase);
+            }
+            unsigned long long mk[Ew];
+            leaf_row<Ew>(d, carry, jbase, __builtin_amdgcn_readlane(xr, rr), s, n, sigma, w0, pmax, tab,
+                         W, nm, mk);
+            if (lane == rr) {
+#pragma unroll
+                for (int e = 0; e < Ew; ++e) {
+                    mlo[e] = (uint32_t)mk[e];
+                    mhi[e] = (uint32_t)(mk[e] >> 32);
+                }
+            }
+        }
+        if (lane < rn) {
+#pragma unroll
+            for (int e = 0; e < Ew; ++e)
+                masks[(rb + lane) * E + wv * Ew + e] = ((unsigned long long)mhi[e] << 32) | mlo[e];
+        }
+    }
+    if (stall && lane == 0) atomicOr(err, kErrTrace);
+    if (w0 >= 1 && ((w0 - 1) >> 6) / Ew == wv) {  // the wave holding column w0: D_h(s, w0)
+        const int32_t er = ((w0 - 1) >> 6) - wv * Ew;
+        int32_t v = INF;
+#pragma unroll
+        for (int e = 0; e < Ew; ++e)
+            if (e == er) v = __builtin_amdgcn_readlane(d[e], (w0 - 1) & (kWave - 1));
+        if (lane == 0) sync[K] = v;
+    }
+    __syncthreads();
+    if (wv == 0) {
+        int32_t w = w0;
+        for (int32_t r = h; r >= 1 && w >= 1; --r) {
+            const unsigned long long mk = masks[(r - 1) * E + ((w - 1) >> 6)];
+            if ((mk >> ((w - 1) & (kWave - 1))) & 1ull) {
+                if (lane == 0) mrow[w - 1] = r;
+                --w;
+            }
+        }
+        const int32_t dend = (w0 >= 1) ? sync[K] : s;
         if (lane == 0) {
-#pragma unroll
-            for (int e = 0; e < E; ++e) masks[r * E + e] = mk[e];
+            if (w != 0 || dend != node.z) atomicOr(err, kErrTrace);
+            sync[K + 1] = w;
         }
     }
-    int32_t dend = s;
-    if (w0 >= 1) {
+    __syncthreads();
+    if (sync[K + 1] != 0 || w0 == 0) return;
+    int32_t mr[Ew], cap[Ew];
 #pragma unroll
-        for (int e = 0; e < E; ++e)
-            if (e == ((w0 - 1) >> 6)) dend = __builtin_amdgcn_readlane(d[e], (w0 - 1) & (kWave - 1));
-    }
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    int32_t w = w0;
-    for (int32_t r = h; r >= 1 && w >= 1; --r) {
-        const unsigned long long mk = masks[(r - 1) * E + ((w - 1) >> 6)];
-        if ((mk >> ((w - 1) & (kWave - 1))) & 1ull) {
-            if (lane == 0) mrow[w - 1] = r;
-            --w;
-        }
-    }
-    if (lane == 0 && (w != 0 || dend != node.z)) atomicOr(err, kErrTrace);
-    if (w != 0 || w0 == 0) return;
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    int32_t mr[E], cap[E];
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const int32_t j = e * kWave + lane + 1;
+    for (int e = 0; e < Ew; ++e) {
+        const int32_t j = jbase + e * kWave + lane + 1;
         mr[e] = (j <= w0) ? mrow[j - 1] : 0;
         cap[e] = INF;
         d[e] = INF;
     }
     const int32_t rlast = mrow[w0 - 1];  // weights match in increasing rows
-    for (int32_t r = 0; r < rlast; ++r) {
-        unsigned long long mk[E];
-        leaf_row<E>(d, xs[r], s, n, sigma, w0, pmax, tab, W, nm, mk);
+    for (int32_t rb = 0; rb < rlast; rb += kWave) {
+        const int32_t xr = xs[rb + lane];
+        win = (wv > 0 && rb + lane < h) ? ring[(wv - 1) * RH + rb + lane] : INF;
+        const int32_t rn = imin(kWave, rlast - rb);
+        for (int32_t rr = 0; rr < rn; ++rr) {
+            const int32_t carry = (wv > 0) ? __builtin_amdgcn_readlane(win, rr) : s;
+            unsigned long long mk[Ew];
+            leaf_row<Ew>(d, carry, jbase, __builtin_amdgcn_readlane(xr, rr), s, n, sigma, w0, pmax, tab,
+                         W, nm, mk);
 #pragma unroll
-        for (int e = 0; e < E; ++e)
-            if (mr[e] == r + 1) cap[e] = d[e];
+            for (int e = 0; e < Ew; ++e)
+                if (mr[e] == rb + rr + 1) cap[e] = d[e];
+        }
     }
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const int32_t j = e * kWave + lane + 1;
+    for (int e = 0; e < Ew; ++e) {
+        const int32_t j = jbase + e * kWave + lane + 1;
         if (j <= w0 && mr[e] >= 1 && off + j <= wcap) {
             a_idx[off + j - 1] = row0 + mr[e] - 1;
             b_idx[off + j - 1] = cap[e] - 1;

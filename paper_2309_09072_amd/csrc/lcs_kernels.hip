@@ -279,20 +279,24 @@ __global__ void __launch_bounds__(kWave) k_trace_leaf(const uint8_t *a, int32_t 
                                wcap, err, lds, tab, kLeafTab);
 }
 
-// Base strips of 128 to 512 rows (E = 2, 4, 8): one wave per strip.
-template <int E>
-__global__ void __launch_bounds__(kWave) k_trace_leaf_tall(const uint8_t *a, int32_t n, int32_t sigma,
-                                                            const int32_t *nm, int32_t h0,
-                                                            int32_t nstrips, int32_t hlast,
-                                                            const int4 *nodes, int32_t *a_idx,
-                                                            int32_t *b_idx, int32_t wcap, int32_t *err) {
+// Base strips of 128 to 512 rows (Ew K = 2, 4, 8 registers of columns): K
+// waves per strip.
+template <int Ew, int K>
+__global__ void __launch_bounds__(K * kWave) k_trace_leaf_pipe(const uint8_t *a, int32_t n,
+                                                                int32_t sigma, const int32_t *nm,
+                                                                int32_t h0, int32_t nstrips,
+                                                                int32_t hlast, const int4 *nodes,
+                                                                int32_t *a_idx, int32_t *b_idx,
+                                                                int32_t wcap, int32_t *err) {
+    constexpr int E = Ew * K;
     __shared__ int32_t tab[kLeafTabTall];
     __shared__ unsigned long long masks[E * kWave * E];
     __shared__ int32_t mrow[E * kWave], xs[E * kWave];
+    __shared__ int32_t ring[(K - 1) * E * kWave], sync[K + 2];
     const int32_t s = blockIdx.x;
     const int32_t h = (s == nstrips - 1) ? hlast : h0;
-    trace_leaf_tall<E>(a + (size_t)s * h0, h, n, sigma, nm, nodes[s], s * h0, a_idx, b_idx, wcap,
-                       err, tab, kLeafTabTall, masks, mrow, xs);
+    trace_leaf_pipe<Ew, K>(a + (size_t)s * h0, h, n, sigma, nm, nodes[s], s * h0, a_idx, b_idx, wcap,
+                           err, tab, kLeafTabTall, masks, mrow, xs, ring, sync);
 }
 
 __global__ void __launch_bounds__(kBlock) k_semilocal(const int32_t *top, int32_t m, int32_t n,
@@ -563,16 +567,16 @@ hipError_t launch_trace_leaf(int32_t h0, const uint8_t *a, int32_t n, int32_t si
                                nstrips, hlast, nodes, a_idx, b_idx, wcap, err);
             break;
         case 128:
-            hipLaunchKernelGGL(k_trace_leaf_tall<2>, dim3(nstrips), dim3(kWave), 0, s, a, n, sigma, nm,
-                               h0, nstrips, hlast, nodes, a_idx, b_idx, wcap, err);
+            hipLaunchKernelGGL((k_trace_leaf_pipe<1, 2>), dim3(nstrips), dim3(2 * kWave), 0, s, a, n,
+                               sigma, nm, h0, nstrips, hlast, nodes, a_idx, b_idx, wcap, err);
             break;
         case 256:
-            hipLaunchKernelGGL(k_trace_leaf_tall<4>, dim3(nstrips), dim3(kWave), 0, s, a, n, sigma, nm,
-                               h0, nstrips, hlast, nodes, a_idx, b_idx, wcap, err);
+            hipLaunchKernelGGL((k_trace_leaf_pipe<1, 4>), dim3(nstrips), dim3(4 * kWave), 0, s, a, n,
+                               sigma, nm, h0, nstrips, hlast, nodes, a_idx, b_idx, wcap, err);
             break;
         case 512:
-            hipLaunchKernelGGL(k_trace_leaf_tall<8>, dim3(nstrips), dim3(kWave), 0, s, a, n, sigma, nm,
-                               h0, nstrips, hlast, nodes, a_idx, b_idx, wcap, err);
+            hipLaunchKernelGGL((k_trace_leaf_pipe<2, 4>), dim3(nstrips), dim3(4 * kWave), 0, s, a, n,
+                               sigma, nm, h0, nstrips, hlast, nodes, a_idx, b_idx, wcap, err);
             break;
         default:
             return hipErrorInvalidValue;
