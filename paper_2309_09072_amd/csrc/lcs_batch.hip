@@ -497,7 +497,7 @@ __global__ void __launch_bounds__(kBlock) k_stage_anchor_wave(BatchArgs A, Stage
 // Staged seaweed combing: one work-group per (pair, base strip), blockDim set
 // by the plan's longest string (C columns per thread, as in the single-pair
 // path).
-template <int C>
+template <int C, bool kPacked>
 __global__ void __launch_bounds__(kCombMaxThreads) k_stage_comb(BatchArgs A, StageArgs S) {
     __shared__ int32_t lds[3 * kCombMaxRows + 4 * (kCombMaxThreads / kWave)];
     const int2 pu = stage_item(S, blockIdx.x);
@@ -507,7 +507,7 @@ __global__ void __launch_bounds__(kCombMaxThreads) k_stage_comb(BatchArgs A, Sta
     const int32_t s = pu.y;
     const int32_t h = (s == g.nstrips - 1) ? g.hlast : P.h0;
     int32_t *cs = reinterpret_cast<int32_t *>(ws + P.off_comb) + (size_t)s * (size_t)P.comb_stride;
-    comb_strip_block<kCombMaxThreads, C>(A.symbols + P.a_off + (size_t)s * P.h0, h, A.symbols + P.b_off,
+    comb_strip_block<kCombMaxThreads, C, kPacked>(A.symbols + P.a_off + (size_t)s * P.h0, h, A.symbols + P.b_off,
                                          P.n, A.sigma, cs, cs + P.n, cs + 2 * (size_t)P.n, lds,
                                          reinterpret_cast<int32_t *>(ws + P.off_hdr));
 }
@@ -636,15 +636,18 @@ static hipError_t launch_stage(const BatchArgs &A, const StageArgs &S, dim3 grid
         case ST_SPLIT: hipLaunchKernelGGL((k_stage<H0, ST_SPLIT>), grid, dim3(kBlock), 0, st, A, S); break;
         case ST_LEAF: hipLaunchKernelGGL((k_stage<H0, ST_LEAF>), grid, dim3(kBlock), 0, st, A, S); break;
         case ST_COMB: {
-            const int32_t C = (S.cols <= 4 * kCombMaxThreads) ? 4 : (S.cols <= 8 * kCombMaxThreads) ? 8 : 16;
-            int32_t thr = (S.cols + C - 1) / C;
-            thr = imin(kCombMaxThreads, imax(kWave, (thr + kWave - 1) / kWave * kWave));
-            if (C == 4)
-                hipLaunchKernelGGL((k_stage_comb<4>), grid, dim3(thr), 0, st, A, S);
+            const int32_t C = comb_cols(S.cols);  // as in the single-pair path
+            const int32_t thr = comb_threads(S.cols, C);
+            if (S.cols > kCombPackedMaxN)
+                hipLaunchKernelGGL((k_stage_comb<16, false>), grid, dim3(thr), 0, st, A, S);
+            else if (C == 4)
+                hipLaunchKernelGGL((k_stage_comb<4, true>), grid, dim3(thr), 0, st, A, S);
             else if (C == 8)
-                hipLaunchKernelGGL((k_stage_comb<8>), grid, dim3(thr), 0, st, A, S);
+                hipLaunchKernelGGL((k_stage_comb<8, true>), grid, dim3(thr), 0, st, A, S);
+            else if (C == 16)
+                hipLaunchKernelGGL((k_stage_comb<16, true>), grid, dim3(thr), 0, st, A, S);
             else
-                hipLaunchKernelGGL((k_stage_comb<16>), grid, dim3(thr), 0, st, A, S);
+                hipLaunchKernelGGL((k_stage_comb<32, true>), grid, dim3(thr), 0, st, A, S);
             break;
         }
         case ST_DGEN: {

@@ -293,6 +293,19 @@ __device__ void base_strip_block(const uint8_t *__restrict__ arow, int32_t h, in
 // pos[0..n) (n + 1 for a seaweed that leaves on the right) and right[0..h).
 constexpr int32_t kCombMaxThreads = 1024;
 constexpr int32_t kCombMaxRows = 512;
+constexpr int32_t kCombPackedMaxN = 32767;  // labels -h..n-1 and the padding 0x7fff fit int16
+// columns per thread and threads of the combing work-group for n columns
+__host__ __device__ inline int32_t comb_cols(int32_t n) {
+    if (n > kCombPackedMaxN) return 16;
+    int32_t c = 4;
+    while (c < 32 && c * 512 < n) c *= 2;
+    return c;
+}
+__host__ __device__ inline int32_t comb_threads(int32_t n, int32_t C) {
+    const int32_t t = (n + C - 1) / C;
+    const int32_t r = (t + kWave - 1) / kWave * kWave;
+    return r < kWave ? kWave : (r > kCombMaxThreads ? kCombMaxThreads : r);
+}
 
 // (c, v) stands for x -> c ? v : min(x, v); b := b after a
 __device__ __forceinline__ void comb_fn_after(int32_t ac, int32_t av, int32_t &bc, int32_t &bv) {
@@ -340,14 +353,50 @@ __device__ __forceinline__ void wave_fn_scan(int32_t &c, int32_t &v) {
     }
 }
 
-// lds: 3 * h + 4 * (NT / kWave) int32
-template <int NT, int C>
+// Packed 16-bit lanes (two labels or two symbols per register).
+typedef short comb_s2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t pk_min_i16(uint32_t a, uint32_t b) {
+    const comb_s2 x = __builtin_bit_cast(comb_s2, a), y = __builtin_bit_cast(comb_s2, b);
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_min(x, y));
+}
+__device__ __forceinline__ uint32_t pk_max_i16(uint32_t a, uint32_t b) {
+    const comb_s2 x = __builtin_bit_cast(comb_s2, a), y = __builtin_bit_cast(comb_s2, b);
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(x, y));
+}
+// 0xffff in each half where the halves of a and b are equal, else 0:
+// min(a ^ b, 1) - 1 per half.  Written as the packed instructions themselves
+// (register operands only): as plain code the compiler splits it into
+// per-half compares and re-packs, which costs more than the unpacked form.
+__device__ __forceinline__ uint32_t pk_eq_mask(uint32_t a, uint32_t b) {
+    const uint32_t one = 0x00010001u;
+    uint32_t t, m;
+    asm("v_pk_min_u16 %0, %1, %2" : "=v"(t) : "v"(a ^ b), "v"(one));
+    asm("v_pk_sub_u16 %0, %1, %2" : "=v"(m) : "v"(t), "v"(one));
+    return m;
+}
+// (m & a) | (~m & b) in one instruction
+__device__ __forceinline__ uint32_t bit_select(uint32_t m, uint32_t a, uint32_t b) {
+    uint32_t r;
+    asm("v_bfi_b32 %0, %1, %2, %3" : "=v"(r) : "v"(m), "v"(a), "v"(b));
+    return r;
+}
+__device__ __forceinline__ int32_t sext16(uint32_t v) { return (int32_t)(int16_t)(v & 0xffffu); }
+
+// lds: 3 * h + 4 * (NT / kWave) int32.  kPacked (n <= 32767, so every label
+// and the padding label 0x7fff fit int16): register e of a thread holds
+// columns cb + e and cb + C/2 + e in its two halves, two independent chains
+// whose maps compose as (high after low), so a row costs about half the
+// instructions: v_pk_min/max_i16, a bit-select for the match, and a packed
+// equality mask per symbol pair.
+template <int NT, int C, bool kPacked>
 __device__ void comb_strip_block(const uint8_t *__restrict__ arow, int32_t h,
                                  const uint8_t *__restrict__ b, int32_t n, int32_t sigma,
                                  int32_t *__restrict__ bot, int32_t *__restrict__ pos,
                                  int32_t *__restrict__ right, int32_t *lds, int32_t *err) {
     constexpr int32_t NW = NT / kWave;
+    constexpr int32_t P = C / 2;
     static_assert(NW <= 16, "the wave totals are scanned by one row of 16 lanes");
+    static_assert(C % 2 == 0, "packed columns come in pairs");
     const int32_t tid = threadIdx.x;
     const int32_t nthr = (int32_t)blockDim.x;  // <= NT, a multiple of kWave
     const int32_t w = __builtin_amdgcn_readfirstlane(tid / kWave);
@@ -363,24 +412,54 @@ __device__ void comb_strip_block(const uint8_t *__restrict__ arow, int32_t h,
     }
     const int32_t T = nthr * C;
     for (int32_t c0 = 0; c0 < n; c0 += T) {
-        int32_t v[C], bs[C];
+        int32_t v[kPacked ? 1 : C], bs[kPacked ? 1 : C];
+        uint32_t v2[kPacked ? P : 1], b2[kPacked ? P : 1];
         const int32_t cb = c0 + tid * C;
+        if constexpr (kPacked) {
 #pragma unroll
-        for (int e = 0; e < C; ++e) {
-            const int32_t c = cb + e;
-            v[e] = (c < n) ? c : 0x7fffffff;   // a padding column maps x -> x
-            bs[e] = (c < n) ? (int32_t)b[c] : 0x100;
+            for (int e = 0; e < P; ++e) {
+                const int32_t cl = cb + e, ch = cb + P + e;
+                const uint32_t vl = (cl < n) ? (uint32_t)cl : 0x7fffu, vh = (ch < n) ? (uint32_t)ch : 0x7fffu;
+                const uint32_t sl = (cl < n) ? (uint32_t)b[cl] : 0x100u, sh = (ch < n) ? (uint32_t)b[ch] : 0x100u;
+                v2[e] = vl | (vh << 16);
+                b2[e] = sl | (sh << 16);
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < C; ++e) {
+                const int32_t c = cb + e;
+                v[e] = (c < n) ? c : 0x7fffffff;   // a padding column maps x -> x
+                bs[e] = (c < n) ? (int32_t)b[c] : 0x100;
+            }
         }
         __syncthreads();  // hin of this tile written
         int32_t buf = 0;
         for (int32_t r = 0; r < h; ++r) {
             const int32_t x = xs[r];
             int32_t fc = 0, fv = 0x7fffffff;
+            uint32_t m2[kPacked ? P : 1];
+            int32_t clo = 0, vlo = 0;
+            if constexpr (kPacked) {
+                const uint32_t xx = (uint32_t)x * 0x00010001u;
+                uint32_t fc2 = 0, fv2 = 0x7fff7fffu;
 #pragma unroll
-            for (int e = 0; e < C; ++e) {
-                const bool m = bs[e] == x;
-                fv = m ? v[e] : imin(fv, v[e]);
-                fc |= (int32_t)m;
+                for (int e = 0; e < P; ++e) {
+                    m2[e] = pk_eq_mask(b2[e], xx);
+                    fv2 = bit_select(m2[e], v2[e], pk_min_i16(fv2, v2[e]));
+                    fc2 |= m2[e];
+                }
+                clo = (fc2 & 0xffffu) != 0;
+                vlo = sext16(fv2);
+                const int32_t chi = (fc2 >> 16) != 0, vhi = (int32_t)fv2 >> 16;
+                fc = clo | chi;
+                fv = chi ? vhi : imin(vlo, vhi);
+            } else {
+#pragma unroll
+                for (int e = 0; e < C; ++e) {
+                    const bool m = bs[e] == x;
+                    fv = m ? v[e] : imin(fv, v[e]);
+                    fc |= (int32_t)m;
+                }
             }
             wave_fn_scan(fc, fv);
             if (lane == kWave - 1) {
@@ -405,22 +484,51 @@ __device__ void comb_strip_block(const uint8_t *__restrict__ arow, int32_t h,
             const int32_t xl = fc ? fv : imin(xw, fv);       // label leaving this thread
             // label entering this thread: the left neighbour's (wave_shr:1), lane 0: xw
             int32_t hh = __builtin_amdgcn_update_dpp(xw, xl, 0x138, 0xF, 0xF, false);
+            if constexpr (kPacked) {
+                const int32_t hhi = clo ? vlo : imin(hh, vlo);  // entering the high chain
+                uint32_t h2 = ((uint32_t)hh & 0xffffu) | ((uint32_t)hhi << 16);
 #pragma unroll
-            for (int e = 0; e < C; ++e) {
-                const int32_t y = v[e];
-                const bool m = bs[e] == x;
-                v[e] = m ? hh : imax(hh, y);
-                hh = m ? y : imin(hh, y);
+                for (int e = 0; e < P; ++e) {
+                    const uint32_t y = v2[e];
+                    const uint32_t lo = pk_min_i16(h2, y), hi = pk_max_i16(h2, y);
+                    v2[e] = bit_select(m2[e], h2, hi);
+                    h2 = bit_select(m2[e], y, lo);
+                }
+                hh = (int32_t)h2 >> 16;
+            } else {
+#pragma unroll
+                for (int e = 0; e < C; ++e) {
+                    const int32_t y = v[e];
+                    const bool m = bs[e] == x;
+                    v[e] = m ? hh : imax(hh, y);
+                    hh = m ? y : imin(hh, y);
+                }
             }
             if (tid == nthr - 1) hout[r] = hh;
             buf ^= 1;
         }
+        if constexpr (kPacked) {
 #pragma unroll
-        for (int e = 0; e < C; ++e) {
-            const int32_t c = cb + e;
-            if (c < n) {
-                bot[c] = v[e];
-                if (v[e] >= 0) pos[v[e]] = c;
+            for (int e = 0; e < P; ++e) {
+                const int32_t cl = cb + e, ch = cb + P + e;
+                const int32_t ll = sext16(v2[e]), lh = (int32_t)v2[e] >> 16;
+                if (cl < n) {
+                    bot[cl] = ll;
+                    if (ll >= 0) pos[ll] = cl;
+                }
+                if (ch < n) {
+                    bot[ch] = lh;
+                    if (lh >= 0) pos[lh] = ch;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < C; ++e) {
+                const int32_t c = cb + e;
+                if (c < n) {
+                    bot[c] = v[e];
+                    if (v[e] >= 0) pos[v[e]] = c;
+                }
             }
         }
         __syncthreads();  // hout complete, every read of hin done

@@ -32,7 +32,7 @@ __global__ void __launch_bounds__(kBlock) k_base(const uint8_t *a, int32_t n, in
 
 // Seaweed combing of every base strip, one work-group (NT threads, fewer
 // for narrow strings) per strip; region comb holds comb_stride int32 per strip.
-template <int NT, int C>
+template <int NT, int C, bool kPacked>
 __global__ void __launch_bounds__(NT) k_comb(const uint8_t *a, const uint8_t *b, int32_t n,
                                              int32_t sigma, int32_t h0, int32_t nstrips,
                                              int32_t hlast, int32_t *comb, int32_t cstride,
@@ -41,8 +41,8 @@ __global__ void __launch_bounds__(NT) k_comb(const uint8_t *a, const uint8_t *b,
     const int32_t s = blockIdx.x;
     const int32_t h = (s == nstrips - 1) ? hlast : h0;
     int32_t *cs = comb + (size_t)s * (size_t)cstride;
-    comb_strip_block<NT, C>(a + (size_t)s * h0, h, b, n, sigma, cs, cs + n, cs + 2 * (size_t)n, lds,
-                            err);
+    comb_strip_block<NT, C, kPacked>(a + (size_t)s * h0, h, b, n, sigma, cs, cs + n, cs + 2 * (size_t)n,
+                                     lds, err);
 }
 
 // Breakout rows of every base strip from its combing: one wave per run of
@@ -382,20 +382,28 @@ hipError_t launch_base_comb(int32_t h0, const uint8_t *a, const uint8_t *b, int3
                             int32_t hlast, int32_t *comb, int32_t comb_stride, int32_t *err,
                             hipStream_t s) {
     if (h0 < 1 || h0 > kCombMaxRows) return hipErrorInvalidValue;
-    // the fewest columns per thread that cover the string in one tile (a
-    // shorter dependent chain per row), at most 16 (then several tiles)
-    const int32_t C = (n <= 4 * kCombMaxThreads) ? 4 : (n <= 8 * kCombMaxThreads) ? 8 : 16;
-    int32_t thr = (n + C - 1) / C;
-    thr = imin(kCombMaxThreads, imax(kWave, (thr + kWave - 1) / kWave * kWave));
-    if (C == 4)
-        hipLaunchKernelGGL((k_comb<kCombMaxThreads, 4>), dim3(nstrips), dim3(thr), 0, s, a, b, n, sigma,
-                           h0, nstrips, hlast, comb, comb_stride, err);
+    // Columns per thread: the row's scan over the threads costs about as much
+    // per thread as 16 packed columns, so a work-group of ~512 threads (two
+    // waves per SIMD) with up to 32 columns each; labels fit 16 bits up to
+    // 32767 columns (the packed form), past that 16 unpacked columns per thread
+    // and several tiles.
+    const int32_t C = comb_cols(n);
+    const int32_t thr = comb_threads(n, C);
+    if (n > kCombPackedMaxN)
+        hipLaunchKernelGGL((k_comb<kCombMaxThreads, 16, false>), dim3(nstrips), dim3(thr), 0, s, a, b, n,
+                           sigma, h0, nstrips, hlast, comb, comb_stride, err);
+    else if (C == 4)
+        hipLaunchKernelGGL((k_comb<kCombMaxThreads, 4, true>), dim3(nstrips), dim3(thr), 0, s, a, b, n,
+                           sigma, h0, nstrips, hlast, comb, comb_stride, err);
     else if (C == 8)
-        hipLaunchKernelGGL((k_comb<kCombMaxThreads, 8>), dim3(nstrips), dim3(thr), 0, s, a, b, n, sigma,
-                           h0, nstrips, hlast, comb, comb_stride, err);
+        hipLaunchKernelGGL((k_comb<kCombMaxThreads, 8, true>), dim3(nstrips), dim3(thr), 0, s, a, b, n,
+                           sigma, h0, nstrips, hlast, comb, comb_stride, err);
+    else if (C == 16)
+        hipLaunchKernelGGL((k_comb<kCombMaxThreads, 16, true>), dim3(nstrips), dim3(thr), 0, s, a, b, n,
+                           sigma, h0, nstrips, hlast, comb, comb_stride, err);
     else
-        hipLaunchKernelGGL((k_comb<kCombMaxThreads, 16>), dim3(nstrips), dim3(thr), 0, s, a, b, n, sigma,
-                           h0, nstrips, hlast, comb, comb_stride, err);
+        hipLaunchKernelGGL((k_comb<kCombMaxThreads, 32, true>), dim3(nstrips), dim3(thr), 0, s, a, b, n,
+                           sigma, h0, nstrips, hlast, comb, comb_stride, err);
     // runs short enough that the waves fill the chip, long enough to amortise
     // the scan for the first vertex of each run
     int32_t chunk = 256;

@@ -146,6 +146,20 @@ def test_base_strips_alphabet_20():
             _base_rows_check(a, b, plan, ws, verts)
 
 
+def test_wide_strings_combed_in_32_bits():
+    """More than 32767 columns: labels no longer fit 16 bits, so the base strips
+    are combed in the 32-bit form (several column tiles per strip)."""
+    r = np.random.default_rng(3232)
+    n = 40000
+    verts = sorted(set(list(range(0, n + 1, 997)) + [1, 16383, 16384, 32767, 32768, 32769, n - 1, n]))
+    for sig, h0 in ((4, 64), (20, 256)):
+        a = r.integers(0, sig, 700).astype(np.uint8)
+        b = r.integers(0, sig, n).astype(np.uint8)
+        say("wide comb", sig, h0)
+        Lg, plan, ws = check_against_oracle(a, b, sig, base_rows=h0)
+        _base_rows_check(a, b, plan, ws, verts)
+
+
 def test_many_short_anchor_rows():
     """Levels with many anchors and rows of at most 1024 weights run one
     anchor search per wave; 512 x 3000 with 16-row strips and tile 4 puts
