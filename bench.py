@@ -202,7 +202,8 @@ def bench_batched(reps: int, tune_shapes: bool = True, modes=BATCH_MODES, base_r
         tuning = tr.as_json()
         log("batch autotuner: base_rows %d tile %d (%s)" % (h0, tile, tuning["ms"]))
     plan = lcs.Batch(batch.count, maxlen, batch.sigma, h0, tile, slots=slots)
-    # the persistent and pair-queue modes append rows: base strips of at most 64 rows
+    # the persistent and pair-queue modes append rows: base strips of at most 64
+    # rows; one pair per launch runs at 64 rows too (its best for pairs this short)
     h0_rows = min(h0, 64)
     plan_rows = plan if h0 <= 64 else lcs.Batch(batch.count, maxlen, batch.sigma, h0_rows, tile,
                                                   slots=slots)
@@ -216,7 +217,7 @@ def bench_batched(reps: int, tune_shapes: bool = True, modes=BATCH_MODES, base_r
     nbytes_rows = nbytes if h0 <= 64 else sum(alg_bytes(int(batch.m[p]), int(batch.n[p]), h0_rows)
                                               for p in range(batch.count))
     out = {"workload": batch.name, "pairs": batch.count, "cells": batch.cells, "seed": batch.seed,
-           "slots": slots, "base_rows": h0, "base_rows_persistent_modes": h0_rows, "tile": tile,
+           "slots": slots, "base_rows": h0, "base_rows_other_modes": h0_rows, "tile": tile,
            "autotune": tuning,
            "workspace_GB": round(ws.numel() / 1e9, 2), "alg_bytes_per_batch": nbytes}
     mode_of = {"staged_graph": lcs.BATCH_STAGED | lcs.BATCH_GRAPH,
@@ -226,8 +227,8 @@ def bench_batched(reps: int, tune_shapes: bool = True, modes=BATCH_MODES, base_r
                "one_pair_per_launch": lcs.BATCH_PER_PAIR}
     for name in modes:
         mode = mode_of[name]
-        combed = bool(mode & (lcs.BATCH_STAGED | lcs.BATCH_PER_PAIR))
-        pl, nb = (plan, nbytes) if combed else (plan_rows, nbytes_rows)
+        staged = bool(mode & lcs.BATCH_STAGED)
+        pl, nb = (plan, nbytes) if staged else (plan_rows, nbytes_rows)
         pl.submit(sym, batch.a_off, batch.b_off, batch.m, batch.n, ws, lengths, ai, bi, mode)
         torch.cuda.synchronize()
         # poison the outputs, so that a mode which wrote nothing cannot pass on the
