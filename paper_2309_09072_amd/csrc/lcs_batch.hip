@@ -540,9 +540,9 @@ __global__ void __launch_bounds__(kBlock) k_stage_dgen(BatchArgs A, StageArgs S,
 
 // Staged trace inside base strips of 128 to 512 rows: K waves per strip.
 template <int Ew, int K>
-__global__ void __launch_bounds__(K * kWave) k_stage_leaf_tall(BatchArgs A, StageArgs S) {
+__global__ void __launch_bounds__(K * kWave) k_stage_leaf_tall(BatchArgs A, StageArgs S, int32_t tabcap) {
     constexpr int E = Ew * K;
-    __shared__ int32_t tab[kLeafTabTall];
+    extern __shared__ int32_t tab[];  // tabcap int32: the next-match window
     __shared__ unsigned long long masks[E * kWave * E];
     __shared__ int32_t mrow[E * kWave], xs[E * kWave];
     __shared__ int32_t ring[(K - 1) * E * kWave], sync[K + 2];
@@ -556,7 +556,7 @@ __global__ void __launch_bounds__(K * kWave) k_stage_leaf_tall(BatchArgs A, Stag
     trace_leaf_pipe<Ew, K>(A.symbols + P.a_off + (size_t)u * P.h0, h, P.n, A.sigma,
                            reinterpret_cast<const int32_t *>(ws + P.off_nm), nodes[u], u * P.h0,
                            A.a_idx + P.wit_off, A.b_idx + P.wit_off, P.m < P.n ? P.m : P.n,
-                           reinterpret_cast<int32_t *>(ws + P.off_hdr), tab, kLeafTabTall, masks, mrow,
+                           reinterpret_cast<int32_t *>(ws + P.off_hdr), tab, tabcap, masks, mrow,
                            xs, ring, sync);
 }
 
@@ -663,14 +663,17 @@ static hipError_t launch_stage(const BatchArgs &A, const StageArgs &S, dim3 grid
                 hipLaunchKernelGGL((k_stage_dgen<8>), g, dim3(kBlock), 0, st, A, S, items);
             break;
         }
-        case ST_LEAF_TALL:
+        case ST_LEAF_TALL: {
+            const int32_t tabcap = leaf_tab_cap(A.sigma, S.cols);  // by the plan's longest string
+            const size_t bytes = 4 * (size_t)tabcap;
             if (A.base_rows <= 2 * kWave)
-                hipLaunchKernelGGL((k_stage_leaf_tall<1, 2>), grid, dim3(2 * kWave), 0, st, A, S);
+                hipLaunchKernelGGL((k_stage_leaf_tall<1, 2>), grid, dim3(2 * kWave), bytes, st, A, S, tabcap);
             else if (A.base_rows <= 4 * kWave)
-                hipLaunchKernelGGL((k_stage_leaf_tall<1, 4>), grid, dim3(4 * kWave), 0, st, A, S);
+                hipLaunchKernelGGL((k_stage_leaf_tall<1, 4>), grid, dim3(4 * kWave), bytes, st, A, S, tabcap);
             else
-                hipLaunchKernelGGL((k_stage_leaf_tall<2, 4>), grid, dim3(4 * kWave), 0, st, A, S);
+                hipLaunchKernelGGL((k_stage_leaf_tall<2, 4>), grid, dim3(4 * kWave), bytes, st, A, S, tabcap);
             break;
+        }
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -1945,7 +1945,11 @@ __device__ void trace_leaf_block(const uint8_t *__restrict__ arow, int32_t h, in
 // values pass 1 stored (they are the same), with no waiting.
 // LDS: tab (tabcap int32), masks (h E u64), mrow and xs (64 E int32 each),
 // ring ((K - 1) 64 E int32), sync (K + 2 int32).
-constexpr int32_t kLeafTabTall = 16384;  // next-match entries a tall leaf keeps in LDS
+constexpr int32_t kLeafTabTall = 16384;  // next-match entries a tall leaf keeps in LDS, at most
+__host__ __device__ inline int32_t leaf_tab_cap(int32_t sigma, int32_t n) {
+    const int64_t all = (int64_t)(sigma < 1 ? 1 : sigma) * (n + 2);
+    return all < kLeafTabTall ? (int32_t)all : kLeafTabTall;
+}
 constexpr int32_t kLeafLag = 8;
 constexpr uint32_t kLeafSpinLimit = 1u << 22;
 
