@@ -545,6 +545,137 @@ __device__ void comb_strip_block(const uint8_t *__restrict__ arow, int32_t h,
     if (__syncthreads_or(bad) && tid == 0) atomicOr(err, kErrSymbol);
 }
 
+// Combing of one strip (n <= 32767, packed labels) as a pipeline of the
+// work-group's waves instead of a block-wide scan per row: wave w owns
+// columns [64 C w, 64 C (w + 1)), lane l the C columns 64 C w + C l ...
+// For row r a wave first composes its own columns' maps (they depend only on
+// its columns' labels and the row symbol) and scans them over its lanes; only
+// then does it need the label entering its first column, which is the label
+// leaving wave w - 1 in row r.  That label crosses the wave with one map
+// application (no barrier, no block scan), is written to the LDS slot
+// ring[w][r] (every slot starts at a sentinel no label takes) and read there
+// by wave w + 1, so the row's waves run staggered by one LDS hop and the
+// apply of every wave overlaps the next waves' hops.  A wait past
+// kCombSpinLimit polls reports kErrTrace instead of hanging.  lds: 64 C-column
+// waves K = blockDim.x / 64 <= 16; ring K x h int32, then h int32 of row
+// symbols.
+constexpr uint32_t kCombSpinLimit = 1u << 22;
+constexpr int32_t kCombPipeWaves = 16;  // waves of a pipelined combing work-group, at most
+// columns per lane of the pipelined combing (<= kCombPipeWaves waves cover n)
+__host__ __device__ inline int32_t comb_pipe_cols(int32_t n) {
+    int32_t c = 4;
+    while (c < 32 && (n + 64 * c - 1) / (64 * c) > kCombPipeWaves) c *= 2;
+    return c;
+}
+constexpr int32_t kCombSentinel = (int32_t)0x80000000;
+template <int C>
+__device__ void comb_strip_pipe(const uint8_t *__restrict__ arow, int32_t h,
+                                const uint8_t *__restrict__ b, int32_t n, int32_t sigma,
+                                int32_t *__restrict__ bot, int32_t *__restrict__ pos,
+                                int32_t *__restrict__ right, int32_t *lds, int32_t *err) {
+    constexpr int32_t P = C / 2;
+    const int32_t tid = threadIdx.x;
+    const int32_t nthr = (int32_t)blockDim.x;
+    const int32_t K = nthr / kWave;
+    const int32_t w = __builtin_amdgcn_readfirstlane(tid / kWave);
+    const int lane = __lane_id();
+    int32_t *ring = lds;          // ring[w * h + r]: label leaving wave w in row r
+    int32_t *xs = lds + K * h;    // row symbols
+    bool bad = false;
+    for (int32_t i = tid; i < K * h; i += nthr) ring[i] = kCombSentinel;
+    for (int32_t r = tid; r < h; r += nthr) {
+        xs[r] = arow[r];
+        bad |= xs[r] >= sigma;
+    }
+    uint32_t v2[P], b2[P];
+    const int32_t cb = tid * C;
+#pragma unroll
+    for (int e = 0; e < P; ++e) {
+        const int32_t cl = cb + e, ch = cb + P + e;
+        const uint32_t vl = (cl < n) ? (uint32_t)cl : 0x7fffu, vh = (ch < n) ? (uint32_t)ch : 0x7fffu;
+        const uint32_t sl = (cl < n) ? (uint32_t)b[cl] : 0x100u, sh = (ch < n) ? (uint32_t)b[ch] : 0x100u;
+        v2[e] = vl | (vh << 16);
+        b2[e] = sl | (sh << 16);
+    }
+    __syncthreads();
+    bool stall = false;
+    for (int32_t rb = 0; rb < h; rb += kWave) {
+        const int32_t xr = xs[rb + imin(lane, h - 1 - rb)];
+        const int32_t rn = imin(kWave, h - rb);
+        for (int32_t rr = 0; rr < rn; ++rr) {
+            const int32_t r = rb + rr;
+            const uint32_t xx = (uint32_t)__builtin_amdgcn_readlane(xr, rr) * 0x00010001u;
+            uint32_t m2[P];
+            uint32_t fc2 = 0, fv2 = 0x7fff7fffu;
+#pragma unroll
+            for (int e = 0; e < P; ++e) {
+                m2[e] = pk_eq_mask(b2[e], xx);
+                fv2 = bit_select(m2[e], v2[e], pk_min_i16(fv2, v2[e]));
+                fc2 |= m2[e];
+            }
+            const int32_t clo = (fc2 & 0xffffu) != 0, vlo = sext16(fv2);
+            const int32_t chi = (fc2 >> 16) != 0, vhi = (int32_t)fv2 >> 16;
+            int32_t fc = clo | chi, fv = chi ? vhi : imin(vlo, vhi);
+            wave_fn_scan(fc, fv);  // lane l: lanes 0..l of this wave composed
+            // the label entering this wave in row r
+            int32_t xin = -(r + 1);
+            if (w > 0) {
+                const int32_t *slot = ring + (w - 1) * h + r;
+                xin = __builtin_amdgcn_readfirstlane(
+                    __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
+                uint32_t spins = 0;
+                while (xin == kCombSentinel) {
+                    __builtin_amdgcn_s_sleep(1);
+                    if (++spins > kCombSpinLimit) {
+                        stall = true;
+                        xin = 0;
+                        break;
+                    }
+                    xin = __builtin_amdgcn_readfirstlane(
+                        __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
+                }
+            }
+            const int32_t xl = fc ? fv : imin(xin, fv);  // label leaving this lane's columns
+            const int32_t xout = __builtin_amdgcn_readlane(xl, kWave - 1);
+            if (lane == 0)
+                __hip_atomic_store(ring + w * h + r, xout, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            // label entering this lane: the left neighbour's (wave_shr:1), lane 0: xin
+            const int32_t hh = __builtin_amdgcn_update_dpp(xin, xl, 0x138, 0xF, 0xF, false);
+            const int32_t hhi = clo ? vlo : imin(hh, vlo);  // entering the high chain
+            uint32_t h2 = ((uint32_t)hh & 0xffffu) | ((uint32_t)hhi << 16);
+#pragma unroll
+            for (int e = 0; e < P; ++e) {
+                const uint32_t y = v2[e];
+                const uint32_t lo = pk_min_i16(h2, y), hi = pk_max_i16(h2, y);
+                v2[e] = bit_select(m2[e], h2, hi);
+                h2 = bit_select(m2[e], y, lo);
+            }
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < P; ++e) {
+        const int32_t cl = cb + e, ch = cb + P + e;
+        const int32_t ll = sext16(v2[e]), lh = (int32_t)v2[e] >> 16;
+        if (cl < n) {
+            bot[cl] = ll;
+            if (ll >= 0) pos[ll] = cl;
+        }
+        if (ch < n) {
+            bot[ch] = lh;
+            if (lh >= 0) pos[lh] = ch;
+        }
+    }
+    __syncthreads();  // every ring slot of the last wave written
+    for (int32_t r = tid; r < h; r += nthr) {
+        const int32_t lab = ring[(K - 1) * h + r];
+        right[r] = lab;
+        if (lab >= 0) pos[lab] = n + 1;
+    }
+    if (__syncthreads_or(bad) && tid == 0) atomicOr(err, kErrSymbol);
+    if (__syncthreads_or(stall) && tid == 0) atomicOr(err, kErrTrace);
+}
+
+
 // Breakout rows of vertices i0 .. i1-1 of one base strip (h rows) from its
 // combing, by one wave; vertex n + 1 is the all-unreachable sentinel row.
 // The wave keeps the sorted set {q + 1 : q >= i, bot[q] < i} (at most h

@@ -45,6 +45,20 @@ __global__ void __launch_bounds__(NT) k_comb(const uint8_t *a, const uint8_t *b,
                                      lds, err);
 }
 
+// The same as a pipeline of waves (n <= 32767): 64 C columns per wave.
+template <int C>
+__global__ void __launch_bounds__(kCombPipeWaves * kWave) k_comb_pipe(const uint8_t *a, const uint8_t *b,
+                                                                       int32_t n, int32_t sigma, int32_t h0,
+                                                                       int32_t nstrips, int32_t hlast,
+                                                                       int32_t *comb, int32_t cstride,
+                                                                       int32_t *err) {
+    __shared__ int32_t lds[(kCombPipeWaves + 1) * kCombMaxRows];
+    const int32_t s = blockIdx.x;
+    const int32_t h = (s == nstrips - 1) ? hlast : h0;
+    int32_t *cs = comb + (size_t)s * (size_t)cstride;
+    comb_strip_pipe<C>(a + (size_t)s * h0, h, b, n, sigma, cs, cs + n, cs + 2 * (size_t)n, lds, err);
+}
+
 // Breakout rows of every base strip from its combing: one wave per run of
 // `chunk` consecutive vertices of one strip (runs of a strip on one XCD).
 template <int E>
@@ -390,7 +404,22 @@ hipError_t launch_base_comb(int32_t h0, const uint8_t *a, const uint8_t *b, int3
     // and several tiles.
     const int32_t C = comb_cols(n);
     const int32_t thr = comb_threads(n, C);
-    if (n > kCombPackedMaxN)
+    if (n <= kCombPackedMaxN && n >= 1) {  // the wave pipeline
+        const int32_t cp = comb_pipe_cols(n);
+        const dim3 blk((unsigned)(kWave * ((n + kWave * cp - 1) / (kWave * cp))));
+        if (cp == 4)
+            hipLaunchKernelGGL((k_comb_pipe<4>), dim3(nstrips), blk, 0, s, a, b, n, sigma, h0, nstrips,
+                               hlast, comb, comb_stride, err);
+        else if (cp == 8)
+            hipLaunchKernelGGL((k_comb_pipe<8>), dim3(nstrips), blk, 0, s, a, b, n, sigma, h0, nstrips,
+                               hlast, comb, comb_stride, err);
+        else if (cp == 16)
+            hipLaunchKernelGGL((k_comb_pipe<16>), dim3(nstrips), blk, 0, s, a, b, n, sigma, h0, nstrips,
+                               hlast, comb, comb_stride, err);
+        else
+            hipLaunchKernelGGL((k_comb_pipe<32>), dim3(nstrips), blk, 0, s, a, b, n, sigma, h0, nstrips,
+                               hlast, comb, comb_stride, err);
+    } else if (n > kCombPackedMaxN)
         hipLaunchKernelGGL((k_comb<kCombMaxThreads, 16, false>), dim3(nstrips), dim3(thr), 0, s, a, b, n,
                            sigma, h0, nstrips, hlast, comb, comb_stride, err);
     else if (C == 4)
