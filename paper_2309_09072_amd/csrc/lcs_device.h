@@ -561,10 +561,13 @@ __device__ void comb_strip_block(const uint8_t *__restrict__ arow, int32_t h,
 // symbols.
 constexpr uint32_t kCombSpinLimit = 1u << 22;
 constexpr int32_t kCombPipeWaves = 16;  // waves of a pipelined combing work-group, at most
-// columns per lane of the pipelined combing (<= kCombPipeWaves waves cover n)
+// Columns per lane of the pipelined combing: up to 32, so that 8 waves cover n
+// (16 for n > 16384).  Each wave's row scan costs about as much as 16 packed
+// columns; fewer, longer waves cut that per row (16384^2 base strips: 16 waves
+// 0.83 ms, 8 waves 0.76, 4 waves of 64 columns 0.79).
 __host__ __device__ inline int32_t comb_pipe_cols(int32_t n) {
     int32_t c = 4;
-    while (c < 32 && (n + 64 * c - 1) / (64 * c) > kCombPipeWaves) c *= 2;
+    while (c < 32 && (n + 64 * c - 1) / (64 * c) > kCombPipeWaves / 2) c *= 2;
     return c;
 }
 constexpr int32_t kCombSentinel = (int32_t)0x80000000;
