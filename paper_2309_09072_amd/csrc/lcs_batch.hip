@@ -512,6 +512,22 @@ __global__ void __launch_bounds__(kCombMaxThreads) k_stage_comb(BatchArgs A, Sta
                                          reinterpret_cast<int32_t *>(ws + P.off_hdr));
 }
 
+// The same as a pipeline of waves (the plan's longest string <= 32767): 64 C
+// columns per wave, blockDim set by that string.
+template <int C>
+__global__ void __launch_bounds__(kCombPipeWaves * kWave) k_stage_comb_pipe(BatchArgs A, StageArgs S) {
+    __shared__ int32_t lds[(kCombPipeWaves + 1) * kCombMaxRows];
+    const int2 pu = stage_item(S, blockIdx.x);
+    const PairRec &P = A.pairs[pu.x];
+    uint8_t *ws = A.ws + P.ws_off;
+    const LevelGeom &g = P.lev[0];
+    const int32_t s = pu.y;
+    const int32_t h = (s == g.nstrips - 1) ? g.hlast : P.h0;
+    int32_t *cs = reinterpret_cast<int32_t *>(ws + P.off_comb) + (size_t)s * (size_t)P.comb_stride;
+    comb_strip_pipe<C>(A.symbols + P.a_off + (size_t)s * P.h0, h, A.symbols + P.b_off, P.n, A.sigma, cs,
+                       cs + P.n, cs + 2 * (size_t)P.n, lds, reinterpret_cast<int32_t *>(ws + P.off_hdr));
+}
+
 // Staged breakout-row generation: one wave per (pair, strip, run of
 // kStageRun vertices), four per work-group (runs of one strip on one XCD).
 constexpr int32_t kStageRun = 64;
@@ -638,7 +654,18 @@ static hipError_t launch_stage(const BatchArgs &A, const StageArgs &S, dim3 grid
         case ST_COMB: {
             const int32_t C = comb_cols(S.cols);  // as in the single-pair path
             const int32_t thr = comb_threads(S.cols, C);
-            if (S.cols > kCombPackedMaxN)
+            if (S.cols <= kCombPackedMaxN) {  // the wave pipeline (a pair's n may be below S.cols)
+                const int32_t cp = comb_pipe_cols(S.cols);
+                const dim3 blk((unsigned)(kWave * ((S.cols + kWave * cp - 1) / (kWave * cp))));
+                if (cp == 4)
+                    hipLaunchKernelGGL((k_stage_comb_pipe<4>), grid, blk, 0, st, A, S);
+                else if (cp == 8)
+                    hipLaunchKernelGGL((k_stage_comb_pipe<8>), grid, blk, 0, st, A, S);
+                else if (cp == 16)
+                    hipLaunchKernelGGL((k_stage_comb_pipe<16>), grid, blk, 0, st, A, S);
+                else
+                    hipLaunchKernelGGL((k_stage_comb_pipe<32>), grid, blk, 0, st, A, S);
+            } else if (S.cols > kCombPackedMaxN)
                 hipLaunchKernelGGL((k_stage_comb<16, false>), grid, dim3(thr), 0, st, A, S);
             else if (C == 4)
                 hipLaunchKernelGGL((k_stage_comb<4, true>), grid, dim3(thr), 0, st, A, S);
