@@ -223,7 +223,8 @@ int32_t enqueue_trace(const Layout &L, uint8_t *ws, const uint8_t *a, int32_t *a
     R.begin(LCS_PHASE_TRACE_LEAF, 0, (int64_t)L.m + 8 * (int64_t)L.m);
     hipError_t e = launch_trace_leaf(L.h0, a, L.n, L.sigma, nm, g0.nstrips, g0.hlast,
                                      reinterpret_cast<const int4 *>(ws + L.node_off[0]), a_idx,
-                                     b_idx, L.m < L.n ? L.m : L.n, hdr, s);
+                                     b_idx, L.m < L.n ? L.m : L.n, hdr, ws + L.off_leaf, L.leaf_stride,
+                                     s);
     R.end();
     return hip_status(e);
 }

@@ -559,7 +559,6 @@ template <int Ew, int K>
 __global__ void __launch_bounds__(K * kWave) k_stage_leaf_tall(BatchArgs A, StageArgs S, int32_t tabcap) {
     constexpr int E = Ew * K;
     extern __shared__ int32_t tab[];  // tabcap int32: the next-match window
-    __shared__ unsigned long long masks[E * kWave * E];
     __shared__ int32_t mrow[E * kWave], xs[E * kWave];
     __shared__ int32_t ring[(K - 1) * E * kWave], sync[K + 2];
     const int2 pu = stage_item(S, blockIdx.x);
@@ -572,8 +571,8 @@ __global__ void __launch_bounds__(K * kWave) k_stage_leaf_tall(BatchArgs A, Stag
     trace_leaf_pipe<Ew, K>(A.symbols + P.a_off + (size_t)u * P.h0, h, P.n, A.sigma,
                            reinterpret_cast<const int32_t *>(ws + P.off_nm), nodes[u], u * P.h0,
                            A.a_idx + P.wit_off, A.b_idx + P.wit_off, P.m < P.n ? P.m : P.n,
-                           reinterpret_cast<int32_t *>(ws + P.off_hdr), tab, tabcap, masks, mrow,
-                           xs, ring, sync);
+                           reinterpret_cast<int32_t *>(ws + P.off_hdr), tab, tabcap,
+                           ws + P.off_leaf + (size_t)u * (size_t)P.leaf_stride, mrow, xs, ring, sync);
 }
 
 // dynamic LDS a staged anchor search may take: what one work-group of gfx950
@@ -901,6 +900,8 @@ static bool make_pair(const lcs_batch_s *B, const lcs_pair_desc &pd, int32_t p, 
     R.h0 = B->d.base_rows;
     R.comb_stride = L.comb_stride;
     R.off_comb = L.off_comb;
+    R.off_leaf = L.off_leaf;
+    R.leaf_stride = L.leaf_stride;
     int32_t c = kCtrHead;
     for (int32_t l = 0; l < R.nlev; ++l) {
         R.lev[l] = L.lev[l];

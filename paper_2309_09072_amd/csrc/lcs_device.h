@@ -2067,18 +2067,18 @@ __device__ void trace_leaf_block(const uint8_t *__restrict__ arow, int32_t h, in
 // Column j of D_{r+1}(s, .) depends only on columns j - 1 and j of D_r(s, .),
 // and the walk reads no weight above w0, so every lookup index is at most
 // e = D_h(s, w0) and a table window [s, e] serves all of them when it fits in
-// LDS (lookups past the window read the global table).  Pass 1 keeps each
-// row's match masks in LDS; the walk back picks the row where each weight
-// matched; pass 2 appends the rows again and each lane keeps D_r(s, j) of the
-// row r where weight j matched (that column - 1 is the match in b).
+// LDS (lookups past the window read the global table).  The row appends
+// store each row's match masks and values in the strip's global scratch
+// (leaf_scratch_bytes); the walk back picks the row where each weight matched
+// and the weight's column is read from that row's stored values (their
+// column - 1 is the match in b).
 // The waves run as a pipeline: appending row r in wave k needs D_r(s, .) of
 // the column just left of its own, which wave k - 1 holds.  Wave k - 1 stores
 // that value for every row in an LDS ring and publishes its progress every
 // kLeafLag rows; wave k runs at least kLeafLag rows behind it (a bounded
-// wait: past kSpinLimit polls the trace reports kErrTrace).  Pass 2 reads the
-// values pass 1 stored (they are the same), with no waiting.
-// LDS: tab (tabcap int32), masks (h E u64), mrow and xs (64 E int32 each),
-// ring ((K - 1) 64 E int32), sync (K + 2 int32).
+// wait: past kSpinLimit polls the trace reports kErrTrace).
+// LDS: tab (tabcap int32), mrow and xs (64 E int32 each), ring ((K - 1) 64 E
+// int32), sync (K + 2 int32).
 constexpr int32_t kLeafTabTall = 16384;  // next-match entries a tall leaf keeps in LDS, at most
 __host__ __device__ inline int32_t leaf_tab_cap(int32_t sigma, int32_t n) {
     const int64_t all = (int64_t)(sigma < 1 ? 1 : sigma) * (n + 2);
@@ -2118,11 +2118,14 @@ __device__ void trace_leaf_pipe(const uint8_t *__restrict__ arow, int32_t h, int
                                 int32_t sigma, const int32_t *__restrict__ nm, int4 node,
                                 int32_t row0, int32_t *__restrict__ a_idx,
                                 int32_t *__restrict__ b_idx, int32_t wcap, int32_t *err,
-                                int32_t *tab, int32_t tabcap, unsigned long long *masks,
-                                int32_t *mrow, int32_t *xs, int32_t *ring, int32_t *sync) {
+                                int32_t *tab, int32_t tabcap, uint8_t *scratch, int32_t *mrow,
+                                int32_t *xs, int32_t *ring, int32_t *sync) {
     constexpr int32_t E = Ew * K;
     constexpr int32_t RH = E * kWave;  // ring entries per wave boundary (>= h)
     constexpr int32_t NT = K * kWave;
+    // global scratch of this strip: masks[r E + e], then rows[r RH + j - 1] = D_{r+1}(s, j)
+    unsigned long long *masks = reinterpret_cast<unsigned long long *>(scratch);
+    int32_t *rows = reinterpret_cast<int32_t *>(scratch + (size_t)RH * E * 8);
     const int32_t INF = n + 1;
     const int32_t s = umin(node.x, n);
     const int lane = __lane_id();
@@ -2211,6 +2214,8 @@ __device__ void trace_leaf_pipe(const uint8_t *__restrict__ arow, int32_t h, int
             unsigned long long mk[Ew];
             leaf_row<Ew>(d, carry, jbase, __builtin_amdgcn_readlane(xr, rr), s, n, sigma, w0, pmax, tab,
                          W, nm, mk);
+#pragma unroll
+            for (int e = 0; e < Ew; ++e) rows[(size_t)r * RH + jbase + e * kWave + lane] = d[e];
             if (lane == rr) {
 #pragma unroll
                 for (int e = 0; e < Ew; ++e) {
@@ -2234,14 +2239,28 @@ __device__ void trace_leaf_pipe(const uint8_t *__restrict__ arow, int32_t h, int
             if (e == er) v = __builtin_amdgcn_readlane(d[e], (w0 - 1) & (kWave - 1));
         if (lane == 0) sync[K] = v;
     }
-    __syncthreads();
+    __syncthreads();  // every wave's masks and rows stored
     if (wv == 0) {
         int32_t w = w0;
-        for (int32_t r = h; r >= 1 && w >= 1; --r) {
-            const unsigned long long mk = masks[(r - 1) * E + ((w - 1) >> 6)];
-            if ((mk >> ((w - 1) & (kWave - 1))) & 1ull) {
-                if (lane == 0) mrow[w - 1] = r;
-                --w;
+        for (int32_t rb = ((h - 1) / kWave) * kWave; rb >= 0 && w >= 1; rb -= kWave) {
+            uint32_t mlo[E], mhi[E];  // lane l: the masks of row rb + l
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const unsigned long long m = (rb + lane < h) ? masks[(size_t)(rb + lane) * E + e] : 0ull;
+                mlo[e] = (uint32_t)m;
+                mhi[e] = (uint32_t)(m >> 32);
+            }
+            for (int32_t r = imin(h, rb + kWave); r > rb && w >= 1; --r) {
+                const int32_t er = (w - 1) >> 6, bit = (w - 1) & (kWave - 1);
+                uint32_t word = 0;
+#pragma unroll
+                for (int e = 0; e < E; ++e)
+                    if (e == er) word = (uint32_t)__builtin_amdgcn_readlane((int32_t)(bit < 32 ? mlo[e] : mhi[e]),
+                                                                            r - 1 - rb);
+                if ((word >> (bit & 31)) & 1u) {
+                    if (lane == 0) mrow[w - 1] = r;
+                    --w;
+                }
             }
         }
         const int32_t dend = (w0 >= 1) ? sync[K] : s;
@@ -2252,35 +2271,14 @@ __device__ void trace_leaf_pipe(const uint8_t *__restrict__ arow, int32_t h, int
     }
     __syncthreads();
     if (sync[K + 1] != 0 || w0 == 0) return;
-    int32_t mr[Ew], cap[Ew];
+    // weight j matched in row mrow[j - 1]; its column is D of that row - 1
 #pragma unroll
     for (int e = 0; e < Ew; ++e) {
         const int32_t j = jbase + e * kWave + lane + 1;
-        mr[e] = (j <= w0) ? mrow[j - 1] : 0;
-        cap[e] = INF;
-        d[e] = INF;
-    }
-    const int32_t rlast = mrow[w0 - 1];  // weights match in increasing rows
-    for (int32_t rb = 0; rb < rlast; rb += kWave) {
-        const int32_t xr = xs[rb + lane];
-        win = (wv > 0 && rb + lane < h) ? ring[(wv - 1) * RH + rb + lane] : INF;
-        const int32_t rn = imin(kWave, rlast - rb);
-        for (int32_t rr = 0; rr < rn; ++rr) {
-            const int32_t carry = (wv > 0) ? __builtin_amdgcn_readlane(win, rr) : s;
-            unsigned long long mk[Ew];
-            leaf_row<Ew>(d, carry, jbase, __builtin_amdgcn_readlane(xr, rr), s, n, sigma, w0, pmax, tab,
-                         W, nm, mk);
-#pragma unroll
-            for (int e = 0; e < Ew; ++e)
-                if (mr[e] == rb + rr + 1) cap[e] = d[e];
-        }
-    }
-#pragma unroll
-    for (int e = 0; e < Ew; ++e) {
-        const int32_t j = jbase + e * kWave + lane + 1;
-        if (j <= w0 && mr[e] >= 1 && off + j <= wcap) {
-            a_idx[off + j - 1] = row0 + mr[e] - 1;
-            b_idx[off + j - 1] = cap[e] - 1;
+        const int32_t mr = (j <= w0) ? mrow[j - 1] : 0;
+        if (j <= w0 && mr >= 1 && off + j <= wcap) {
+            a_idx[off + j - 1] = row0 + mr - 1;
+            b_idx[off + j - 1] = rows[(size_t)(mr - 1) * RH + j - 1] - 1;
         }
     }
 }

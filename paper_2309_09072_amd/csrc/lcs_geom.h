@@ -75,6 +75,15 @@ struct StripRef {
 
 LCS_HD size_t strip_elems(int32_t n, int32_t h) { return (size_t)(n + 2) * (size_t)(h + 1); }
 
+// Scratch of the trace inside one base strip of h0 > 64 rows (E = h0 / 64
+// registers of columns): the match masks of every row (h0 E u64), then the
+// row values D_r(s, 1..64 E) of every row r = 1..h0 (int32); 0 for h0 <= 64.
+LCS_HD int64_t leaf_scratch_bytes(int32_t h0) {
+    if (h0 <= 64) return 0;
+    const int64_t E = (h0 + 63) / 64;
+    return ((int64_t)h0 * E * 8 + (int64_t)h0 * 64 * E * 4 + 255) & ~(int64_t)255;
+}
+
 LCS_HD StripRef child_strip(const CombineArgs &c, int32_t q) {
     StripRef r;
     if (q < c.nc - 1) {

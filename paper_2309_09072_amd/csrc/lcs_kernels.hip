@@ -302,16 +302,17 @@ __global__ void __launch_bounds__(K * kWave) k_trace_leaf_pipe(const uint8_t *a,
                                                                 int32_t hlast, const int4 *nodes,
                                                                 int32_t *a_idx, int32_t *b_idx,
                                                                 int32_t wcap, int32_t *err,
-                                                                int32_t tabcap) {
+                                                                int32_t tabcap, uint8_t *leaf,
+                                                                int64_t leaf_stride) {
     constexpr int E = Ew * K;
     extern __shared__ int32_t tab[];  // tabcap int32: the next-match window
-    __shared__ unsigned long long masks[E * kWave * E];
     __shared__ int32_t mrow[E * kWave], xs[E * kWave];
     __shared__ int32_t ring[(K - 1) * E * kWave], sync[K + 2];
     const int32_t s = blockIdx.x;
     const int32_t h = (s == nstrips - 1) ? hlast : h0;
     trace_leaf_pipe<Ew, K>(a + (size_t)s * h0, h, n, sigma, nm, nodes[s], s * h0, a_idx, b_idx, wcap,
-                           err, tab, tabcap, masks, mrow, xs, ring, sync);
+                           err, tab, tabcap, leaf + (size_t)s * (size_t)leaf_stride, mrow, xs, ring,
+                           sync);
 }
 
 __global__ void __launch_bounds__(kBlock) k_semilocal(const int32_t *top, int32_t m, int32_t n,
@@ -590,7 +591,7 @@ hipError_t launch_trace_splits(const TraceSplitArgs &t, hipStream_t s) {
 hipError_t launch_trace_leaf(int32_t h0, const uint8_t *a, int32_t n, int32_t sigma,
                              const int32_t *nm, int32_t nstrips, int32_t hlast, const int4 *nodes,
                              int32_t *a_idx, int32_t *b_idx, int32_t wcap, int32_t *err,
-                             hipStream_t s) {
+                             uint8_t *leaf, int64_t leaf_stride, hipStream_t s) {
     // the tall leaves' next-match window: no more than the tables hold, so that
     // short strings leave LDS for more leaves per CU
     const int32_t tabcap = leaf_tab_cap(sigma, n);
@@ -610,17 +611,17 @@ hipError_t launch_trace_leaf(int32_t h0, const uint8_t *a, int32_t n, int32_t si
         case 128:
             hipLaunchKernelGGL((k_trace_leaf_pipe<1, 2>), dim3(nstrips), dim3(2 * kWave), 4 * (size_t)tabcap,
                                s, a, n, sigma, nm, h0, nstrips, hlast, nodes, a_idx, b_idx, wcap, err,
-                               tabcap);
+                               tabcap, leaf, leaf_stride);
             break;
         case 256:
             hipLaunchKernelGGL((k_trace_leaf_pipe<1, 4>), dim3(nstrips), dim3(4 * kWave), 4 * (size_t)tabcap,
                                s, a, n, sigma, nm, h0, nstrips, hlast, nodes, a_idx, b_idx, wcap, err,
-                               tabcap);
+                               tabcap, leaf, leaf_stride);
             break;
         case 512:
             hipLaunchKernelGGL((k_trace_leaf_pipe<2, 4>), dim3(nstrips), dim3(4 * kWave), 4 * (size_t)tabcap,
                                s, a, n, sigma, nm, h0, nstrips, hlast, nodes, a_idx, b_idx, wcap, err,
-                               tabcap);
+                               tabcap, leaf, leaf_stride);
             break;
         default:
             return hipErrorInvalidValue;

@@ -25,7 +25,7 @@ hipError_t launch_trace_splits(const TraceSplitArgs &t, hipStream_t s);
 hipError_t launch_trace_leaf(int32_t h0, const uint8_t *a, int32_t n, int32_t sigma,
                              const int32_t *nm, int32_t nstrips, int32_t hlast, const int4 *nodes,
                              int32_t *a_idx, int32_t *b_idx, int32_t wcap, int32_t *err,
-                             hipStream_t s);
+                             uint8_t *leaf, int64_t leaf_stride, hipStream_t s);
 hipError_t launch_copy_len(const int32_t *hdr, int32_t *dst, hipStream_t s);
 hipError_t launch_path(const int32_t *a_idx, const int32_t *b_idx, const int32_t *length,
                        int32_t cap, int32_t m, int32_t n, int32_t *col_in, int32_t *col_out,

@@ -61,6 +61,8 @@ struct PairRec {
     int32_t h0;      // rows per base strip
     int32_t comb_stride;  // int32 per base strip in the combing region
     int64_t off_comb;     // the combing region (bot, pos, right per strip)
+    int64_t off_leaf;     // the trace leaves' scratch (leaf_stride bytes per strip)
+    int64_t leaf_stride;
 };
 
 // One stage of one pair in the global order, cut into chunks of at most
