@@ -72,11 +72,11 @@ typedef struct lcs_plan_desc {
     int32_t max_n;     /* largest column-string length, >= 0 */
     int32_t alphabet;  /* number of symbol codes, 1..256 */
     int32_t base_rows; /* rows per base strip (Section II-B-3 generalised to
-                          base_rows rows): 16, 32, 64, 128, 256 or 512; 0 selects
-                          by the sizes built (rows = max_m and columns = max_n,
-                          or the shorter and longer of the two with
-                          LCS_PLAN_ORIENT): 512 from 16384 rows, 256 from
-                          8192 rows or from 4096 rows with 8192 columns, 128
+                          base_rows rows): 16, 32, 64, 128, 256, 512 or 1024;
+                          0 selects by the sizes built (rows = max_m and
+                          columns = max_n, or the shorter and longer of the two
+                          with LCS_PLAN_ORIENT): 1024 from 12288 rows, 512 from
+                          8192 rows or from 4096 rows with 8192 columns, 256
                           from 4096 rows, else 64 */
     int32_t tile;      /* vertices per search tile of the combine: power of two
                           in 4..32; 0 selects the default (32) */
@@ -299,7 +299,7 @@ typedef struct lcs_batch_desc {
     int32_t max_pairs; /* most pairs per submit */
     int32_t max_len;   /* largest m and largest n of any pair */
     int32_t alphabet;  /* 1..256 */
-    int32_t base_rows; /* 16, 32 or 64 (0 selects 64); 128, 256 or 512 with
+    int32_t base_rows; /* 16, 32 or 64 (0 selects 64); 128 to 1024 with
                           LCS_BATCH_STAGED or LCS_BATCH_PER_PAIR only
                           (lcs_batch_submit returns LCS_E_INVAL otherwise) */
     int32_t tile;      /* as in lcs_plan_desc */

@@ -116,11 +116,12 @@ bool valid_shape(int32_t base_rows, int32_t tile) {
     return true;
 }
 
-// single-pair plans also take base strips of 128, 256 and 512 rows (their base
+// single-pair plans also take base strips of 128 to 1024 rows (their base
 // strips are combed; the serving loop and the persistent batch modes append
 // rows, up to 64)
 static bool valid_pair_shape(int32_t base_rows, int32_t tile) {
-    if (base_rows == 128 || base_rows == 256 || base_rows == 512) return valid_shape(64, tile);
+    if (base_rows == 128 || base_rows == 256 || base_rows == 512 || base_rows == 1024)
+        return valid_shape(64, tile);
     return valid_shape(base_rows, tile);
 }
 
@@ -237,16 +238,16 @@ extern "C" int32_t lcs_plan(const lcs_plan_desc *desc, lcs_plan_t *out, size_t *
     lcs_plan_desc d = *desc;
     if (d.base_rows == 0) {
         // Taller base strips replace combine levels; the combing of a strip is
-        // one work-group, so they pay once there are rows for many strips and
-        // columns enough to keep each busy (measured on MI355X: 64 rows up to
-        // 2048 x 2048, 128 at 4096 x 4096, 256 at 8192 x 8192 and 4096 x 16384,
-        // 512 at 16384 x 16384).
+        // one work-group and the trace inside it is a chain of its rows, so they
+        // pay once there are rows for many strips (measured on MI355X, random
+        // strings: 64 rows up to 2048 x 2048, 256 at 4096 x 4096, 512 at
+        // 8192 x 8192 and 4096 x 16384, 1024 from 12000 x 12000).
         const bool orient = (d.flags & LCS_PLAN_ORIENT) != 0;
         const int32_t rows = orient ? std::min(d.max_m, d.max_n) : d.max_m;
         const int32_t cols = orient ? std::max(d.max_m, d.max_n) : d.max_n;
-        d.base_rows = rows >= 16384                                     ? 512
-                      : (rows >= 8192 || (rows >= 4096 && cols >= 8192)) ? 256
-                      : rows >= 4096                                     ? 128
+        d.base_rows = rows >= 12288                                      ? 1024
+                      : (rows >= 8192 || (rows >= 4096 && cols >= 8192)) ? 512
+                      : rows >= 4096                                     ? 256
                                                                          : kDefaultBaseRows;
     }
     d.tile = resolve(d.tile, kDefaultTile);

@@ -516,7 +516,7 @@ __global__ void __launch_bounds__(kCombMaxThreads) k_stage_comb(BatchArgs A, Sta
 // columns per wave, blockDim set by that string.
 template <int C>
 __global__ void __launch_bounds__(kCombPipeWaves * kWave) k_stage_comb_pipe(BatchArgs A, StageArgs S) {
-    __shared__ int32_t lds[(kCombPipeWaves + 1) * kCombMaxRows];
+    extern __shared__ int32_t lds[];  // (waves + 1) x base rows int32
     const int2 pu = stage_item(S, blockIdx.x);
     const PairRec &P = A.pairs[pu.x];
     uint8_t *ws = A.ws + P.ws_off;
@@ -653,17 +653,19 @@ static hipError_t launch_stage(const BatchArgs &A, const StageArgs &S, dim3 grid
         case ST_COMB: {
             const int32_t C = comb_cols(S.cols);  // as in the single-pair path
             const int32_t thr = comb_threads(S.cols, C);
-            if (S.cols <= kCombPackedMaxN) {  // the wave pipeline (a pair's n may be below S.cols)
-                const int32_t cp = comb_pipe_cols(S.cols);
-                const dim3 blk((unsigned)(kWave * ((S.cols + kWave * cp - 1) / (kWave * cp))));
+            const int32_t cp = comb_pipe_cols(S.cols);
+            const int32_t waves = (S.cols + kWave * cp - 1) / (kWave * cp);
+            const size_t bytes = 4 * (size_t)(waves + 1) * (size_t)A.base_rows;
+            if (S.cols <= kCombPackedMaxN && bytes <= kCombPipeMaxLds) {  // the wave pipeline
+                const dim3 blk((unsigned)(kWave * waves));  // (a pair's n may be below S.cols)
                 if (cp == 4)
-                    hipLaunchKernelGGL((k_stage_comb_pipe<4>), grid, blk, 0, st, A, S);
+                    hipLaunchKernelGGL((k_stage_comb_pipe<4>), grid, blk, bytes, st, A, S);
                 else if (cp == 8)
-                    hipLaunchKernelGGL((k_stage_comb_pipe<8>), grid, blk, 0, st, A, S);
+                    hipLaunchKernelGGL((k_stage_comb_pipe<8>), grid, blk, bytes, st, A, S);
                 else if (cp == 16)
-                    hipLaunchKernelGGL((k_stage_comb_pipe<16>), grid, blk, 0, st, A, S);
+                    hipLaunchKernelGGL((k_stage_comb_pipe<16>), grid, blk, bytes, st, A, S);
                 else
-                    hipLaunchKernelGGL((k_stage_comb_pipe<32>), grid, blk, 0, st, A, S);
+                    hipLaunchKernelGGL((k_stage_comb_pipe<32>), grid, blk, bytes, st, A, S);
             } else if (S.cols > kCombPackedMaxN)
                 hipLaunchKernelGGL((k_stage_comb<16, false>), grid, dim3(thr), 0, st, A, S);
             else if (C == 4)
@@ -685,8 +687,10 @@ static hipError_t launch_stage(const BatchArgs &A, const StageArgs &S, dim3 grid
                 hipLaunchKernelGGL((k_stage_dgen<2>), g, dim3(kBlock), 0, st, A, S, items);
             else if (A.base_rows <= 4 * kWave)
                 hipLaunchKernelGGL((k_stage_dgen<4>), g, dim3(kBlock), 0, st, A, S, items);
-            else
+            else if (A.base_rows <= 8 * kWave)
                 hipLaunchKernelGGL((k_stage_dgen<8>), g, dim3(kBlock), 0, st, A, S, items);
+            else
+                hipLaunchKernelGGL((k_stage_dgen<16>), g, dim3(kBlock), 0, st, A, S, items);
             break;
         }
         case ST_LEAF_TALL: {
@@ -696,8 +700,10 @@ static hipError_t launch_stage(const BatchArgs &A, const StageArgs &S, dim3 grid
                 hipLaunchKernelGGL((k_stage_leaf_tall<1, 2>), grid, dim3(2 * kWave), bytes, st, A, S, tabcap);
             else if (A.base_rows <= 4 * kWave)
                 hipLaunchKernelGGL((k_stage_leaf_tall<1, 4>), grid, dim3(4 * kWave), bytes, st, A, S, tabcap);
-            else
+            else if (A.base_rows <= 8 * kWave)
                 hipLaunchKernelGGL((k_stage_leaf_tall<2, 4>), grid, dim3(4 * kWave), bytes, st, A, S, tabcap);
+            else
+                hipLaunchKernelGGL((k_stage_leaf_tall<4, 4>), grid, dim3(4 * kWave), bytes, st, A, S, tabcap);
             break;
         }
         default: return hipErrorInvalidValue;
@@ -762,8 +768,8 @@ static int32_t plan_sizes(const lcs_batch_desc *desc, lcs_batch_s *b) {
     if (d.max_pairs < 1 || d.max_len < 1 || d.alphabet < 1 || d.alphabet > 256 || d.flags != 0 ||
         d.slots < 0)
         return LCS_E_INVAL;
-    // 128- to 512-row base strips: staged and per-pair modes only (checked at submit)
-    const bool tall = d.base_rows == 128 || d.base_rows == 256 || d.base_rows == 512;
+    // 128- to 1024-row base strips: staged and per-pair modes only (checked at submit)
+    const bool tall = d.base_rows == 128 || d.base_rows == 256 || d.base_rows == 512 || d.base_rows == 1024;
     if (!valid_shape(tall ? 64 : d.base_rows, d.tile)) return LCS_E_INVAL;
     if (d.slots == 0 || d.slots > d.max_pairs) d.slots = d.max_pairs;
     Layout L;

@@ -292,7 +292,7 @@ __device__ void base_strip_block(const uint8_t *__restrict__ arow, int32_t h, in
 // labels leaving a tile on the right entering the next.  Writes bot[0..n),
 // pos[0..n) (n + 1 for a seaweed that leaves on the right) and right[0..h).
 constexpr int32_t kCombMaxThreads = 1024;
-constexpr int32_t kCombMaxRows = 512;
+constexpr int32_t kCombMaxRows = 1024;
 constexpr int32_t kCombPackedMaxN = 32767;  // labels -h..n-1 and the padding 0x7fff fit int16
 // columns per thread and threads of the combing work-group for n columns
 __host__ __device__ inline int32_t comb_cols(int32_t n) {
@@ -561,6 +561,7 @@ __device__ void comb_strip_block(const uint8_t *__restrict__ arow, int32_t h,
 // symbols.
 constexpr uint32_t kCombSpinLimit = 1u << 22;
 constexpr int32_t kCombPipeWaves = 16;  // waves of a pipelined combing work-group, at most
+constexpr size_t kCombPipeMaxLds = 64 * 1024;  // its dynamic LDS (ring and row symbols), at most
 // Columns per lane of the pipelined combing: up to 32, so that 8 waves cover n
 // (16 for n > 16384).  Each wave's row scan costs about as much as 16 packed
 // columns; fewer, longer waves cut that per row (16384^2 base strips: 16 waves

@@ -52,7 +52,7 @@ __global__ void __launch_bounds__(kCombPipeWaves * kWave) k_comb_pipe(const uint
                                                                        int32_t nstrips, int32_t hlast,
                                                                        int32_t *comb, int32_t cstride,
                                                                        int32_t *err) {
-    __shared__ int32_t lds[(kCombPipeWaves + 1) * kCombMaxRows];
+    extern __shared__ int32_t lds[];  // (waves + 1) x h0 int32
     const int32_t s = blockIdx.x;
     const int32_t h = (s == nstrips - 1) ? hlast : h0;
     int32_t *cs = comb + (size_t)s * (size_t)cstride;
@@ -293,7 +293,7 @@ __global__ void __launch_bounds__(kWave) k_trace_leaf(const uint8_t *a, int32_t 
                                wcap, err, lds, tab, kLeafTab);
 }
 
-// Base strips of 128 to 512 rows (Ew K = 2, 4, 8 registers of columns): K
+// Base strips of 128 to 1024 rows (Ew K = 2, 4, 8, 16 registers of columns): K
 // waves per strip.
 template <int Ew, int K>
 __global__ void __launch_bounds__(K * kWave) k_trace_leaf_pipe(const uint8_t *a, int32_t n,
@@ -405,20 +405,23 @@ hipError_t launch_base_comb(int32_t h0, const uint8_t *a, const uint8_t *b, int3
     // and several tiles.
     const int32_t C = comb_cols(n);
     const int32_t thr = comb_threads(n, C);
-    if (n <= kCombPackedMaxN && n >= 1) {  // the wave pipeline
-        const int32_t cp = comb_pipe_cols(n);
-        const dim3 blk((unsigned)(kWave * ((n + kWave * cp - 1) / (kWave * cp))));
+    // the wave pipeline: labels in 16 bits, its ring and row symbols in 64 KB of LDS
+    const int32_t cp = comb_pipe_cols(n);
+    const int32_t waves = (n + kWave * cp - 1) / (kWave * cp);
+    const size_t bytes = 4 * (size_t)(waves + 1) * (size_t)h0;
+    if (n >= 1 && n <= kCombPackedMaxN && bytes <= kCombPipeMaxLds) {
+        const dim3 blk((unsigned)(kWave * waves));
         if (cp == 4)
-            hipLaunchKernelGGL((k_comb_pipe<4>), dim3(nstrips), blk, 0, s, a, b, n, sigma, h0, nstrips,
+            hipLaunchKernelGGL((k_comb_pipe<4>), dim3(nstrips), blk, bytes, s, a, b, n, sigma, h0, nstrips,
                                hlast, comb, comb_stride, err);
         else if (cp == 8)
-            hipLaunchKernelGGL((k_comb_pipe<8>), dim3(nstrips), blk, 0, s, a, b, n, sigma, h0, nstrips,
+            hipLaunchKernelGGL((k_comb_pipe<8>), dim3(nstrips), blk, bytes, s, a, b, n, sigma, h0, nstrips,
                                hlast, comb, comb_stride, err);
         else if (cp == 16)
-            hipLaunchKernelGGL((k_comb_pipe<16>), dim3(nstrips), blk, 0, s, a, b, n, sigma, h0, nstrips,
+            hipLaunchKernelGGL((k_comb_pipe<16>), dim3(nstrips), blk, bytes, s, a, b, n, sigma, h0, nstrips,
                                hlast, comb, comb_stride, err);
         else
-            hipLaunchKernelGGL((k_comb_pipe<32>), dim3(nstrips), blk, 0, s, a, b, n, sigma, h0, nstrips,
+            hipLaunchKernelGGL((k_comb_pipe<32>), dim3(nstrips), blk, bytes, s, a, b, n, sigma, h0, nstrips,
                                hlast, comb, comb_stride, err);
     } else if (n > kCombPackedMaxN)
         hipLaunchKernelGGL((k_comb<kCombMaxThreads, 16, false>), dim3(nstrips), dim3(thr), 0, s, a, b, n,
@@ -440,8 +443,8 @@ hipError_t launch_base_comb(int32_t h0, const uint8_t *a, const uint8_t *b, int3
     int32_t chunk = 256;
     while (chunk > 32 && (int64_t)nstrips * ((n + 2 + chunk - 1) / chunk) < 16384) chunk /= 2;
     const int32_t nchunks = (n + 2 + chunk - 1) / chunk;
-    const int64_t waves = (int64_t)nstrips * nchunks;
-    const dim3 grid((uint32_t)((waves + kWaves - 1) / kWaves));
+    const int64_t runs = (int64_t)nstrips * nchunks;  // one wave each
+    const dim3 grid((uint32_t)((runs + kWaves - 1) / kWaves));
     if (h0 <= kWave)
         hipLaunchKernelGGL((k_dgen<1>), grid, dim3(kBlock), 0, s, comb, comb_stride, n, h0, nstrips,
                            hlast, base0, last, chunk, nchunks);
@@ -451,8 +454,11 @@ hipError_t launch_base_comb(int32_t h0, const uint8_t *a, const uint8_t *b, int3
     else if (h0 <= 4 * kWave)
         hipLaunchKernelGGL((k_dgen<4>), grid, dim3(kBlock), 0, s, comb, comb_stride, n, h0, nstrips,
                            hlast, base0, last, chunk, nchunks);
-    else
+    else if (h0 <= 8 * kWave)
         hipLaunchKernelGGL((k_dgen<8>), grid, dim3(kBlock), 0, s, comb, comb_stride, n, h0, nstrips,
+                           hlast, base0, last, chunk, nchunks);
+    else
+        hipLaunchKernelGGL((k_dgen<16>), grid, dim3(kBlock), 0, s, comb, comb_stride, n, h0, nstrips,
                            hlast, base0, last, chunk, nchunks);
     return hipGetLastError();
 }
@@ -620,6 +626,11 @@ hipError_t launch_trace_leaf(int32_t h0, const uint8_t *a, int32_t n, int32_t si
             break;
         case 512:
             hipLaunchKernelGGL((k_trace_leaf_pipe<2, 4>), dim3(nstrips), dim3(4 * kWave), 4 * (size_t)tabcap,
+                               s, a, n, sigma, nm, h0, nstrips, hlast, nodes, a_idx, b_idx, wcap, err,
+                               tabcap, leaf, leaf_stride);
+            break;
+        case 1024:
+            hipLaunchKernelGGL((k_trace_leaf_pipe<4, 4>), dim3(nstrips), dim3(4 * kWave), 4 * (size_t)tabcap,
                                s, a, n, sigma, nm, h0, nstrips, hlast, nodes, a_idx, b_idx, wcap, err,
                                tabcap, leaf, leaf_stride);
             break;

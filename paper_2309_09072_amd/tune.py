@@ -1,7 +1,7 @@
 """Autotuner for the tile shapes of the strip recursion.
 
 Two shape parameters change the speed but never the result (every choice is
-exact): ``base_rows`` (rows per base strip: 16 to 512 for single pairs and
+exact): ``base_rows`` (rows per base strip: 16 to 1024 for single pairs and
 staged batches, 16/32/64 for the persistent batch modes) and ``tile`` (vertices
 between two anchor searches of a combine, a power of two 4..32).  The tuner
 times each candidate on the GPU through the C ABI (one pair: the whole build
@@ -20,7 +20,7 @@ from dataclasses import dataclass, field
 from typing import Callable, Dict, List, Optional, Sequence, Tuple
 
 BASE_ROWS = (16, 32, 64)                  # persistent batches (row-append base strips)
-PAIR_BASE_ROWS = (16, 32, 64, 128, 256, 512)  # single pairs, staged batches (combed base strips)
+PAIR_BASE_ROWS = (16, 32, 64, 128, 256, 512, 1024)  # single pairs, staged batches (combed)
 TILES = (8, 16, 32)
 DEFAULT = (64, 32)
 

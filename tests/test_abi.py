@@ -36,7 +36,7 @@ def test_status_strings():
 
 @pytest.mark.parametrize("kw", [
     dict(alphabet=0), dict(alphabet=257), dict(base_rows=8), dict(base_rows=48), dict(base_rows=96),
-    dict(base_rows=1024),
+    dict(base_rows=2048),
     dict(tile=3), dict(tile=128), dict(tile=24), dict(max_m=-1), dict(max_n=-5),
 ])
 def test_plan_rejects_bad_descriptors(kw):
@@ -55,17 +55,18 @@ def test_plan_rejects_int32_overflow():
 
 def test_workspace_sizes():
     p = L.Plan(16384, 16384, 20)
-    assert p.base_rows == 512  # the default for this many rows
+    assert p.base_rows == 1024  # the default for this many rows
     # all levels kept: about 4 (n+2) m (1 + log2(m / base_rows)) bytes
     est = 4 * 16386 * 16384 * (1 + math.log2(16384 / p.base_rows))
     assert est < p.workspace_bytes < 1.05 * est
-    for m, n, h in ((100, 100, 64), (4095, 9000, 64), (4096, 4096, 128), (4096, 8191, 128),
-                    (4096, 8192, 256), (8191, 100, 128), (8192, 100, 256), (16384, 100, 512)):
+    for m, n, h in ((100, 100, 64), (4095, 9000, 64), (4096, 4096, 256), (4096, 8191, 256),
+                    (4096, 8192, 512), (8191, 100, 256), (8192, 100, 512), (12287, 100, 512),
+                    (12288, 100, 1024)):
         assert L.Plan(m, n, 4).base_rows == h, (m, n)
     # oriented: rows = the shorter string, columns = the longer
     assert L.Plan(20000, 3000, 4, orient=True).base_rows == 64
-    assert L.Plan(20000, 5000, 4, orient=True).base_rows == 256
-    assert L.Plan(5000, 6000, 4, orient=True).base_rows == 128
+    assert L.Plan(20000, 5000, 4, orient=True).base_rows == 512
+    assert L.Plan(5000, 6000, 4, orient=True).base_rows == 256
     assert L.Plan(100, 100, 4, 32).base_rows == 32
     assert p.workspace_for(16384, 16384) == p.workspace_bytes
     assert p.workspace_for(100, 100) < p.workspace_for(200, 100) < p.workspace_for(200, 200)

@@ -52,12 +52,13 @@ def test_persistent_matches_oracle(base_rows, tile, slots):
 
 
 @pytest.mark.parametrize("base_rows,tile,slots", [(16, 8, 2), (32, 32, 0), (64, 16, 1), (128, 16, 3),
-                                                  (256, 32, 0), (512, 32, 5)])
+                                                  (256, 32, 0), (512, 32, 5), (1024, 16, 0)])
 def test_staged_matches_oracle(base_rows, tile, slots):
     """Staged launches; small slot areas force the pairs into several waves.
-    Base strips of 128 to 512 rows (staged mode only) get pairs long enough
+    Base strips of 128 to 1024 rows (staged mode only) get pairs long enough
     for several strips and combine levels."""
-    batch = mixed_small(60, 50 + base_rows, maxlen=300 if base_rows <= 64 else 1100 if base_rows <= 256 else 1700)
+    batch = mixed_small(60, 50 + base_rows, maxlen=300 if base_rows <= 64 else 1100 if base_rows <= 256 else
+                        1700 if base_rows <= 512 else 2400)
     say("staged", base_rows, tile, slots)
     res = L.run_batch(batch, L.BATCH_STAGED, base_rows, tile, slots)
     check(batch, *res)

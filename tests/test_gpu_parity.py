@@ -67,7 +67,7 @@ def check_against_oracle(a, b, sigma, **kw):
 
 
 @pytest.mark.parametrize("base_rows,tile", [(16, 4), (16, 8), (32, 16), (64, 32), (16, 32), (128, 8),
-                                            (256, 32), (512, 16)])
+                                            (256, 32), (512, 16), (1024, 32)])
 def test_levels_cell_for_cell(base_rows, tile):
     r = np.random.default_rng(100 + base_rows + tile)
     shapes = [(200, 150, 4), (129, 203, 2), (97, 64, 20), (65, 257, 4), (16, 31, 1), (250, 9, 3)]
@@ -75,6 +75,8 @@ def test_levels_cell_for_cell(base_rows, tile):
         shapes += [(700, 333, 4), (530, 260, 20), (257, 1100, 2)]
     if base_rows >= 512:
         shapes += [(1300, 700, 4), (1100, 900, 20)]
+    if base_rows >= 1024:
+        shapes += [(2300, 600, 4), (2100, 1500, 20)]
     for m, n, sig in shapes:
         a = r.integers(0, sig, m).astype(np.uint8)
         b = r.integers(0, sig, n).astype(np.uint8)
@@ -140,7 +142,7 @@ def test_base_strips_alphabet_20():
     p3 = synth.pair_mutated(192, 192, 20, 77, 0.10, 0.05, 0.05)
     b3 = np.concatenate([p3.b, r.integers(0, 20, n - p3.b.size)]).astype(np.uint8)
     for a, b in ((a1, b1), (a1, b2), (p3.a, b3)):
-        for h0 in (16, 32, 64, 128, 256, 512):
+        for h0 in (16, 32, 64, 128, 256, 512, 1024):
             say("alphabet 20 base", h0, b.size)
             Lg, plan, ws = check_against_oracle(a, b, 20, base_rows=h0)
             _base_rows_check(a, b, plan, ws, verts)
@@ -215,7 +217,7 @@ def test_random_shapes_length_and_witness():
         n = int(r.integers(0, 3000))
         if case % 5 == 0:
             m = int(r.integers(0, 70))
-        base_rows = int(r.choice([16, 32, 64, 128, 256, 512]))
+        base_rows = int(r.choice([16, 32, 64, 128, 256, 512, 1024]))
         tile = int(r.choice([4, 8, 16, 32]))
         a = r.integers(0, sig, m).astype(np.uint8)
         if case % 3 == 0 and m > 0:
