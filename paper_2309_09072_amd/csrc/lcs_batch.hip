@@ -703,7 +703,7 @@ static hipError_t launch_stage(const BatchArgs &A, const StageArgs &S, dim3 grid
             else if (A.base_rows <= 8 * kWave)
                 hipLaunchKernelGGL((k_stage_leaf_tall<2, 4>), grid, dim3(4 * kWave), bytes, st, A, S, tabcap);
             else
-                hipLaunchKernelGGL((k_stage_leaf_tall<4, 4>), grid, dim3(4 * kWave), bytes, st, A, S, tabcap);
+                hipLaunchKernelGGL((k_stage_leaf_tall<2, 8>), grid, dim3(8 * kWave), bytes, st, A, S, tabcap);
             break;
         }
         default: return hipErrorInvalidValue;

@@ -1926,6 +1926,10 @@ __device__ __forceinline__ int32_t leaf_lookup(bool live, int32_t x, int32_t p, 
     const bool far = live && p - s >= W;
     if (__ballot(far) != 0ull) {
         if (far) cd = nm[(size_t)x * (n + 2) + p];
+        // use the value here, so that the wait for this load stays inside the
+        // rare branch: at the merge the counter of vector memory operations also
+        // covers the row stores of the tall leaf, and every row would wait for them
+        asm volatile("" : "+v"(cd));
     }
     return cd;
 }
@@ -2251,14 +2255,20 @@ __device__ void trace_leaf_pipe(const uint8_t *__restrict__ arow, int32_t h, int
                 mlo[e] = (uint32_t)m;
                 mhi[e] = (uint32_t)(m >> 32);
             }
+            // the mask word of weight w only changes when w crosses a multiple of
+            // 32: select it (a dynamic register index) only then
+            int32_t half = -1;
+            uint32_t cur = 0;
             for (int32_t r = imin(h, rb + kWave); r > rb && w >= 1; --r) {
-                const int32_t er = (w - 1) >> 6, bit = (w - 1) & (kWave - 1);
-                uint32_t word = 0;
+                const int32_t hw = (w - 1) >> 5;
+                if (hw != half) {
+                    half = hw;
 #pragma unroll
-                for (int e = 0; e < E; ++e)
-                    if (e == er) word = (uint32_t)__builtin_amdgcn_readlane((int32_t)(bit < 32 ? mlo[e] : mhi[e]),
-                                                                            r - 1 - rb);
-                if ((word >> (bit & 31)) & 1u) {
+                    for (int e = 0; e < E; ++e)
+                        if (e == (hw >> 1)) cur = (hw & 1) ? mhi[e] : mlo[e];
+                }
+                const uint32_t word = (uint32_t)__builtin_amdgcn_readlane((int32_t)cur, r - 1 - rb);
+                if ((word >> ((w - 1) & 31)) & 1u) {
                     if (lane == 0) mrow[w - 1] = r;
                     --w;
                 }

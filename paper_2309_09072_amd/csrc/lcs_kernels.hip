@@ -630,7 +630,7 @@ hipError_t launch_trace_leaf(int32_t h0, const uint8_t *a, int32_t n, int32_t si
                                tabcap, leaf, leaf_stride);
             break;
         case 1024:
-            hipLaunchKernelGGL((k_trace_leaf_pipe<4, 4>), dim3(nstrips), dim3(4 * kWave), 4 * (size_t)tabcap,
+            hipLaunchKernelGGL((k_trace_leaf_pipe<2, 8>), dim3(nstrips), dim3(8 * kWave), 4 * (size_t)tabcap,
                                s, a, n, sigma, nm, h0, nstrips, hlast, nodes, a_idx, b_idx, wcap, err,
                                tabcap, leaf, leaf_stride);
             break;
