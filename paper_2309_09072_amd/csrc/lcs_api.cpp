@@ -171,7 +171,8 @@ int32_t enqueue_build(const Layout &L, uint8_t *ws, const uint8_t *a, const uint
     R.begin(LCS_PHASE_BASE, 0, g0.bytes + L.m);
     e = launch_base_comb(L.h0, a, b, L.n, L.sigma, reinterpret_cast<int32_t *>(ws + g0.base),
                          reinterpret_cast<int32_t *>(ws + g0.last_off), g0.nstrips, g0.hlast,
-                         reinterpret_cast<int32_t *>(ws + L.off_comb), L.comb_stride, hdr, s);
+                         reinterpret_cast<int32_t *>(ws + L.off_comb), L.comb_stride,
+                         reinterpret_cast<int32_t *>(ws + L.off_rec), hdr, s);
     R.end();
     if (e != hipSuccess) return LCS_E_HIP;
     for (size_t l = 1; l < L.lev.size(); ++l) {

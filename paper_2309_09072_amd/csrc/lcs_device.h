@@ -679,6 +679,162 @@ __device__ void comb_strip_pipe(const uint8_t *__restrict__ arow, int32_t h,
     if (__syncthreads_or(stall) && tid == 0) atomicOr(err, kErrTrace);
 }
 
+// One column segment of a strip combed by several work-groups: segment g
+// (columns [c0, c0 + 64 C K) of n, K = blockDim.x / 64 waves, a pipeline as in
+// comb_strip_pipe) takes the labels entering its first column from the
+// records of segment g - 1 and gives the labels leaving its last column to
+// segment g + 1.  A record is one 64-bit word, (row + 1) << 32 | label, so
+// the row tag and the label become visible together (relaxed atomics at
+// device scope; the records are cleared before the launch).  The first wave
+// reads 64 rows' records at a time and polls again only past the last ready
+// one; a wait past kCombSpinLimit polls reports kErrTrace.  Work-group
+// numbers grow with g, so every segment waits only on one dispatched before
+// it.  The last segment writes right[] and the right-side entries of pos[].
+// lds: K x h int32 (ring), then h int32 (row symbols).
+template <int C>
+__device__ void comb_strip_seg(const uint8_t *__restrict__ arow, int32_t h,
+                               const uint8_t *__restrict__ b, int32_t n, int32_t sigma, int32_t c0,
+                               bool first, bool last, const unsigned long long *rec_in,
+                               unsigned long long *rec_out, int32_t *__restrict__ bot,
+                               int32_t *__restrict__ pos, int32_t *__restrict__ right, int32_t *lds,
+                               int32_t *err) {
+    constexpr int32_t P = C / 2;
+    const int32_t tid = threadIdx.x;
+    const int32_t nthr = (int32_t)blockDim.x;
+    const int32_t K = nthr / kWave;
+    const int32_t w = __builtin_amdgcn_readfirstlane(tid / kWave);
+    const int lane = __lane_id();
+    int32_t *ring = lds;
+    int32_t *xs = lds + K * h;
+    bool bad = false;
+    for (int32_t i = tid; i < K * h; i += nthr) ring[i] = kCombSentinel;
+    for (int32_t r = tid; r < h; r += nthr) {
+        xs[r] = arow[r];
+        bad |= xs[r] >= sigma;
+    }
+    uint32_t v2[P], b2[P];
+    const int32_t cb = c0 + tid * C;
+#pragma unroll
+    for (int e = 0; e < P; ++e) {
+        const int32_t cl = cb + e, ch = cb + P + e;
+        const uint32_t vl = (cl < n) ? (uint32_t)cl : 0x7fffu, vh = (ch < n) ? (uint32_t)ch : 0x7fffu;
+        const uint32_t sl = (cl < n) ? (uint32_t)b[cl] : 0x100u, sh = (ch < n) ? (uint32_t)b[ch] : 0x100u;
+        v2[e] = vl | (vh << 16);
+        b2[e] = sl | (sh << 16);
+    }
+    __syncthreads();
+    bool stall = false;
+    int32_t rbase = 0, rready = 0;  // first wave of a later segment: records rbase .. rbase+rready-1 in rwin
+    int32_t rwin = 0;
+    for (int32_t rb = 0; rb < h; rb += kWave) {
+        const int32_t xr = xs[rb + imin(lane, h - 1 - rb)];
+        const int32_t rn = imin(kWave, h - rb);
+        for (int32_t rr = 0; rr < rn; ++rr) {
+            const int32_t r = rb + rr;
+            const uint32_t xx = (uint32_t)__builtin_amdgcn_readlane(xr, rr) * 0x00010001u;
+            uint32_t m2[P];
+            uint32_t fc2 = 0, fv2 = 0x7fff7fffu;
+#pragma unroll
+            for (int e = 0; e < P; ++e) {
+                m2[e] = pk_eq_mask(b2[e], xx);
+                fv2 = bit_select(m2[e], v2[e], pk_min_i16(fv2, v2[e]));
+                fc2 |= m2[e];
+            }
+            const int32_t clo = (fc2 & 0xffffu) != 0, vlo = sext16(fv2);
+            const int32_t chi = (fc2 >> 16) != 0, vhi = (int32_t)fv2 >> 16;
+            int32_t fc = clo | chi, fv = chi ? vhi : imin(vlo, vhi);
+            wave_fn_scan(fc, fv);
+            int32_t xin = -(r + 1);
+            if (w > 0) {
+                const int32_t *slot = ring + (w - 1) * h + r;
+                xin = __builtin_amdgcn_readfirstlane(
+                    __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
+                uint32_t spins = 0;
+                while (xin == kCombSentinel) {
+                    __builtin_amdgcn_s_sleep(1);
+                    if (++spins > kCombSpinLimit) {
+                        stall = true;
+                        xin = 0;
+                        break;
+                    }
+                    xin = __builtin_amdgcn_readfirstlane(
+                        __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
+                }
+            } else if (!first) {
+                if (r >= rbase + rready) {  // (re)load the records from row r on
+                    uint32_t spins = 0;
+                    for (;;) {
+                        unsigned long long v = 0ull;
+                        if (r + lane < h)
+                            v = __hip_atomic_load(rec_in + r + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        const bool ok = (r + lane < h) && (int32_t)(v >> 32) == r + lane + 1;
+                        const unsigned long long mk = __ballot(ok);
+                        const int32_t cnt = (~mk == 0ull) ? kWave : (int32_t)__builtin_ctzll(~mk);  // ready from r on
+                        if (cnt > 0) {
+                            rbase = r;
+                            rready = cnt;
+                            rwin = (int32_t)(uint32_t)v;
+                            break;
+                        }
+                        __builtin_amdgcn_s_sleep(2);
+                        if (++spins > kCombSpinLimit) {
+                            stall = true;
+                            rbase = r;
+                            rready = h;
+                            rwin = 0;
+                            break;
+                        }
+                    }
+                }
+                xin = __builtin_amdgcn_readlane(rwin, r - rbase);
+            }
+            const int32_t xl = fc ? fv : imin(xin, fv);
+            const int32_t xout = __builtin_amdgcn_readlane(xl, kWave - 1);
+            if (lane == 0) {
+                if (w < K - 1 || last)
+                    __hip_atomic_store(ring + w * h + r, xout, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                else
+                    __hip_atomic_store(rec_out + r, ((unsigned long long)(uint32_t)(r + 1) << 32) | (uint32_t)xout,
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            const int32_t hh = __builtin_amdgcn_update_dpp(xin, xl, 0x138, 0xF, 0xF, false);
+            const int32_t hhi = clo ? vlo : imin(hh, vlo);
+            uint32_t h2 = ((uint32_t)hh & 0xffffu) | ((uint32_t)hhi << 16);
+#pragma unroll
+            for (int e = 0; e < P; ++e) {
+                const uint32_t y = v2[e];
+                const uint32_t lo = pk_min_i16(h2, y), hi = pk_max_i16(h2, y);
+                v2[e] = bit_select(m2[e], h2, hi);
+                h2 = bit_select(m2[e], y, lo);
+            }
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < P; ++e) {
+        const int32_t cl = cb + e, ch = cb + P + e;
+        const int32_t ll = sext16(v2[e]), lh = (int32_t)v2[e] >> 16;
+        if (cl < n) {
+            bot[cl] = ll;
+            if (ll >= 0) pos[ll] = cl;
+        }
+        if (ch < n) {
+            bot[ch] = lh;
+            if (lh >= 0) pos[lh] = ch;
+        }
+    }
+    __syncthreads();
+    if (last) {
+        for (int32_t r = tid; r < h; r += nthr) {
+            const int32_t lab = ring[(K - 1) * h + r];
+            right[r] = lab;
+            if (lab >= 0) pos[lab] = n + 1;
+        }
+    }
+    if (__syncthreads_or(bad && first) && tid == 0) atomicOr(err, kErrSymbol);
+    if (__syncthreads_or(stall) && tid == 0) atomicOr(err, kErrTrace);
+}
+
+
 
 // Breakout rows of vertices i0 .. i1-1 of one base strip (h rows) from its
 // combing, by one wave; vertex n + 1 is the all-unreachable sentinel row.

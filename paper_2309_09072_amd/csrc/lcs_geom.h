@@ -75,6 +75,16 @@ struct StripRef {
 
 LCS_HD size_t strip_elems(int32_t n, int32_t h) { return (size_t)(n + 2) * (size_t)(h + 1); }
 
+// Column segments (work-groups) per strip for the combing of a single pair's
+// base strips: several when the strips are tall and few (then one work-group
+// per strip would leave most of the chip idle), each 1024 columns (two waves
+// of 8 packed columns per lane); 1 otherwise.
+LCS_HD int32_t comb_segments(int32_t n, int32_t nstrips, int32_t h0) {
+    if (h0 < 512 || n < 4096 || n > 32767 || nstrips * 8 > 256) return 1;
+    const int32_t g = (n + 1023) / 1024;
+    return g < 32 ? g : 32;
+}
+
 // Scratch of the trace inside one base strip of h0 > 64 rows (E = h0 / 64
 // registers of columns): the match masks of every row (h0 E u64), then the
 // row values D_r(s, 1..64 E) of every row r = 1..h0 (int32); 0 for h0 <= 64.

@@ -59,6 +59,24 @@ __global__ void __launch_bounds__(kCombPipeWaves * kWave) k_comb_pipe(const uint
     comb_strip_pipe<C>(a + (size_t)s * h0, h, b, n, sigma, cs, cs + n, cs + 2 * (size_t)n, lds, err);
 }
 
+// The same split into G column segments per strip, one work-group (two waves)
+// each; work-group s G + g is segment g of strip s, so a segment's
+// predecessor is always dispatched before it.
+template <int C>
+__global__ void __launch_bounds__(2 * kWave) k_comb_seg(const uint8_t *a, const uint8_t *b, int32_t n,
+                                                        int32_t sigma, int32_t h0, int32_t nstrips,
+                                                        int32_t hlast, int32_t *comb, int32_t cstride,
+                                                        unsigned long long *rec, int32_t G, int32_t *err) {
+    extern __shared__ int32_t lds[];  // 3 x h0 int32
+    const int32_t s = (int32_t)blockIdx.x / G, g = (int32_t)blockIdx.x - s * G;
+    const int32_t h = (s == nstrips - 1) ? hlast : h0;
+    int32_t *cs = comb + (size_t)s * (size_t)cstride;
+    unsigned long long *rs = rec + (size_t)s * (size_t)(G - 1) * (size_t)h0;
+    comb_strip_seg<C>(a + (size_t)s * h0, h, b, n, sigma, g * 2 * kWave * C, g == 0, g == G - 1,
+                      g > 0 ? rs + (size_t)(g - 1) * h0 : nullptr, g < G - 1 ? rs + (size_t)g * h0 : nullptr,
+                      cs, cs + n, cs + 2 * (size_t)n, lds, err);
+}
+
 // Breakout rows of every base strip from its combing: one wave per run of
 // `chunk` consecutive vertices of one strip (runs of a strip on one XCD).
 template <int E>
@@ -395,9 +413,10 @@ hipError_t launch_base(int32_t h0, const uint8_t *a, int32_t n, int32_t sigma, c
 
 hipError_t launch_base_comb(int32_t h0, const uint8_t *a, const uint8_t *b, int32_t n,
                             int32_t sigma, int32_t *base0, int32_t *last, int32_t nstrips,
-                            int32_t hlast, int32_t *comb, int32_t comb_stride, int32_t *err,
-                            hipStream_t s) {
+                            int32_t hlast, int32_t *comb, int32_t comb_stride, int32_t *rec,
+                            int32_t *err, hipStream_t s) {
     if (h0 < 1 || h0 > kCombMaxRows) return hipErrorInvalidValue;
+    const int32_t G = comb_segments(n, nstrips, h0);
     // Columns per thread: the row's scan over the threads costs about as much
     // per thread as 16 packed columns, so a work-group of ~512 threads (two
     // waves per SIMD) with up to 32 columns each; labels fit 16 bits up to
@@ -409,7 +428,13 @@ hipError_t launch_base_comb(int32_t h0, const uint8_t *a, const uint8_t *b, int3
     const int32_t cp = comb_pipe_cols(n);
     const int32_t waves = (n + kWave * cp - 1) / (kWave * cp);
     const size_t bytes = 4 * (size_t)(waves + 1) * (size_t)h0;
-    if (n >= 1 && n <= kCombPackedMaxN && bytes <= kCombPipeMaxLds) {
+    if (G > 1) {  // tall, few strips: several work-groups per strip (records cleared first)
+        const hipError_t e = launch_clear(rec, 2 * nstrips * (G - 1) * h0, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_comb_seg<8>), dim3((unsigned)(nstrips * G)), dim3(2 * kWave),
+                           12 * (size_t)h0, s, a, b, n, sigma, h0, nstrips, hlast, comb, comb_stride,
+                           reinterpret_cast<unsigned long long *>(rec), G, err);
+    } else if (n >= 1 && n <= kCombPackedMaxN && bytes <= kCombPipeMaxLds) {
         const dim3 blk((unsigned)(kWave * waves));
         if (cp == 4)
             hipLaunchKernelGGL((k_comb_pipe<4>), dim3(nstrips), blk, bytes, s, a, b, n, sigma, h0, nstrips,

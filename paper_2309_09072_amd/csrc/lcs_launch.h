@@ -15,8 +15,8 @@ hipError_t launch_base(int32_t h0, const uint8_t *a, int32_t n, int32_t sigma, c
                        hipStream_t s);
 hipError_t launch_base_comb(int32_t h0, const uint8_t *a, const uint8_t *b, int32_t n,
                             int32_t sigma, int32_t *base0, int32_t *last, int32_t nstrips,
-                            int32_t hlast, int32_t *comb, int32_t comb_stride, int32_t *err,
-                            hipStream_t s);
+                            int32_t hlast, int32_t *comb, int32_t comb_stride, int32_t *rec,
+                            int32_t *err, hipStream_t s);
 hipError_t launch_anchor(const CombineArgs &c, int32_t npairs, hipStream_t s);
 hipError_t launch_bracket(const CombineArgs &c, int32_t npairs, hipStream_t s);
 hipError_t launch_length(const int32_t *top, int32_t m, int32_t n, int32_t *hdr, int4 *root,

@@ -24,6 +24,8 @@ struct Layout {
     int64_t off_rev = -1;  // reversed strings of an oriented build (rows, then columns)
     int64_t off_comb = 0;  // per base strip: the combed seaweeds (bot[n], pos[n], right[h0])
     int32_t comb_stride = 0;  // int32 per base strip in that region
+    int64_t off_rec = 0;      // segment hand-off records of the combing (u64), and their
+    int32_t rec_words = 0;    // size in int32 words (cleared before every combing)
     int64_t off_leaf = 0;     // per base strip of more than 64 rows: the trace leaf's
     int64_t leaf_stride = 0;  // match masks and rows (leaf_scratch_bytes), 0 otherwise
     int32_t nanch = 0;
@@ -63,6 +65,12 @@ inline bool make_layout(int32_t m, int32_t n, int32_t sigma, int32_t h0, int32_t
         L.comb_stride = (2 * n + h0 + 63) & ~63;
         L.off_comb = off;
         off = align256(off + 4 * (int64_t)g.nstrips * L.comb_stride);
+        {
+            const int32_t G = comb_segments(n, g.nstrips, h0);
+            L.rec_words = 2 * g.nstrips * (G - 1) * h0;
+            L.off_rec = off;
+            off = align256(off + 4 * (int64_t)L.rec_words);
+        }
         L.leaf_stride = leaf_scratch_bytes(h0);
         L.off_leaf = off;
         off = align256(off + (int64_t)g.nstrips * L.leaf_stride);
