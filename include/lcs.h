@@ -75,9 +75,9 @@ typedef struct lcs_plan_desc {
                           base_rows rows): 16, 32, 64, 128, 256, 512 or 1024;
                           0 selects by the sizes built (rows = max_m and
                           columns = max_n, or the shorter and longer of the two
-                          with LCS_PLAN_ORIENT): 1024 from 12288 rows, 512 from
-                          8192 rows or from 4096 rows with 8192 columns, 256
-                          from 4096 rows, else 64 */
+                          with LCS_PLAN_ORIENT): 1024 from 8192 rows, 512 from
+                          4096 rows with 8192 columns, 256 from 4096 rows, else
+                          64 */
     int32_t tile;      /* vertices per search tile of the combine: power of two
                           in 4..32; 0 selects the default (32) */
     uint32_t flags;    /* 0 or an OR of LCS_PLAN_PROFILE, LCS_PLAN_ORIENT */

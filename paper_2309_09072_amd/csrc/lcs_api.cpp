@@ -238,16 +238,16 @@ extern "C" int32_t lcs_plan(const lcs_plan_desc *desc, lcs_plan_t *out, size_t *
     *out = nullptr;
     lcs_plan_desc d = *desc;
     if (d.base_rows == 0) {
-        // Taller base strips replace combine levels; the combing of a strip is
-        // one work-group and the trace inside it is a chain of its rows, so they
-        // pay once there are rows for many strips (measured on MI355X, random
-        // strings: 64 rows up to 2048 x 2048, 256 at 4096 x 4096, 512 at
-        // 8192 x 8192 and 4096 x 16384, 1024 from 12000 x 12000).
+        // Taller base strips replace combine levels; the trace inside a strip is
+        // a chain of its rows, so they pay once there are rows for many strips
+        // (measured on MI355X: 64 rows up to 2048 x 2048, 256 at 4096 x 4096,
+        // 512 at 4096 x 16384, 512 and 1024 equal at 8192 x 8192, 1024 from
+        // 12000 x 12000).
         const bool orient = (d.flags & LCS_PLAN_ORIENT) != 0;
         const int32_t rows = orient ? std::min(d.max_m, d.max_n) : d.max_m;
         const int32_t cols = orient ? std::max(d.max_m, d.max_n) : d.max_n;
-        d.base_rows = rows >= 12288                                      ? 1024
-                      : (rows >= 8192 || (rows >= 4096 && cols >= 8192)) ? 512
+        d.base_rows = rows >= 8192                                       ? 1024
+                      : (rows >= 4096 && cols >= 8192)                   ? 512
                       : rows >= 4096                                     ? 256
                                                                          : kDefaultBaseRows;
     }
