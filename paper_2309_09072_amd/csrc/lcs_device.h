@@ -1097,18 +1097,22 @@ __device__ __forceinline__ int32_t block_exclusive_sum(int32_t v, int32_t *wsum,
     return before + incl - v;
 }
 
-template <bool kLds>
+template <bool kLds, typename KT>
 __device__ __forceinline__ int32_t anchor_u(const int32_t *__restrict__ U, uint32_t urow,
-                                            const int32_t *us, int32_t k, int32_t n) {
-    if (kLds) return us[k];
+                                            const KT *us, int32_t k, int32_t n) {
+    if (kLds) return (int32_t)us[k];
     return umin(ld_cell(U, urow + (uint32_t)k), n + 1);
 }
 
-template <bool kLds, int NT, int CPT>
+// kLds: the vertex's D_U row and k* row live in LDS (us, ks), as int32 or,
+// with KT = uint16_t (n + 1 <= 65535 and hU <= 65533), as 16-bit values with
+// k* stored as k* + 1, so that -1 is 0: half the LDS per work-group.
+template <bool kLds, int NT, int CPT, typename KT = int32_t>
 __device__ __forceinline__ void anchor_block_t(const int32_t *__restrict__ U, int32_t hU,
                                const int32_t *__restrict__ L, int32_t hL, int32_t *__restrict__ G,
                                int32_t n, int32_t vtx, int32_t *__restrict__ Krow,
-                               AnchorSmem<NT, CPT> &sm, int32_t *us, int32_t *ks) {
+                               AnchorSmem<NT, CPT> &sm, KT *us, KT *ks) {
+    static_assert(sizeof(KT) == 4 || kLds, "16-bit rows are LDS rows");
     constexpr int32_t CM = AnchorSmem<NT, CPT>::kCols;
     const int32_t tid = anchor_tid<NT>();
     const int32_t INF = n + 1;
@@ -1117,7 +1121,20 @@ __device__ __forceinline__ void anchor_block_t(const int32_t *__restrict__ U, in
     while (P < H + 1) P <<= 1;
     const uint32_t urow = (uint32_t)vtx * (uint32_t)(hU + 1);
     int32_t *__restrict__ grow = G + (size_t)vtx * (size_t)H;
-    int32_t *krow = kLds ? ks : Krow;
+    auto kget = [&](int32_t c) -> int32_t {
+        if constexpr (!kLds)
+            return Krow[c];
+        else if constexpr (sizeof(KT) == 2)
+            return (int32_t)ks[c] - 1;
+        else
+            return ks[c];
+    };
+    auto kput = [&](int32_t c, int32_t k) {
+        if constexpr (!kLds)
+            Krow[c] = k;
+        else
+            ks[c] = (KT)(sizeof(KT) == 2 ? k + 1 : k);
+    };
     const int32_t ldL = hL + 1;
     if (tid == 0) sm.ku = -1;
     anchor_sync<NT>();
@@ -1125,7 +1142,7 @@ __device__ __forceinline__ void anchor_block_t(const int32_t *__restrict__ U, in
     for (int32_t k = tid; k <= hU; k += NT) {
         const int32_t x = umin(ld_cell(U, urow + (uint32_t)k), INF);
         const int32_t xn = (k < hU) ? umin(ld_cell(U, urow + (uint32_t)k + 1u), INF) : INF;
-        if (kLds) us[k] = x;
+        if (kLds) us[k] = (KT)x;
         if (x <= n && xn > n) sm.ku = k;
     }
     anchor_sync<NT>();
@@ -1155,11 +1172,11 @@ __device__ __forceinline__ void anchor_block_t(const int32_t *__restrict__ U, in
                     int32_t kl = 0, kr = hU;
                     bool dead = false;
                     if (cl >= 0) {
-                        kl = krow[cl];
+                        kl = kget(cl);
                         dead = kl < 0;
                     }
                     if (cr < H) {
-                        const int32_t t2 = krow[cr];
+                        const int32_t t2 = kget(cr);
                         if (t2 >= 0) kr = t2;
                     }
                     lo = imax(kl, imax(c - hL, 0));
@@ -1167,7 +1184,7 @@ __device__ __forceinline__ void anchor_block_t(const int32_t *__restrict__ U, in
                     if (!dead && lo <= hi) {
                         r[u] = hi - lo + 1;
                     } else {
-                        krow[c] = -1;
+                        kput(c, -1);
                         grow[c] = INF;
                     }
                 }
@@ -1217,7 +1234,7 @@ __device__ __forceinline__ void anchor_block_t(const int32_t *__restrict__ U, in
                         kk[t] = clo + (ee - cbeg);
                     }
 #pragma unroll
-                    for (int t = 0; t < kBatch; ++t) xs[t] = anchor_u<kLds>(U, urow, us, kk[t], n);
+                    for (int t = 0; t < kBatch; ++t) xs[t] = anchor_u<kLds, KT>(U, urow, us, kk[t], n);
 #pragma unroll
                     for (int t = 0; t < kBatch; ++t) {
                         const int32_t c = (seg + cix[t] + 1) * S2 - 1;
@@ -1249,10 +1266,10 @@ __device__ __forceinline__ void anchor_block_t(const int32_t *__restrict__ U, in
                     const unsigned long long key = sm.key[idx];
                     const uint32_t v = (uint32_t)(key >> 32);
                     if (v <= (uint32_t)n) {
-                        krow[c] = (int32_t)(uint32_t)(key & 0xffffffffull);
+                        kput(c, (int32_t)(uint32_t)(key & 0xffffffffull));
                         grow[c] = (int32_t)v;
                     } else {
-                        krow[c] = -1;
+                        kput(c, -1);
                         grow[c] = INF;
                     }
                 }
@@ -1262,7 +1279,7 @@ __device__ __forceinline__ void anchor_block_t(const int32_t *__restrict__ U, in
         S = S2;
     }
     if (kLds) {
-        for (int32_t c = tid; c < H; c += NT) Krow[c] = ks[c];
+        for (int32_t c = tid; c < H; c += NT) Krow[c] = kget(c);
         anchor_sync<NT>();
     }
 }
@@ -1273,7 +1290,7 @@ __device__ __forceinline__ void anchor_block(const int32_t *__restrict__ U, int3
                                              const int32_t *__restrict__ L, int32_t hL,
                                              int32_t *__restrict__ G, int32_t n, int32_t vtx,
                                              int32_t *__restrict__ Krow, AnchorSmemBlock &sm) {
-    anchor_block_t<false, kBlock, 4>(U, hU, L, hL, G, n, vtx, Krow, sm, nullptr, nullptr);
+    anchor_block_t<false, kBlock, 4, int32_t>(U, hU, L, hL, G, n, vtx, Krow, sm, nullptr, nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -1724,7 +1741,7 @@ __device__ __forceinline__ void bracket_levels(BracketSmemT<C> &sm, const int32_
         const int32_t nitems = nv * S;
         if (threadIdx.x == 0) sm.qn[par ^ 1] = 0;  // next level's queue (read after a barrier)
         // first pass: coarse levels spread each window over g threads; the
-        // fine levels (most outputs, narrow windows) take batches of 4
+        // fine levels (most outputs, narrow windows) take small batches
         int32_t b1;
         if (st == 2) {
             b1 = 3;
@@ -1745,8 +1762,11 @@ __device__ __forceinline__ void bracket_levels(BracketSmemT<C> &sm, const int32_
                 bracket_pass1<C, 2, 3, kLds>(sm, U, hU, L, hL, G, n, i0, len, j0, js, half, st,
                                              nitems, par, ubase, eb);
         } else {
-            b1 = 4;
-            bracket_pass1<C, 1, 4, kLds>(sm, U, hU, L, hL, G, n, i0, len, j0, js, half, st, nitems,
+            // one output per thread; its window is at least st + 1 wide.
+            // Batches of 6: with 4, 43% to 70% of this level's outputs went on
+            // to pass 2 in the 2048- to 8192-row combines of the 16384² pair
+            b1 = 6;
+            bracket_pass1<C, 1, 6, kLds>(sm, U, hU, L, hL, G, n, i0, len, j0, js, half, st, nitems,
                                          par, ubase, 0);
         }
         __syncthreads();

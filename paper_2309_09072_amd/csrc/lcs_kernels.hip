@@ -109,8 +109,8 @@ __device__ __forceinline__ int32_t anchor_block_id() {
 }
 
 // Anchor search with the D_U row and the k* row of the vertex in LDS
-// (dynamic: the search's AnchorSmem, then hc + 1 and 2 hc + 1 int32).
-template <int NT, int CPT>
+// (dynamic: the search's AnchorSmem, then hc + 1 and 2 hc + 1 values of KT).
+template <int NT, int CPT, typename KT>
 __global__ void __launch_bounds__(NT) k_anchor_lds(CombineArgs c) {
     extern __shared__ unsigned long long dyn[];
     const int32_t lb = anchor_block_id();
@@ -120,9 +120,9 @@ __global__ void __launch_bounds__(NT) k_anchor_lds(CombineArgs c) {
     const int32_t vtx = anchor_vertex(a, c.tile, c.n);
     int32_t *Krow = c.anch + ((size_t)p * c.nanch + a) * (size_t)c.hs;
     AnchorSmem<NT, CPT> &sm = *reinterpret_cast<AnchorSmem<NT, CPT> *>(dyn);
-    int32_t *us = reinterpret_cast<int32_t *>(dyn + sizeof(AnchorSmem<NT, CPT>) / 8);
-    int32_t *ks = us + (c.hc + 1);
-    anchor_block_t<true, NT, CPT>(U.d, U.h, L.d, L.h, G, c.n, vtx, Krow, sm, us, ks);
+    KT *us = reinterpret_cast<KT *>(dyn + sizeof(AnchorSmem<NT, CPT>) / 8);
+    KT *ks = us + (c.hc + 1);
+    anchor_block_t<true, NT, CPT, KT>(U.d, U.h, L.d, L.h, G, c.n, vtx, Krow, sm, us, ks);
     if (a == c.nanch - 1) {  // sentinel row n + 1
         const int32_t H = U.h + L.h + 1;
         int32_t *srow = G + (size_t)(c.n + 1) * H;
@@ -167,7 +167,7 @@ __global__ void __launch_bounds__(NT) k_anchor(CombineArgs c) {
     int32_t *G = parent_strip(c, p);
     const int32_t vtx = anchor_vertex(a, c.tile, c.n);
     int32_t *Krow = c.anch + ((size_t)p * c.nanch + a) * (size_t)c.hs;
-    anchor_block_t<false, NT, CPT>(U.d, U.h, L.d, L.h, G, c.n, vtx, Krow, sm, nullptr, nullptr);
+    anchor_block_t<false, NT, CPT, int32_t>(U.d, U.h, L.d, L.h, G, c.n, vtx, Krow, sm, nullptr, nullptr);
     if (a == c.nanch - 1) {  // sentinel row n + 1
         const int32_t H = U.h + L.h + 1;
         int32_t *srow = G + (size_t)(c.n + 1) * H;
@@ -506,37 +506,50 @@ static int64_t device_cus() {
 }
 
 // Opt a kernel in to more than 64 KB of dynamic LDS, once per device.
-template <int NT, int CPT>
+template <int NT, int CPT, typename KT>
 static hipError_t opt_in_anchor_lds() {
     static bool opted[64] = {};
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
     if (dev < 0 || dev >= 64 || opted[dev]) return hipSuccess;
-    e = hipFuncSetAttribute((const void *)k_anchor_lds<NT, CPT>,
+    e = hipFuncSetAttribute((const void *)k_anchor_lds<NT, CPT, KT>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxGroupLds);
     if (e != hipSuccess) return e;
     opted[dev] = true;
     return hipSuccess;
 }
 
-template <int NT, int CPT>
-static bool try_anchor_lds(const CombineArgs &c, int32_t npairs, hipStream_t s, hipError_t &e) {
-    const size_t bytes = sizeof(AnchorSmem<NT, CPT>) + 4 * ((size_t)c.hc + 1 + (size_t)c.hs);
+template <int NT, int CPT, typename KT>
+static bool try_anchor_lds_t(const CombineArgs &c, int32_t npairs, hipStream_t s, hipError_t &e) {
+    const size_t bytes = sizeof(AnchorSmem<NT, CPT>) + sizeof(KT) * ((size_t)c.hc + 1 + (size_t)c.hs);
     if (bytes > kMaxGroupLds) return false;
-    e = opt_in_anchor_lds<NT, CPT>();
+    e = opt_in_anchor_lds<NT, CPT, KT>();
     if (e == hipSuccess) {
-        hipLaunchKernelGGL((k_anchor_lds<NT, CPT>), dim3(c.nanch, npairs), dim3(NT), bytes, s, c);
+        hipLaunchKernelGGL((k_anchor_lds<NT, CPT, KT>), dim3(c.nanch, npairs), dim3(NT), bytes, s, c);
         e = hipGetLastError();
     }
     return true;
+}
+
+// 16-bit rows when every value and k* + 1 fits (half the LDS, so more
+// work-groups per CU: the search is bound by dependent depth rounds).
+template <int NT, int CPT>
+static bool try_anchor_lds(const CombineArgs &c, int32_t npairs, hipStream_t s, hipError_t &e) {
+    if (c.n + 1 <= 65535 && c.hc <= 65533) return try_anchor_lds_t<NT, CPT, uint16_t>(c, npairs, s, e);
+    return try_anchor_lds_t<NT, CPT, int32_t>(c, npairs, s, e);
 }
 
 hipError_t launch_anchor(const CombineArgs &c, int32_t npairs, hipStream_t s) {
     // Few anchors (the top levels) get many threads each, so that a depth's
     // candidates take fewer rounds, but never so many that the work-groups
     // stop fitting on the chip at once (one 1024-thread or about three
-    // 512-thread work-groups per CU).
+    // 512-thread work-groups per CU).  The search is bound by dependent
+    // depth rounds, so LDS per work-group sets the speed: below the fewest-
+    // anchor case two columns per thread per segment (half the search state)
+    // let, with 16-bit rows, two 512-thread work-groups share a CU at the
+    // 16384-row top level and 7 to 8 256-thread ones at the 2048-row level
+    // (measured at 16384²: anchors 1.81 -> 1.69 ms per build).
     const int64_t blocks = (int64_t)c.nanch * npairs;
     const int64_t cus = device_cus();
     hipError_t e = hipSuccess;
@@ -547,7 +560,7 @@ hipError_t launch_anchor(const CombineArgs &c, int32_t npairs, hipStream_t s) {
         return hipGetLastError();
     }
     if (blocks <= 3 * cus) {
-        if (try_anchor_lds<512, 4>(c, npairs, s, e)) return e;
+        if (try_anchor_lds<512, 2>(c, npairs, s, e)) return e;
         hipLaunchKernelGGL((k_anchor<512, 4>), dim3(c.nanch, npairs), dim3(512), 0, s, c);
         return hipGetLastError();
     }
@@ -566,7 +579,7 @@ hipError_t launch_anchor(const CombineArgs &c, int32_t npairs, hipStream_t s) {
             hipLaunchKernelGGL((k_anchor_wave<8>), grid, dim3(kBlock), bytes, s, c, per_wave);
         return hipGetLastError();
     }
-    if (try_anchor_lds<kBlock, 4>(c, npairs, s, e)) return e;
+    if (try_anchor_lds<kBlock, 2>(c, npairs, s, e)) return e;
     hipLaunchKernelGGL((k_anchor<kBlock, 4>), dim3(c.nanch, npairs), dim3(kBlock), 0, s, c);
     return hipGetLastError();
 }
@@ -576,13 +589,16 @@ using NarrowBracket = BracketCfg16;
 template <class C, class Mid, class Wide>
 static void launch_bracket_cfg(const CombineArgs &c, dim3 grid, hipStream_t s) {
     // The cooperative pass 2 is compiled only into the kernels for tall
-    // strips, so that the others keep their register allocation.  Strips of
-    // kWideWindowMinH rows and more take the shape with the wider D_U window:
-    // there k* moves further across a block (measured at 4096² and 16384²:
-    // with the narrow window 27% of the top level's live blocks read D_U from
-    // global memory, two round trips per batch), which is worth one
-    // work-group per CU less.
-    if (c.hc >= kWideWindowMinH)
+    // strips, so that the others keep their register allocation.  The top
+    // combine (one parent strip) of strips of kWideWindowMinH rows and more
+    // takes the shape with the wider D_U window: there k* moves furthest
+    // across a block (with the narrow window 27% of the top level's live
+    // blocks read D_U from global memory, two round trips per batch), which
+    // is worth one work-group per CU less.  Below the top the narrow window
+    // still holds about 95% of the live blocks and the eighth work-group per
+    // CU wins (measured at 16384²: 9% less time in the 2048- and 4096-row
+    // combines).
+    if (c.hc >= kWideWindowMinH && grid.y == 1)
         hipLaunchKernelGGL((k_bracket<Wide, true>), grid, dim3(kBlock), 0, s, c);
     else if (c.hc >= kCoopPass2MinH)
         hipLaunchKernelGGL((k_bracket<Mid, true>), grid, dim3(kBlock), 0, s, c);
