@@ -2093,11 +2093,13 @@ __device__ void trace_split_block(const int32_t *__restrict__ U, int32_t hU,
 // the global one sits behind a wave-uniform branch: as the two arms of one
 // select, the compiler merges them into a single flat load, which waits on
 // both memory counters in every row of the dependent chain.
+// The window holds int32 or, when n + 1 <= 65535, 16-bit entries (TT).
+template <typename TT>
 __device__ __forceinline__ int32_t leaf_lookup(bool live, int32_t x, int32_t p, int32_t s, int32_t n,
-                                               const int32_t *tab, int32_t W,
+                                               const TT *tab, int32_t W,
                                                const int32_t *__restrict__ nm) {
     const int32_t q = imin(imax(p - s, 0), W - 1);
-    int32_t cd = tab[(live ? x : 0) * W + q];  // inside the window for every lane
+    int32_t cd = (int32_t)tab[(live ? x : 0) * W + q];  // inside the window for every lane
     if (!live) cd = n + 1;
     const bool far = live && p - s >= W;
     if (__ballot(far) != 0ull) {
@@ -2258,48 +2260,77 @@ __device__ void trace_leaf_block(const uint8_t *__restrict__ arow, int32_t h, in
 // that value for every row in an LDS ring and publishes its progress every
 // kLeafLag rows; wave k runs at least kLeafLag rows behind it (a bounded
 // wait: past kSpinLimit polls the trace reports kErrTrace).
-// LDS: tab (tabcap int32), mrow and xs (64 E int32 each), ring ((K - 1) 64 E
-// int32), sync (K + 2 int32).
-constexpr int32_t kLeafTabTall = 16384;  // next-match entries a tall leaf keeps in LDS, at most
-__host__ __device__ inline int32_t leaf_tab_cap(int32_t sigma, int32_t n) {
+// LDS: tab (tabcap entries of TT: int32, or 16 bits when n + 1 <= 65535, which
+// doubles the window's columns in the same 64 KB: at 16384 columns and 20
+// symbols 1638 columns instead of 819, more than a 1024-row strip's path
+// spans), mrow and xs (64 E int32 each), ring ((K - 1) 64 E int32), sync
+// (K + 2 int32).
+constexpr int32_t kLeafTabTall = 16384;  // int32 next-match entries a tall leaf keeps in LDS, at most
+__host__ __device__ inline int32_t leaf_tab_cap(int32_t sigma, int32_t n, int32_t entry_bytes = 4) {
     const int64_t all = (int64_t)(sigma < 1 ? 1 : sigma) * (n + 2);
-    return all < kLeafTabTall ? (int32_t)all : kLeafTabTall;
+    const int64_t cap = (int64_t)kLeafTabTall * 4 / entry_bytes;
+    return (int32_t)(all < cap ? all : cap);
 }
 constexpr int32_t kLeafLag = 8;
 constexpr uint32_t kLeafSpinLimit = 1u << 22;
 
 // One row append for this wave's Ew registers; carry = D_r(s, jbase), the
-// column left of the wave's first (s for the first wave).
-template <int Ew>
+// column left of the wave's first (s for the first wave).  The row's symbol x
+// is uniform, so the window row x W is too; every register's LDS lookup is
+// issued before one wave-uniform test for lookups past the window (their
+// global reads wait inside that rare branch), so a row costs one LDS round
+// trip whatever Ew.
+template <int Ew, typename TT>
 __device__ __forceinline__ void leaf_row(int32_t (&d)[Ew], int32_t carry, int32_t jbase, int32_t x,
                                          int32_t s, int32_t n, int32_t sigma, int32_t wmax,
-                                         int32_t pmax, const int32_t *tab, int32_t W,
+                                         int32_t pmax, const TT *tab, int32_t W,
                                          const int32_t *__restrict__ nm, unsigned long long (&mk)[Ew]) {
     const int lane = __lane_id();
     const int32_t INF = n + 1;
+    const bool xok = x < sigma;
+    const TT *trow = tab + (xok ? x : 0) * W;
     int32_t p[Ew];  // D_r(s, j - 1): the next lower column, across lanes and registers
 #pragma unroll
     for (int e = 0; e < Ew; ++e) {
         const int32_t c = (e == 0) ? carry : __builtin_amdgcn_readlane(d[e > 0 ? e - 1 : 0], kWave - 1);
         p[e] = __builtin_amdgcn_update_dpp(c, d[e], 0x138, 0xF, 0xF, false);  // wave_shr:1
     }
+    int32_t cd[Ew];
+    bool live[Ew], far[Ew];
+    bool anyfar = false;
 #pragma unroll
     for (int e = 0; e < Ew; ++e) {
         const int32_t j = jbase + e * kWave + lane + 1;
-        const bool live = j <= wmax && x < sigma && p[e] <= pmax;
-        const int32_t cd = leaf_lookup(live, x, p[e], s, n, tab, W, nm);
-        const int32_t dn = umin(d[e], cd);
-        mk[e] = __ballot(live && cd == dn);
+        const int32_t q = p[e] - s;
+        live[e] = j <= wmax && xok && p[e] <= pmax;
+        cd[e] = (int32_t)trow[imin(imax(q, 0), W - 1)];  // inside the window for every lane
+        far[e] = live[e] && q >= W;
+        anyfar |= far[e];
+    }
+    if (__ballot(anyfar) != 0ull) {
+        const int32_t *__restrict__ grow = nm + (size_t)x * (n + 2);
+#pragma unroll
+        for (int e = 0; e < Ew; ++e) {
+            if (far[e]) cd[e] = grow[p[e]];
+            asm volatile("" : "+v"(cd[e]));  // the wait for these loads stays in this branch
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < Ew; ++e) {
+        const int32_t j = jbase + e * kWave + lane + 1;
+        const int32_t c = live[e] ? cd[e] : INF;
+        const int32_t dn = umin(d[e], c);
+        mk[e] = __ballot(live[e] && c == dn);
         d[e] = (j <= wmax) ? dn : INF;
     }
 }
 
-template <int Ew, int K>
+template <int Ew, int K, typename TT>
 __device__ void trace_leaf_pipe(const uint8_t *__restrict__ arow, int32_t h, int32_t n,
                                 int32_t sigma, const int32_t *__restrict__ nm, int4 node,
                                 int32_t row0, int32_t *__restrict__ a_idx,
                                 int32_t *__restrict__ b_idx, int32_t wcap, int32_t *err,
-                                int32_t *tab, int32_t tabcap, uint8_t *scratch, int32_t *mrow,
+                                TT *tab, int32_t tabcap, uint8_t *scratch, int32_t *mrow,
                                 int32_t *xs, int32_t *ring, int32_t *sync) {
     constexpr int32_t E = Ew * K;
     constexpr int32_t RH = E * kWave;  // ring entries per wave boundary (>= h)
@@ -2324,14 +2355,14 @@ __device__ void trace_leaf_pipe(const uint8_t *__restrict__ arow, int32_t h, int
     const int32_t W = imin(imin(eend - s + 1, n + 2 - s), tabcap / imax(sigma, 1));
     for (int32_t x = 0; x < sigma; ++x) {
         const int32_t *src = nm + (size_t)x * (n + 2) + s;
-        int32_t *dst = tab + x * W;
+        TT *dst = tab + x * W;
         for (int32_t c0 = 0; c0 < W; c0 += 8 * NT) {
             int32_t v[8];
 #pragma unroll
             for (int t = 0; t < 8; ++t) v[t] = src[imin(c0 + t * NT + tid, W - 1)];
 #pragma unroll
             for (int t = 0; t < 8; ++t)
-                if (c0 + t * NT + tid < W) dst[c0 + t * NT + tid] = v[t];
+                if (c0 + t * NT + tid < W) dst[c0 + t * NT + tid] = (TT)v[t];
         }
     }
     for (int32_t r = tid; r < E * kWave; r += NT) {
@@ -2393,7 +2424,7 @@ __device__ void trace_leaf_pipe(const uint8_t *__restrict__ arow, int32_t h, int
                 carry = __builtin_amdgcn_readlane(win, r - cbase);
             }
             unsigned long long mk[Ew];
-            leaf_row<Ew>(d, carry, jbase, __builtin_amdgcn_readlane(xr, rr), s, n, sigma, w0, pmax, tab,
+            leaf_row<Ew, TT>(d, carry, jbase, __builtin_amdgcn_readlane(xr, rr), s, n, sigma, w0, pmax, tab,
                          W, nm, mk);
 #pragma unroll
             for (int e = 0; e < Ew; ++e) rows[(size_t)r * RH + jbase + e * kWave + lane] = d[e];

@@ -312,8 +312,8 @@ __global__ void __launch_bounds__(kWave) k_trace_leaf(const uint8_t *a, int32_t 
 }
 
 // Base strips of 128 to 1024 rows (Ew K = 2, 4, 8, 16 registers of columns): K
-// waves per strip.
-template <int Ew, int K>
+// waves per strip; TT: the next-match window's entries.
+template <int Ew, int K, typename TT>
 __global__ void __launch_bounds__(K * kWave) k_trace_leaf_pipe(const uint8_t *a, int32_t n,
                                                                 int32_t sigma, const int32_t *nm,
                                                                 int32_t h0, int32_t nstrips,
@@ -323,12 +323,13 @@ __global__ void __launch_bounds__(K * kWave) k_trace_leaf_pipe(const uint8_t *a,
                                                                 int32_t tabcap, uint8_t *leaf,
                                                                 int64_t leaf_stride) {
     constexpr int E = Ew * K;
-    extern __shared__ int32_t tab[];  // tabcap int32: the next-match window
+    extern __shared__ int32_t dyn_tab[];  // tabcap entries of TT: the next-match window
+    TT *tab = reinterpret_cast<TT *>(dyn_tab);
     __shared__ int32_t mrow[E * kWave], xs[E * kWave];
     __shared__ int32_t ring[(K - 1) * E * kWave], sync[K + 2];
     const int32_t s = blockIdx.x;
     const int32_t h = (s == nstrips - 1) ? hlast : h0;
-    trace_leaf_pipe<Ew, K>(a + (size_t)s * h0, h, n, sigma, nm, nodes[s], s * h0, a_idx, b_idx, wcap,
+    trace_leaf_pipe<Ew, K, TT>(a + (size_t)s * h0, h, n, sigma, nm, nodes[s], s * h0, a_idx, b_idx, wcap,
                            err, tab, tabcap, leaf + (size_t)s * (size_t)leaf_stride, mrow, xs, ring,
                            sync);
 }
@@ -635,13 +636,47 @@ hipError_t launch_trace_splits(const TraceSplitArgs &t, hipStream_t s) {
     return hipGetLastError();
 }
 
+template <typename TT>
+static hipError_t launch_trace_leaf_tall(int32_t h0, const uint8_t *a, int32_t n, int32_t sigma,
+                                         const int32_t *nm, int32_t nstrips, int32_t hlast,
+                                         const int4 *nodes, int32_t *a_idx, int32_t *b_idx,
+                                         int32_t wcap, int32_t *err, uint8_t *leaf,
+                                         int64_t leaf_stride, hipStream_t s) {
+    // the next-match window: no more than the tables hold, so that short
+    // strings leave LDS for more leaves per CU
+    const int32_t tabcap = leaf_tab_cap(sigma, n, (int32_t)sizeof(TT));
+    const size_t bytes = sizeof(TT) * (size_t)tabcap;
+    switch (h0) {
+        case 128:
+            hipLaunchKernelGGL((k_trace_leaf_pipe<1, 2, TT>), dim3(nstrips), dim3(2 * kWave), bytes, s, a, n,
+                               sigma, nm, h0, nstrips, hlast, nodes, a_idx, b_idx, wcap, err, tabcap,
+                               leaf, leaf_stride);
+            break;
+        case 256:
+            hipLaunchKernelGGL((k_trace_leaf_pipe<1, 4, TT>), dim3(nstrips), dim3(4 * kWave), bytes, s, a, n,
+                               sigma, nm, h0, nstrips, hlast, nodes, a_idx, b_idx, wcap, err, tabcap,
+                               leaf, leaf_stride);
+            break;
+        case 512:
+            hipLaunchKernelGGL((k_trace_leaf_pipe<2, 4, TT>), dim3(nstrips), dim3(4 * kWave), bytes, s, a, n,
+                               sigma, nm, h0, nstrips, hlast, nodes, a_idx, b_idx, wcap, err, tabcap,
+                               leaf, leaf_stride);
+            break;
+        case 1024:
+            hipLaunchKernelGGL((k_trace_leaf_pipe<2, 8, TT>), dim3(nstrips), dim3(8 * kWave), bytes, s, a, n,
+                               sigma, nm, h0, nstrips, hlast, nodes, a_idx, b_idx, wcap, err, tabcap,
+                               leaf, leaf_stride);
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_trace_leaf(int32_t h0, const uint8_t *a, int32_t n, int32_t sigma,
                              const int32_t *nm, int32_t nstrips, int32_t hlast, const int4 *nodes,
                              int32_t *a_idx, int32_t *b_idx, int32_t wcap, int32_t *err,
                              uint8_t *leaf, int64_t leaf_stride, hipStream_t s) {
-    // the tall leaves' next-match window: no more than the tables hold, so that
-    // short strings leave LDS for more leaves per CU
-    const int32_t tabcap = leaf_tab_cap(sigma, n);
     switch (h0) {
         case 16:
             hipLaunchKernelGGL(k_trace_leaf<16>, dim3(nstrips), dim3(kWave), 0, s, a, n, sigma, nm,
@@ -656,25 +691,14 @@ hipError_t launch_trace_leaf(int32_t h0, const uint8_t *a, int32_t n, int32_t si
                                nstrips, hlast, nodes, a_idx, b_idx, wcap, err);
             break;
         case 128:
-            hipLaunchKernelGGL((k_trace_leaf_pipe<1, 2>), dim3(nstrips), dim3(2 * kWave), 4 * (size_t)tabcap,
-                               s, a, n, sigma, nm, h0, nstrips, hlast, nodes, a_idx, b_idx, wcap, err,
-                               tabcap, leaf, leaf_stride);
-            break;
         case 256:
-            hipLaunchKernelGGL((k_trace_leaf_pipe<1, 4>), dim3(nstrips), dim3(4 * kWave), 4 * (size_t)tabcap,
-                               s, a, n, sigma, nm, h0, nstrips, hlast, nodes, a_idx, b_idx, wcap, err,
-                               tabcap, leaf, leaf_stride);
-            break;
         case 512:
-            hipLaunchKernelGGL((k_trace_leaf_pipe<2, 4>), dim3(nstrips), dim3(4 * kWave), 4 * (size_t)tabcap,
-                               s, a, n, sigma, nm, h0, nstrips, hlast, nodes, a_idx, b_idx, wcap, err,
-                               tabcap, leaf, leaf_stride);
-            break;
         case 1024:
-            hipLaunchKernelGGL((k_trace_leaf_pipe<2, 8>), dim3(nstrips), dim3(8 * kWave), 4 * (size_t)tabcap,
-                               s, a, n, sigma, nm, h0, nstrips, hlast, nodes, a_idx, b_idx, wcap, err,
-                               tabcap, leaf, leaf_stride);
-            break;
+            if (n + 1 <= 65535)
+                return launch_trace_leaf_tall<uint16_t>(h0, a, n, sigma, nm, nstrips, hlast, nodes, a_idx,
+                                                        b_idx, wcap, err, leaf, leaf_stride, s);
+            return launch_trace_leaf_tall<int32_t>(h0, a, n, sigma, nm, nstrips, hlast, nodes, a_idx,
+                                                   b_idx, wcap, err, leaf, leaf_stride, s);
         default:
             return hipErrorInvalidValue;
     }
