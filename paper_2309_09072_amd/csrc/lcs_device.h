@@ -2374,39 +2374,36 @@ __device__ void trace_leaf_pipe(const uint8_t *__restrict__ arow, int32_t h, int
     int32_t d[Ew];
 #pragma unroll
     for (int e = 0; e < Ew; ++e) d[e] = INF;
-    bool stall = false;
-    int32_t avail = 0, cbase = 0, win = 0;  // lane l of win: ring row cbase + l of the wave to the left
-    // rows go in runs of 64: lane l holds the run's row symbol l, and gathers
-    // the row's match masks and the value for the ring, written out per run
-    // (the ring every kLeafLag rows), so one LDS round trip is left per row
+    int32_t stall = 0;  // wave-uniform
+    int32_t avail = 0;  // rows of the wave to the left published so far (wave-uniform)
+    // Rows go in runs of 64 (lane l holds the run's row symbol l and gathers
+    // row l's match masks, written out per run) and each run in groups of
+    // kLeafLag rows, the same partition in every wave: a wave waits for and
+    // reads the left wave's ring values once per group, and publishes its own
+    // group before appending the group's last row.  Inside a group a row is
+    // straight-line code: the values handed on, the masks and the ring values
+    // are gathered with selects.
     for (int32_t rb = 0; rb < h; rb += kWave) {
         const int32_t xr = xs[rb + lane];
         const int32_t rn = imin(kWave, h - rb);
         uint32_t mlo[Ew], mhi[Ew];
-        int32_t rv = INF;
-        for (int32_t rr = 0; rr < rn; ++rr) {
-            const int32_t r = rb + rr;
-            if (wv < K - 1) {  // D_r(s, last column) for the wave to the right
-                const int32_t last = __builtin_amdgcn_readlane(d[Ew - 1], kWave - 1);
-                if (lane == rr) rv = last;
-                if ((r + 1) % kLeafLag == 0 || r + 1 == h) {
-                    if (lane <= rr) ring[wv * RH + rb + lane] = rv;
-                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-                    if (lane == 0)
-                        __hip_atomic_store(sync + wv, r + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                }
-            }
-            int32_t carry = s;
+#pragma unroll
+        for (int e = 0; e < Ew; ++e) mlo[e] = mhi[e] = 0u;
+        int32_t rv = INF;  // lane l: D_{rb+l}(s, last column of this wave)
+        for (int32_t g0 = 0; g0 < rn; g0 += kLeafLag) {
+            const int32_t r0 = rb + g0;
+            const int32_t gn = imin(kLeafLag, rn - g0);
+            int32_t win = INF;  // lane q < gn: D_{r0+q}(s, jbase) from the wave to the left
             if (wv > 0) {
-                if (r >= avail) {
-                    const int32_t want = imin(r + kLeafLag, h);
+                const int32_t want = r0 + gn;
+                if (avail < want) {
                     int32_t got = __builtin_amdgcn_readfirstlane(
                         __hip_atomic_load(sync + wv - 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
                     uint32_t spins = 0;
                     while (got < want) {
                         __builtin_amdgcn_s_sleep(1);
                         if (++spins > kLeafSpinLimit) {
-                            stall = true;
+                            stall = 1;
                             got = h;
                             break;
                         }
@@ -2414,25 +2411,32 @@ __device__ void trace_leaf_pipe(const uint8_t *__restrict__ arow, int32_t h, int
                             __hip_atomic_load(sync + wv - 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
                     }
                     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-                    avail = got;
-                    cbase = r;
-                    win = (r + lane < h) ? ring[(wv - 1) * RH + r + lane] : INF;
-                } else if (r >= cbase + kWave) {
-                    cbase = r;
-                    win = (r + lane < h) ? ring[(wv - 1) * RH + r + lane] : INF;
+                    avail = __builtin_amdgcn_readfirstlane(got);
                 }
-                carry = __builtin_amdgcn_readlane(win, r - cbase);
+                if (lane < gn) win = ring[(wv - 1) * RH + r0 + lane];
             }
-            unsigned long long mk[Ew];
-            leaf_row<Ew, TT>(d, carry, jbase, __builtin_amdgcn_readlane(xr, rr), s, n, sigma, w0, pmax, tab,
-                         W, nm, mk);
-#pragma unroll
-            for (int e = 0; e < Ew; ++e) rows[(size_t)r * RH + jbase + e * kWave + lane] = d[e];
-            if (lane == rr) {
+            for (int32_t q = 0; q < gn; ++q) {
+                const int32_t r = r0 + q;
+                const int32_t rr = g0 + q;
+                if (wv < K - 1) {  // D_r(s, last column) for the wave to the right
+                    const int32_t last = __builtin_amdgcn_readlane(d[Ew - 1], kWave - 1);
+                    rv = (lane == rr) ? last : rv;
+                    if (q == gn - 1) {
+                        if (lane >= g0 && lane <= rr) ring[wv * RH + rb + lane] = rv;
+                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                        if (lane == 0)
+                            __hip_atomic_store(sync + wv, r + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    }
+                }
+                const int32_t carry = (wv > 0) ? __builtin_amdgcn_readlane(win, q) : s;
+                unsigned long long mk[Ew];
+                leaf_row<Ew, TT>(d, carry, jbase, __builtin_amdgcn_readlane(xr, rr), s, n, sigma, w0,
+                                 pmax, tab, W, nm, mk);
 #pragma unroll
                 for (int e = 0; e < Ew; ++e) {
-                    mlo[e] = (uint32_t)mk[e];
-                    mhi[e] = (uint32_t)(mk[e] >> 32);
+                    rows[(size_t)r * RH + jbase + e * kWave + lane] = d[e];
+                    mlo[e] = (lane == rr) ? (uint32_t)mk[e] : mlo[e];
+                    mhi[e] = (lane == rr) ? (uint32_t)(mk[e] >> 32) : mhi[e];
                 }
             }
         }
@@ -2442,7 +2446,7 @@ __device__ void trace_leaf_pipe(const uint8_t *__restrict__ arow, int32_t h, int
                 masks[(rb + lane) * E + wv * Ew + e] = ((unsigned long long)mhi[e] << 32) | mlo[e];
         }
     }
-    if (stall && lane == 0) atomicOr(err, kErrTrace);
+    if (stall != 0 && lane == 0) atomicOr(err, kErrTrace);
     if (w0 >= 1 && ((w0 - 1) >> 6) / Ew == wv) {  // the wave holding column w0: D_h(s, w0)
         const int32_t er = ((w0 - 1) >> 6) - wv * Ew;
         int32_t v = INF;
