@@ -687,7 +687,12 @@ __device__ void comb_strip_pipe(const uint8_t *__restrict__ arow, int32_t h,
 // the row tag and the label become visible together (relaxed atomics at
 // device scope; the records are cleared before the launch).  The first wave
 // reads 64 rows' records at a time and polls again only past the last ready
-// one; a wait past kCombSpinLimit polls reports kErrTrace.  Work-group
+// one; a wait past kCombSpinLimit polls reports kErrTrace.  The read of the
+// records after a window is issued as soon as the window is taken, so its
+// round trip overlaps the window's rows (a record never changes once tagged,
+// so an early read is exact; rows not yet tagged then are read again): a
+// segment then trails the one before it by a few rows instead of about a
+// window, which is what the fill of the segment pipeline costs.  Work-group
 // numbers grow with g, so every segment waits only on one dispatched before
 // it.  The last segment writes right[] and the right-side entries of pos[].
 // lds: K x h int32 (ring), then h int32 (row symbols).
@@ -726,6 +731,8 @@ __device__ void comb_strip_seg(const uint8_t *__restrict__ arow, int32_t h,
     bool stall = false;
     int32_t rbase = 0, rready = 0;  // first wave of a later segment: records rbase .. rbase+rready-1 in rwin
     int32_t rwin = 0;
+    int32_t pfb = -1;  // first row of the records read ahead into pf (-1: none)
+    unsigned long long pf = 0ull;
     for (int32_t rb = 0; rb < h; rb += kWave) {
         const int32_t xr = xs[rb + imin(lane, h - 1 - rb)];
         const int32_t rn = imin(kWave, h - rb);
@@ -762,8 +769,19 @@ __device__ void comb_strip_seg(const uint8_t *__restrict__ arow, int32_t h,
                 }
             } else if (!first) {
                 if (r >= rbase + rready) {  // (re)load the records from row r on
+                    int32_t cnt0 = 0;
+                    if (pfb == r) {  // the records read ahead
+                        const bool ok = (r + lane < h) && (int32_t)(pf >> 32) == r + lane + 1;
+                        const unsigned long long mk = __ballot(ok);
+                        cnt0 = (~mk == 0ull) ? kWave : (int32_t)__builtin_ctzll(~mk);
+                        if (cnt0 > 0) {
+                            rbase = r;
+                            rready = cnt0;
+                            rwin = (int32_t)(uint32_t)pf;
+                        }
+                    }
                     uint32_t spins = 0;
-                    for (;;) {
+                    while (cnt0 == 0) {
                         unsigned long long v = 0ull;
                         if (r + lane < h)
                             v = __hip_atomic_load(rec_in + r + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -785,6 +803,12 @@ __device__ void comb_strip_seg(const uint8_t *__restrict__ arow, int32_t h,
                             break;
                         }
                     }
+                    // read the next window's records now; they are looked at
+                    // when this window is used up
+                    pfb = rbase + rready;
+                    pf = 0ull;
+                    if (pfb < h && pfb + lane < h)
+                        pf = __hip_atomic_load(rec_in + pfb + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 }
                 xin = __builtin_amdgcn_readlane(rwin, r - rbase);
             }

@@ -59,20 +59,20 @@ __global__ void __launch_bounds__(kCombPipeWaves * kWave) k_comb_pipe(const uint
     comb_strip_pipe<C>(a + (size_t)s * h0, h, b, n, sigma, cs, cs + n, cs + 2 * (size_t)n, lds, err);
 }
 
-// The same split into G column segments per strip, one work-group (two waves)
-// each; work-group s G + g is segment g of strip s, so a segment's
-// predecessor is always dispatched before it.
-template <int C>
-__global__ void __launch_bounds__(2 * kWave) k_comb_seg(const uint8_t *a, const uint8_t *b, int32_t n,
+// The same split into G column segments per strip, one work-group (KW waves of
+// C columns per lane: 64 C KW columns) each; work-group s G + g is segment g
+// of strip s, so a segment's predecessor is always dispatched before it.
+template <int C, int KW>
+__global__ void __launch_bounds__(KW * kWave) k_comb_seg(const uint8_t *a, const uint8_t *b, int32_t n,
                                                         int32_t sigma, int32_t h0, int32_t nstrips,
                                                         int32_t hlast, int32_t *comb, int32_t cstride,
                                                         unsigned long long *rec, int32_t G, int32_t *err) {
-    extern __shared__ int32_t lds[];  // 3 x h0 int32
+    extern __shared__ int32_t lds[];  // (KW + 1) x h0 int32
     const int32_t s = (int32_t)blockIdx.x / G, g = (int32_t)blockIdx.x - s * G;
     const int32_t h = (s == nstrips - 1) ? hlast : h0;
     int32_t *cs = comb + (size_t)s * (size_t)cstride;
     unsigned long long *rs = rec + (size_t)s * (size_t)(G - 1) * (size_t)h0;
-    comb_strip_seg<C>(a + (size_t)s * h0, h, b, n, sigma, g * 2 * kWave * C, g == 0, g == G - 1,
+    comb_strip_seg<C>(a + (size_t)s * h0, h, b, n, sigma, g * KW * kWave * C, g == 0, g == G - 1,
                       g > 0 ? rs + (size_t)(g - 1) * h0 : nullptr, g < G - 1 ? rs + (size_t)g * h0 : nullptr,
                       cs, cs + n, cs + 2 * (size_t)n, lds, err);
 }
@@ -432,9 +432,12 @@ hipError_t launch_base_comb(int32_t h0, const uint8_t *a, const uint8_t *b, int3
     if (G > 1) {  // tall, few strips: several work-groups per strip (records cleared first)
         const hipError_t e = launch_clear(rec, 2 * nstrips * (G - 1) * h0, s);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((k_comb_seg<8>), dim3((unsigned)(nstrips * G)), dim3(2 * kWave),
-                           12 * (size_t)h0, s, a, b, n, sigma, h0, nstrips, hlast, comb, comb_stride,
-                           reinterpret_cast<unsigned long long *>(rec), G, err);
+        // 1024 columns per segment (comb_segments)
+        constexpr int kSegC = 4, kSegW = 4;  // waves x columns per lane, measured at 16384² (base strips with their rows): 2 x 8 0.797, 4 x 4 0.750, 8 x 2 0.787 ms
+        static_assert(kSegC * kSegW * kWave == 1024, "segment width");
+        hipLaunchKernelGGL((k_comb_seg<kSegC, kSegW>), dim3((unsigned)(nstrips * G)), dim3(kSegW * kWave),
+                           4 * (kSegW + 1) * (size_t)h0, s, a, b, n, sigma, h0, nstrips, hlast, comb,
+                           comb_stride, reinterpret_cast<unsigned long long *>(rec), G, err);
     } else if (n >= 1 && n <= kCombPackedMaxN && bytes <= kCombPipeMaxLds) {
         const dim3 blk((unsigned)(kWave * waves));
         if (cp == 4)
