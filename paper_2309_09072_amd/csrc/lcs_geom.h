@@ -78,9 +78,11 @@ LCS_HD size_t strip_elems(int32_t n, int32_t h) { return (size_t)(n + 2) * (size
 // Column segments (work-groups) per strip for the combing of a single pair's
 // base strips: several when the strips are tall and few (then one work-group
 // per strip would leave most of the chip idle), each 1024 columns (four waves
-// of 4 packed columns per lane); 1 otherwise.
+// of 4 packed columns per lane); 1 otherwise.  From 256 rows (4096²: 16
+// strips of 256 rows combed in 0.145 ms with 4 segments each, 0.160 ms with
+// one pipelined work-group per strip).
 LCS_HD int32_t comb_segments(int32_t n, int32_t nstrips, int32_t h0) {
-    if (h0 < 512 || n < 4096 || n > 32767 || nstrips * 8 > 256) return 1;
+    if (h0 < 256 || n < 4096 || n > 32767 || nstrips * 8 > 256) return 1;
     const int32_t g = (n + 1023) / 1024;
     return g < 32 ? g : 32;
 }

@@ -166,9 +166,10 @@ def test_combing_in_column_segments():
     """Tall, few base strips are combed by several work-groups per strip (1024
     columns each), handing the row labels on through records: segment counts
     with a full last segment (4096 columns), a one-column last segment (4097)
-    and a ragged one, alphabets 4 and 20, base strips of 512 and 1024 rows."""
+    and a ragged one, alphabets 4 and 20, base strips of 256, 512 and 1024 rows."""
     r = np.random.default_rng(5150)
-    for m, n, sig, h0 in ((1300, 4096, 4, 512), (2100, 4097, 20, 1024), (1100, 7000, 4, 1024)):
+    for m, n, sig, h0 in ((1300, 4096, 4, 512), (2100, 4097, 20, 1024), (1100, 7000, 4, 1024),
+                          (700, 5000, 4, 256)):
         a = r.integers(0, sig, m).astype(np.uint8)
         b = r.integers(0, sig, n).astype(np.uint8)
         verts = sorted(set(list(range(0, n + 1, 211)) + [1, 1023, 1024, 1025, 2047, 2048, n - 1, n]))
