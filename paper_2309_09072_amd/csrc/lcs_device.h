@@ -2302,19 +2302,20 @@ constexpr uint32_t kLeafSpinLimit = 1u << 22;
 
 // One row append for this wave's Ew registers; carry = D_r(s, jbase), the
 // column left of the wave's first (s for the first wave).  The row's symbol x
-// is uniform, so the window row x W is too; every register's LDS lookup is
-// issued before one wave-uniform test for lookups past the window (their
-// global reads wait inside that rare branch), so a row costs one LDS round
-// trip whatever Ew.
-template <int Ew, typename TT>
+// is uniform, and so is its window row trow (row 0 for a symbol outside the
+// alphabet, xok false: then no lane is live).  Every register's LDS lookup is
+// issued before one wave-uniform test for lookups past the window (kFar:
+// compiled in only when the window can be shorter than the leaf's column
+// range; their global reads wait inside that rare branch), so a row costs one
+// LDS round trip whatever Ew.  A weight above wmax is never live, so its entry
+// stays n + 1 without a select.
+template <int Ew, typename TT, bool kFar>
 __device__ __forceinline__ void leaf_row(int32_t (&d)[Ew], int32_t carry, int32_t jbase, int32_t x,
-                                         int32_t s, int32_t n, int32_t sigma, int32_t wmax,
-                                         int32_t pmax, const TT *tab, int32_t W,
-                                         const int32_t *__restrict__ nm, unsigned long long (&mk)[Ew]) {
+                                         bool xok, const TT *trow, int32_t s, int32_t n, int32_t wmax,
+                                         int32_t pmax, int32_t W, const int32_t *__restrict__ nm,
+                                         unsigned long long (&mk)[Ew]) {
     const int lane = __lane_id();
     const int32_t INF = n + 1;
-    const bool xok = x < sigma;
-    const TT *trow = tab + (xok ? x : 0) * W;
     int32_t p[Ew];  // D_r(s, j - 1): the next lower column, across lanes and registers
 #pragma unroll
     for (int e = 0; e < Ew; ++e) {
@@ -2322,32 +2323,36 @@ __device__ __forceinline__ void leaf_row(int32_t (&d)[Ew], int32_t carry, int32_
         p[e] = __builtin_amdgcn_update_dpp(c, d[e], 0x138, 0xF, 0xF, false);  // wave_shr:1
     }
     int32_t cd[Ew];
-    bool live[Ew], far[Ew];
-    bool anyfar = false;
+    bool live[Ew];
 #pragma unroll
     for (int e = 0; e < Ew; ++e) {
         const int32_t j = jbase + e * kWave + lane + 1;
-        const int32_t q = p[e] - s;
         live[e] = j <= wmax && xok && p[e] <= pmax;
-        cd[e] = (int32_t)trow[imin(imax(q, 0), W - 1)];  // inside the window for every lane
-        far[e] = live[e] && q >= W;
-        anyfar |= far[e];
+        cd[e] = (int32_t)trow[imin(imax(p[e] - s, 0), W - 1)];  // inside the window for every lane
     }
-    if (__ballot(anyfar) != 0ull) {
-        const int32_t *__restrict__ grow = nm + (size_t)x * (n + 2);
+    if constexpr (kFar) {
+        bool far[Ew];
+        bool anyfar = false;
 #pragma unroll
         for (int e = 0; e < Ew; ++e) {
-            if (far[e]) cd[e] = grow[p[e]];
-            asm volatile("" : "+v"(cd[e]));  // the wait for these loads stays in this branch
+            far[e] = live[e] && p[e] - s >= W;
+            anyfar |= far[e];
+        }
+        if (__ballot(anyfar) != 0ull) {
+            const int32_t *__restrict__ grow = nm + (size_t)x * (n + 2);
+#pragma unroll
+            for (int e = 0; e < Ew; ++e) {
+                if (far[e]) cd[e] = grow[p[e]];
+                asm volatile("" : "+v"(cd[e]));  // the wait for these loads stays in this branch
+            }
         }
     }
 #pragma unroll
     for (int e = 0; e < Ew; ++e) {
-        const int32_t j = jbase + e * kWave + lane + 1;
         const int32_t c = live[e] ? cd[e] : INF;
         const int32_t dn = umin(d[e], c);
         mk[e] = __ballot(live[e] && c == dn);
-        d[e] = (j <= wmax) ? dn : INF;
+        d[e] = dn;
     }
 }
 
@@ -2409,9 +2414,14 @@ __device__ void trace_leaf_pipe(const uint8_t *__restrict__ arow, int32_t h, int
     // group before appending the group's last row.  Inside a group a row is
     // straight-line code: the values handed on, the masks and the ring values
     // are gathered with selects.
+    // lookups past the window only when it can be shorter than the columns
+    // the leaf reads (pmax - s + 1 of them)
+    const bool need_far = W < pmax - s + 1;
     for (int32_t rb = 0; rb < h; rb += kWave) {
         const int32_t xr = xs[rb + lane];
         const int32_t rn = imin(kWave, h - rb);
+        const unsigned long long xokm = __ballot(xr < sigma);  // bit l: row rb + l's symbol is valid
+        const int32_t xo = (xr < sigma ? xr : 0) * W;          // its window row
         uint32_t mlo[Ew], mhi[Ew];
 #pragma unroll
         for (int e = 0; e < Ew; ++e) mlo[e] = mhi[e] = 0u;
@@ -2456,8 +2466,13 @@ __device__ void trace_leaf_pipe(const uint8_t *__restrict__ arow, int32_t h, int
                 }
                 const int32_t carry = (wv > 0) ? __builtin_amdgcn_readlane(win, q) : s;
                 unsigned long long mk[Ew];
-                leaf_row<Ew, TT>(d, carry, jbase, __builtin_amdgcn_readlane(xr, rr), s, n, sigma, w0,
-                                 pmax, tab, W, nm, mk);
+                const int32_t x = __builtin_amdgcn_readlane(xr, rr);
+                const bool xok = (xokm >> rr) & 1ull;
+                const TT *trow = tab + __builtin_amdgcn_readlane(xo, rr);
+                if (need_far)
+                    leaf_row<Ew, TT, true>(d, carry, jbase, x, xok, trow, s, n, w0, pmax, W, nm, mk);
+                else
+                    leaf_row<Ew, TT, false>(d, carry, jbase, x, xok, trow, s, n, w0, pmax, W, nm, mk);
 #pragma unroll
                 for (int e = 0; e < Ew; ++e) {
                     rows[(size_t)r * RH + jbase + e * kWave + lane] = d[e];
