@@ -563,7 +563,11 @@ hipError_t launch_anchor(const CombineArgs &c, int32_t npairs, hipStream_t s) {
         hipLaunchKernelGGL((k_anchor<1024, 2>), dim3(c.nanch, npairs), dim3(1024), 0, s, c);
         return hipGetLastError();
     }
-    if (blocks <= 3 * cus) {
+    // 512 threads up to three work-groups per CU, and for long rows up to
+    // five (16384², the 4096-row level's 1026 anchors of 8193 weights: 0.42
+    // -> 0.39 ms; short rows lose: 4096², 1032 anchors of 513 weights: 0.029
+    // -> 0.038 ms)
+    if (blocks <= 3 * cus || (blocks <= 5 * cus && c.hs > 2048)) {
         if (try_anchor_lds<512, 2>(c, npairs, s, e)) return e;
         hipLaunchKernelGGL((k_anchor<512, 4>), dim3(c.nanch, npairs), dim3(512), 0, s, c);
         return hipGetLastError();
